@@ -1,0 +1,240 @@
+"""Pins for the oracle (CPU only): every check compares it with something
+other than itself -- exact rational thresholds, an O(N^3) brute force, a
+closed-triangle enumeration, perfect-lattice vector counts, hand-derived
+worked cases, closed forms of the ideal-gas volume W, and g3 -> 1 on an
+ideal gas."""
+from __future__ import annotations
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import refs
+from paper_1708_08619_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- thresholds
+@pytest.mark.parametrize("rmax,nbins", [
+    (1000.0, 10), (10240.0, 50), (12288.0, 60), (0.6 * 65536, 60), (8192.0, 40),
+    (float.fromhex("0x1.3333333333333p+13"), 37), (123.456, 7), (46339.999, 255), (1.0, 1),
+])
+def test_thresholds_exact(oracle_mod, rmax, nbins):
+    thr = oracle_mod.thresholds(rmax, nbins)
+    R = Fraction(rmax)
+    for b in range(nbins + 1):
+        v = (b * R / nbins) ** 2
+        want = math.ceil(v)
+        assert int(thr[b]) == want, (b, int(thr[b]), want)
+
+
+def test_water_unit_thresholds(oracle_mod):
+    """0.6 nm at 2^-16 nm is not an integer; its binary64 value lies just
+    below 39321.6, which leaves the power-of-two thresholds unchanged."""
+    thr = oracle_mod.thresholds(0.6 * 65536, 60)
+    assert int(thr[25]) == 2 ** 28 and int(thr[50]) == 2 ** 30
+    assert Fraction(0.6 * 65536) < Fraction(393216, 10)
+
+
+def test_bin_lookup_matches_fraction(oracle_mod):
+    rng = np.random.default_rng(5)
+    for rmax, nbins in [(1000.0, 10), (0.6 * 65536, 60), (777.7, 13)]:
+        thr = oracle_mod.thresholds(rmax, nbins)
+        R2 = int(thr[-1])
+        pts = list(rng.integers(0, R2 + 50, size=300)) + [int(t) for t in thr] + \
+            [int(t) - 1 for t in thr[1:]]
+        for s in pts:
+            assert oracle_mod.bin_of(int(s), thr) == refs.frac_bin(int(s), rmax, nbins), s
+
+
+# ---------------------------------------------------------------- worked cases
+def _cases():
+    with open(os.path.join(GOLDEN, "worked_cases.json")) as f:
+        return json.load(f)["cases"]
+
+
+def _half_index(lo, hi, c, nbins):
+    rowoff = lo * nbins - lo * (lo - 1) // 2
+    return (rowoff + hi - lo) * nbins + c
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
+def test_worked_cases(oracle_mod, case):
+    pos = np.array(case["positions"], dtype=np.int64)          # [N, 3]
+    frames = pos.T[None].astype(np.int32)
+    nb = case["nbins"]
+    want = np.zeros(nb * (nb + 1) // 2 * nb, dtype=np.uint64)
+    for lo, hi, c, n in case["half"]:
+        want[_half_index(lo, hi, c, nb)] = n
+    got = oracle_mod.hist(frames, case["box"], case["rmax"], nb, layout=0)
+    assert np.array_equal(got, want), np.nonzero(got)
+    full = oracle_mod.hist(frames, case["box"], case["rmax"], nb, layout=1).reshape(nb, nb, nb)
+    for lo, hi, c, n in case["half"]:
+        if lo == hi:
+            assert full[lo, lo, c] == 2 * n
+        else:
+            assert full[lo, hi, c] == n and full[hi, lo, c] == n
+    assert int(full.sum()) == 2 * sum(n for *_, n in case["half"])
+
+
+# ---------------------------------------------------------------- brute force
+def _random_system(rng, N, box, F=2):
+    return np.stack([np.stack([rng.integers(0, L, size=N) for L in box]) for _ in range(F)]
+                    ).astype(np.int32)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_random(oracle_mod, seed):
+    rng = np.random.default_rng(100 + seed)
+    box = [int(x) for x in rng.integers(300, 700, size=3)]
+    # rmax between L/3 and L/2 of the smallest side in half the cases
+    lo = min(box) / (3.0 if seed % 2 else 5.0)
+    rmax = float(rng.uniform(lo, min(box) / 2 - 1))
+    nbins = int(rng.integers(3, 9))
+    N = int(rng.integers(6, 14))
+    fr = _random_system(rng, N, box)
+    want = refs.brute_full(fr, box, rmax, nbins)
+    got = oracle_mod.hist_full(fr, box, rmax, nbins, n_threads=2)
+    assert np.array_equal(got, want)
+
+
+def test_brute_force_clustered(oracle_mod):
+    """Dense cluster with coincident atoms (r = 0 counts in bin 0)."""
+    rng = np.random.default_rng(7)
+    box = [1000, 900, 800]
+    c = rng.integers(100, 700, size=3)
+    pos = c[:, None] + rng.integers(-40, 41, size=(3, 10))
+    pos[:, 3] = pos[:, 4]                       # two distinct atoms at one point
+    fr = np.mod(pos, np.array(box)[:, None])[None].astype(np.int32)
+    want = refs.brute_full(fr, box, 150.0, 6)
+    got = oracle_mod.hist_full(fr, box, 150.0, 6)
+    assert np.array_equal(got, want)
+    assert got[0].sum() > 0
+
+
+# ---------------------------------------------------------------- triangles
+@pytest.mark.parametrize("kind", ["gas", "fcc"])
+def test_closed_triangles_lj256(oracle_mod, kind):
+    """Full-size C1 geometry (rmax > L/3): the oracle equals the
+    closed-triangle enumeration, which also gives sum(H_half) = 3 T."""
+    w = synth.lj_small(kind, n_frames=1)
+    got = oracle_mod.hist_full(w.frames, w.box, w.rmax, w.nbins)
+    want = refs.triangles_full(w.frames, w.box, w.rmax, w.nbins)
+    assert np.array_equal(got, want)
+    half, bad = oracle_mod.fold_half(got)
+    assert bad == 0
+    assert int(half.sum()) * 2 == int(want.sum())          # 3T unordered = 6T ordered / 2
+
+
+# ---------------------------------------------------------------- invariants
+def test_invariants_lj256(oracle_mod):
+    w = synth.lj_small("fcc", n_frames=3)
+    H = oracle_mod.hist_full(w.frames, w.box, w.rmax, w.nbins).astype(np.int64)
+    for p, Hp in refs.permutations_of(H):
+        assert np.array_equal(Hp, H), p                    # all six permutations
+    d = np.einsum("aac->ac", H)
+    assert np.all(d % 2 == 0)                              # even diagonal
+    nb = w.nbins
+    a, b, c = np.meshgrid(np.arange(nb), np.arange(nb), np.arange(nb), indexing="ij")
+    outside = (c >= a + b + 2) | (a >= b + c + 2) | (b >= a + c + 2)
+    assert H[outside].sum() == 0                           # triangle inequality
+
+
+def test_compact_cluster_marginal(oracle_mod):
+    """All atoms inside a ball of diameter < rmax: every triple is counted,
+    sum H_full = N(N-1)(N-2), and the pair histogram comes back as a marginal:
+    sum_{b,c} H_full[a][b][c] = (N-2) H2[a]."""
+    rng = np.random.default_rng(11)
+    box = [200000, 200000, 200000]
+    N, rmax, nbins = 40, 4000.0, 16
+    ctr = np.array([100000, 100000, 100000])
+    pts = []
+    while len(pts) < N:
+        p = rng.integers(-1900, 1901, size=3)
+        if (p * p).sum() < 1900 ** 2:
+            pts.append(ctr + p)
+    fr = np.array(pts).T[None].astype(np.int32)
+    H = oracle_mod.hist_full(fr, box, rmax, nbins)
+    assert int(H.sum()) == N * (N - 1) * (N - 2)
+    H2 = oracle_mod.pair_hist(fr, box, rmax, nbins)
+    assert int(H2.sum()) == N * (N - 1)
+    assert np.array_equal(H.sum(axis=(1, 2)), H2 * np.uint64(N - 2))
+
+
+# ---------------------------------------------------------------- lattices
+def test_perfect_fcc_lj256(oracle_mod):
+    n = 4
+    L = synth.cubic_lattice_box(256, 0.8, synth.LJ_UNIT_PER_SIGMA, n, 2 * n)
+    a = L // n
+    sites = synth.fcc_sites(n, a)
+    fr = synth.lattice_frames(sites, len(sites), [L] * 3, 0.0, 1, 0)
+    rmax, nbins = 2.5 * 4096, 50
+    got = oracle_mod.hist_full(fr, [L] * 3, rmax, nbins)
+    want = refs.lattice_full(refs.fcc_vectors(a, rmax), len(sites), rmax, nbins)
+    assert np.array_equal(got, want)
+    assert got.sum() > 0
+
+
+def test_perfect_diamond_water(oracle_mod):
+    n = 8
+    L = synth.cubic_lattice_box(4096, 33.4, synth.WATER_UNIT_PER_NM, n, 4 * n)
+    a = L // n
+    sites = synth.diamond_sites(n, a)
+    fr = synth.lattice_frames(sites, len(sites), [L] * 3, 0.0, 1, 0)
+    rmax, nbins = 0.6 * 65536, 60
+    got = oracle_mod.hist_full(fr, [L] * 3, rmax, nbins)
+    want = refs.lattice_full(refs.diamond_vectors(a, rmax), len(sites), rmax, nbins)
+    assert np.array_equal(got, want)
+    assert got.sum() > 0
+
+
+# ---------------------------------------------------------------- W and g3 -> 1
+def test_W_closed_forms(oracle_mod):
+    nb, R = 12, 1.0
+    dr = R / nb
+    W = oracle_mod.W_table(nb, dr)
+    # total: (4 pi R^3 / 3)^2 * 15/32 (two uniform points in a ball closer than its radius)
+    assert math.isclose(W.sum(), (4 * math.pi / 3) ** 2 * 15 / 32, rel_tol=1e-12)
+    for a in range(nb):
+        for b in range(nb):
+            if a + b + 2 <= nb:          # every t up to r + s lies inside the cutoff
+                want = (4 * math.pi / 3) ** 2 * ((a + 1) ** 3 - a ** 3) * ((b + 1) ** 3 - b ** 3) \
+                    * dr ** 6
+                assert math.isclose(W[a, b].sum(), want, rel_tol=1e-12), (a, b)
+            for c in range(nb):
+                if c >= abs(a - b) + 1 and c + 1 <= a + b:   # box inside the triangle region
+                    want = math.pi ** 2 * dr ** 6 * ((a + 1) ** 2 - a ** 2) * \
+                        ((b + 1) ** 2 - b ** 2) * ((c + 1) ** 2 - c ** 2)
+                    assert math.isclose(W[a, b, c], want, rel_tol=1e-12), (a, b, c)
+    for p, Wp in refs.permutations_of(W):
+        assert np.allclose(Wp, W, rtol=1e-12, atol=1e-13 * W.max()), p
+
+
+def test_ideal_gas_g3_is_one(oracle_mod):
+    """Uniform positions: E[H_full] = F N(N-1)(N-2)/V^2 W exactly (for
+    rmax < L/2), so g3 -> 1.  Checked per bin against frame-to-frame
+    standard errors, and on the total."""
+    N, F, nbins = 128, 40, 4
+    L = 12000
+    rmax = 4000.0
+    w = synth.ideal_gas(N, [L, L, L], F, rmax, nbins, layout=1, seed=(synth.SEED_BASE, 7))
+    per = np.stack([oracle_mod.hist_full(w.frames[f:f + 1], w.box, rmax, nbins).astype(np.float64)
+                    for f in range(F)])
+    g = oracle_mod.normalize(per.sum(0).astype(np.uint64), 1, nbins, rmax, F, N, w.box)
+    Wt = oracle_mod.W_table(nbins, rmax / nbins)
+    E1 = N * (N - 1) * (N - 2) / float(L) ** 6 * Wt      # per frame
+    m = per.mean(0)
+    sem = per.std(0, ddof=1) / math.sqrt(F)
+    live = E1 > 50
+    z = (m[live] - E1[live]) / np.maximum(sem[live], 1e-9)
+    assert np.all(np.abs(z) < 5.0), z.max()
+    assert np.allclose(g.reshape(per.shape[1:])[live], m[live] / E1[live])
+    tot = per.sum(axis=(1, 2, 3))
+    zt = (tot.mean() - E1.sum()) / (tot.std(ddof=1) / math.sqrt(F))
+    assert abs(zt) < 5.0
+    assert abs(tot.mean() / E1.sum() - 1) < 0.02
