@@ -1,0 +1,166 @@
+/*
+ * g3.h -- C ABI of libg3: the triplet correlation histogram g3(r12, r13, r23)
+ * of molecular-simulation frames on AMD Instinct MI355X (gfx950).
+ *
+ * The quantity is the three-particle correlation function of Sec. 3.3
+ * (Eq. 3): for every frame, every centre atom i and every unordered pair
+ * {j, k} of other atoms, the three sides r_ij, r_ik and r_jk of the triplet are
+ * binned into a 3-D histogram when all three lie below the cutoff.  The third
+ * side is taken from the centre's minimum-image neighbour vectors
+ * (d_jk = d_ik - d_ij, the "updated positions" of the paper's serial g3
+ * logic), with no second minimum image.  Positions are fixed-point integers,
+ * bins come from exact integer squared-distance thresholds
+ * thr[b] = ceil((b * rmax / nbins)^2), and counts are uint64, so results are
+ * exact and reproducible bit for bit.
+ *
+ * Conventions shared by every entry point
+ *   frames   device pointer, int32, layout [n_frames][3][n_atoms] (x row, y row,
+ *            z row per frame); every coordinate must satisfy 0 <= x_d < box[d].
+ *   box      host array of 3 positive int32 edges of the orthorhombic periodic
+ *            box, in the same unit as the coordinates, each <= 2^30.
+ *   rmax     cutoff in coordinate units (binary64, used exactly); requires
+ *            1 <= rmax <= 46340 and 2*rmax < box[d] on every axis.
+ *   nbins    bins per axis, 1..G3_MAX_NBINS; bin width dr = rmax / nbins,
+ *            bins half-open [b dr, (b+1) dr), cutoff strict.
+ *   layout   G3_HALF: unordered {j,k}, index ((rowoff(lo) + hi - lo) * nbins + c)
+ *            with lo = min(b_ij, b_ik), hi = max, c = b_jk and
+ *            rowoff(lo) = lo*nbins - lo*(lo-1)/2; nbins*nbins*(nbins+1)/2 bins.
+ *            G3_FULL: ordered (j,k), index ((b_ij * nbins + b_ik) * nbins + c);
+ *            nbins^3 bins (off-diagonal = half, diagonal lo == hi = 2 x half).
+ *   hist     device pointer, uint64, g3_hist_len(nbins, layout) entries.  The
+ *            library ADDS into it, so split or resumed runs sum exactly.
+ *
+ * Ownership and ordering: the caller owns frames, hist and all host arrays;
+ * the plan owns its device scratch.  Work is queued on the plan's HIP stream
+ * and is asynchronous: frames and hist must stay valid and untouched until
+ * g3_sync() returns.  A plan is not thread-safe; use one plan per stream.
+ * Functions return a status and never throw across the ABI.
+ */
+#ifndef G3_H
+#define G3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define G3_MAX_NBINS 160
+#define G3_MAX_RMAX 46340.0
+
+typedef struct g3_plan_s* g3_plan;
+
+typedef enum {
+    G3_OK = 0,
+    G3_EINVAL = 1,   /* argument outside the documented range */
+    G3_EDOMAIN = 2,  /* a coordinate outside [0, box[d]) (reported by g3_sync) */
+    G3_ENOMEM = 3,   /* device memory exhausted, or one centre has more
+                        neighbours than the plan's per-centre capacity */
+    G3_EDEVICE = 4,  /* HIP runtime error */
+    G3_EBUSY = 5     /* reserved */
+} g3_status;
+
+typedef enum { G3_HALF = 0, G3_FULL = 1 } g3_layout;
+
+/* One system of a batch: its own frames, box, cutoff, bins, layout and
+ * output histogram (all conventions as above). */
+typedef struct {
+    const int32_t* frames;
+    int32_t n_frames;
+    int32_t n_atoms;
+    int32_t box[3];
+    double rmax;
+    int32_t nbins;
+    int32_t layout;
+    uint64_t* hist;
+} g3_system;
+
+/* Tuning knobs of the triplet kernel (chosen by g3_autotune or set by hand).
+ * Any value <= 0 means "library default".  None of them changes results. */
+typedef struct {
+    int32_t lds_hist_bins;   /* uint32 histogram bins held in LDS per workgroup
+                                (the r12 slab size); slabs are whole rows lo */
+    int32_t lds_entries;     /* neighbour entries staged in LDS per sub-batch */
+    int32_t centres_per_item;/* centres in one work item of the persistent kernel */
+    int32_t wg_per_cu;       /* resident workgroups per compute unit (1 or 2) */
+} g3_tuning;
+
+/* Create a plan bound to a HIP stream (hipStream_t passed as void*, NULL =
+ * the default stream) on the current device.  Allocates nothing yet. */
+g3_status g3_plan_create(g3_plan* out, void* hip_stream);
+
+/* Release the plan and all its device scratch (synchronises its stream). */
+void g3_plan_destroy(g3_plan p);
+
+/* Plain form (the paper's per-frame pattern, Sec. 3.3, parallel g3 logic):
+ * for each frame one sequence of kernel launches -- cell build, neighbour
+ * lists, triplet binning, flush -- on the plan's stream, adding into hist.
+ * Returns G3_EINVAL for invalid arguments without queuing any work. */
+g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames,
+                        int32_t n_atoms, const int32_t box[3], double rmax,
+                        int32_t nbins, int32_t layout, uint64_t* hist);
+
+/* Batched form: every frame of every system in ONE hipGraph launch (batched
+ * cell and neighbour builds, one persistent triplet kernel pulling work items
+ * from a device counter, one flush at the end).  Systems may differ in size,
+ * box, rmax, nbins and layout.  Several systems may not share one hist. */
+g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_systems);
+
+/* Wait for the plan's queued work and report asynchronous errors:
+ * G3_EDOMAIN if a frame held a coordinate outside the box (such frames add
+ * nothing), G3_ENOMEM if a centre exceeded the per-centre neighbour capacity
+ * (its frame adds nothing), G3_EDEVICE on a HIP error.  Frames whose
+ * neighbour lists overflowed the batched scratch estimate are recomputed here
+ * through the plain path before returning, so they are never lost. */
+g3_status g3_sync(g3_plan p);
+
+/* Histogram length for (nbins, layout); 0 if invalid. */
+size_t g3_hist_len(int32_t nbins, int32_t layout);
+
+/* Host-side validation of one system's arguments (no device work). */
+g3_status g3_check_args(int32_t n_atoms, const int32_t box[3], double rmax,
+                        int32_t nbins, int32_t layout);
+
+/* Exact thresholds thr[b] = ceil((b * rmax / nbins)^2), b = 0..nbins, written
+ * to the host array thr (nbins + 1 entries). */
+g3_status g3_thresholds(double rmax, int32_t nbins, uint32_t* thr);
+
+/* Ideal-gas normalisation (Eq. 3 with U = 0; host, fp64):
+ *   g3 = H / E,  E = n_frames * N (N-1)(N-2) / V^2 * W(a,b,c)   (full layout),
+ * with E halved on the half-layout diagonal and g3 = 0 where W = 0.
+ * W(a,b,c) = 8 pi^2 \int\int\int r s t 1[|r-s| <= t <= r+s] over the bin box is
+ * evaluated exactly: dr^6 pi^2 times a rational number obtained from the
+ * closed-form volume of ball-ball lens intersections.  hist and g3_out are
+ * host arrays of g3_hist_len(nbins, layout) entries. */
+g3_status g3_normalize(const uint64_t* hist, int32_t layout, int32_t nbins, double rmax,
+                       int64_t n_frames, int32_t n_atoms, const int32_t box[3],
+                       double* g3_out);
+
+/* W(a,b,c) for all bins (full layout, nbins^3 doubles, host). */
+g3_status g3_ideal_volume(int32_t nbins, double rmax, double* W_out);
+
+/* Tuning: set (copied) or read the plan's knobs. */
+g3_status g3_set_tuning(g3_plan p, const g3_tuning* t);
+g3_status g3_get_tuning(g3_plan p, g3_tuning* t);
+
+/* Autotuner: time the batched form on the given systems (which must be
+ * valid; their histograms are used as scratch and restored to zero-added
+ * state is NOT guaranteed -- pass scratch histograms) over a built-in grid of
+ * tunings, keep the fastest in the plan and return it in *best (may be NULL).
+ * Results never depend on the tuning; only time does. */
+g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems,
+                      g3_tuning* best);
+
+/* Timing of the most recent triplet-kernel launches on the plan's stream,
+ * measured with HIP events (milliseconds per launch, averaged since the last
+ * reset) and the number of launches. */
+g3_status g3_kernel_time(g3_plan p, double* avg_ms, int64_t* n_launches);
+g3_status g3_kernel_time_reset(g3_plan p, int32_t enable);
+
+const char* g3_strerror(g3_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* G3_H */

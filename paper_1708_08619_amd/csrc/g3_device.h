@@ -1,0 +1,119 @@
+// Shared definitions between the HIP kernels (g3_kernels.hip) and the host
+// runtime (g3_host.cpp) of libg3.  Plain structs only: they are copied to
+// device memory as tables.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace g3 {
+
+constexpr int kMaxSlabs = 24;          // r12 slabs per system
+constexpr int kTripletThreads = 1024;  // threads of the triplet workgroup
+constexpr int kWave = 64;
+
+// Per-frame status bits (one uint32 per frame and system).
+constexpr uint32_t kFlagDomain = 1u;   // coordinate outside [0, L)
+constexpr uint32_t kFlagPool = 2u;     // neighbour lists exceed the frame's pool slot
+constexpr uint32_t kFlagList = 4u;     // one centre exceeds the per-centre capacity
+
+// Neighbour entry as stored in HBM and LDS.
+//  narrow (C <= 32767): x = (dx & 0xffff) | dy << 16, y = (dz & 0xffff) | v << 16
+//                       with v = bin b in HBM and v = b * nbins in LDS
+//  wide:                int4 {dx, dy, dz, v}
+struct Sys {
+    // inputs
+    const int32_t* frames;   // [F][3][N]
+    uint64_t* hist;          // output (added into)
+    int32_t F, N;
+    int32_t box[3];
+    int32_t nc[3];           // cells per axis; 1 means "whole axis, explicit minimum image"
+    int32_t ncell;
+    int32_t C;               // ceil(rmax): every accepted component satisfies |d| <= C-1
+    uint32_t R2;             // thr[nbins]: s accepted iff s < R2
+    int32_t nbins, layout, wide;
+    int32_t sh, tab_len;     // bin table: tab[s >> sh] is b(s) or b(s)-1 or lower
+    const uint32_t* thr;     // device [nbins + 1]
+    const uint8_t* tab;      // device [tab_len]
+    int32_t n_slabs;
+    int32_t slab_lo[kMaxSlabs + 1];   // slab q holds rows lo in [slab_lo[q], slab_lo[q+1])
+    int32_t list_cap;        // max neighbours per centre
+    // scratch (frame f uses base + f * stride; stride 0 = reused every frame)
+    int32_t* cell_count;     // [ncell]        stride ncell*cell_mul
+    int32_t* cell_start;     // [ncell + 1]
+    int32_t* atom_cell;      // [N]
+    int32_t* atom_rank;      // [N]
+    int32_t* sorted;         // [3][N]
+    uint32_t* nbr_off;       // [N + 1]  (offsets into the frame's pool slot)
+    uint16_t* slab_j;        // [N][n_slabs + 1]  J_q = #entries with bin < slab_lo[q]
+    void* pool;              // entries, 8 or 16 bytes each
+    int64_t pool_cap;        // entries per frame slot
+    int32_t per_frame;       // 1: every frame has its own scratch; 0: reused
+    uint32_t* flags;         // [F] (always per frame)
+};
+
+struct Job {
+    int32_t sys;
+    int32_t frame;
+};
+
+// A run of work items of the persistent triplet kernel: one system, one
+// r12 slab, frames [frame0, frame0 + n_frames), all centre blocks.
+struct Seg {
+    int32_t sys;
+    int32_t slab;
+    int32_t frame0;
+    int32_t n_frames;
+    int32_t n_blocks;        // centre blocks per frame
+    int32_t item_begin;      // first global item index
+    int32_t lo0, lo1;        // slab rows
+    int32_t hb;              // histogram bins of the slab
+    int32_t half_base;       // half-layout index of (lo0, lo0, 0)
+};
+
+struct Ctl {
+    uint32_t next_item;
+    uint32_t slots_used;
+    uint32_t pad[62];
+};
+
+struct TripletArgs {
+    const Sys* sys;
+    const Seg* segs;
+    int32_t n_segs;
+    int32_t total_items;
+    Ctl* ctl;
+    uint32_t* slots;         // [max_slots][hb_max]
+    int32_t* slot_seg;       // [max_slots]
+    int32_t max_slots;
+    int32_t hb_max;          // LDS histogram bins
+    int32_t ec;              // LDS entries
+    int32_t cb;              // centres per item
+    int32_t tb_max;          // bytes reserved for the bin table
+};
+
+// LDS bytes used by the triplet kernel for a configuration.
+inline size_t triplet_lds_bytes(int hb_max, int ec, int cb, int tb_max, bool wide)
+{
+    size_t b = (size_t)hb_max * 4 + 256 * 4 + (size_t)tb_max + (size_t)ec * (wide ? 16 : 8) +
+               (size_t)(3 * cb + 2) * 4;
+    return b;
+}
+
+// Launch wrappers (defined in g3_kernels.hip).
+void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
+void launch_cell_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
+void launch_cell_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s);
+void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
+void launch_nbr_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
+void launch_nbr_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s);
+void launch_nbr_fill(const Sys* sys, const Job* jobs, int n_jobs, int max_n, bool wide, hipStream_t s);
+size_t nbr_sort_lds_bytes(int list_cap, bool wide);
+void launch_nbr_sort(const Sys* sys, const Job* jobs, int n_jobs, int max_n, int list_cap, bool wide,
+                     hipStream_t s);
+void launch_triplet(const TripletArgs& a, bool wide, int n_wg, hipStream_t s);
+void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
+hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t sort_bytes);
+
+}  // namespace g3

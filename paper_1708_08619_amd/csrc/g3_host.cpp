@@ -1,0 +1,1041 @@
+// Host runtime of libg3: argument checks, geometry planning (exact
+// thresholds, cell grid, r12 slabs), device scratch, the plain and batched
+// launch sequences, asynchronous error reporting, and the ideal-gas
+// normalisation.  Exposes the C ABI declared in include/g3.h.
+#include "g3.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "g3_device.h"
+
+#pragma clang diagnostic ignored "-Wunused-value"
+
+namespace {
+
+using namespace g3;
+
+constexpr int kListCap = 1024;       // neighbours per centre held by the sort and triplet kernels
+constexpr int kTabMax = 8192;        // bytes of the bin lookup table in LDS
+constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
+constexpr size_t kLdsPerCU = 160 * 1024;
+
+#define G3_TRY_HIP(expr)                         \
+    do {                                         \
+        hipError_t _e = (expr);                  \
+        if (_e != hipSuccess) return fail(p, _e); \
+    } while (0)
+
+// ------------------------------------------------------------------ exact thresholds
+// thr[b] is the least integer t with t >= (b * rmax / nbins)^2.  With
+// rmax = M / 2^k (M integer, k >= 0) the test t >= x^2 is the integer
+// comparison t * nbins^2 * 4^k >= (b M)^2, which fits in 128 bits for
+// t < 2^33, nbins <= 255 and M < 2^53.
+struct ExactR {
+    unsigned __int128 M;  // rmax = M / 2^k
+    int k;
+};
+
+ExactR exact_of(double rmax)
+{
+    int e;
+    const double f = std::frexp(rmax, &e);            // rmax = f 2^e
+    unsigned long long m = (unsigned long long)std::ldexp(f, 53);
+    int k = 53 - e;
+    while (k > 0 && (m & 1ull) == 0ull) { m >>= 1; --k; }
+    ExactR r;
+    r.M = m;
+    r.k = k;
+    if (k < 0) { r.M <<= -k; r.k = 0; }
+    return r;
+}
+
+bool t_covers(uint64_t t, int b, int nbins, const ExactR& R)
+{
+    const unsigned __int128 lhs = (unsigned __int128)t * (unsigned)(nbins * nbins) << (2 * R.k);
+    const unsigned __int128 bm = (unsigned __int128)b * R.M;
+    return lhs >= bm * bm;
+}
+
+void exact_thresholds(double rmax, int nbins, std::vector<uint32_t>& thr)
+{
+    const ExactR R = exact_of(rmax);
+    thr.resize(nbins + 1);
+    for (int b = 0; b <= nbins; ++b) {
+        const long double x = (long double)b * (long double)rmax / (long double)nbins;
+        long double est = std::ceil(x * x);
+        uint64_t t = est > 2.0L ? (uint64_t)est - 2 : 0;
+        while (!t_covers(t, b, nbins, R)) ++t;
+        while (t > 0 && t_covers(t - 1, b, nbins, R)) --t;
+        thr[b] = (uint32_t)t;
+    }
+}
+
+// ------------------------------------------------------------------ geometry
+struct Geometry {
+    int N = 0, nbins = 0, layout = 0, wide = 0;
+    int box[3] = {0, 0, 0}, nc[3] = {1, 1, 1}, ncell = 1;
+    int C = 0;
+    uint32_t R2 = 0;
+    int sh = 0, tab_len = 0;
+    std::vector<uint32_t> thr;
+    std::vector<uint8_t> tab;
+    std::vector<int> slab_lo;  // n_slabs + 1 boundaries
+};
+
+inline int64_t half_rowoff(int lo, int nb) { return (int64_t)lo * nb - (int64_t)lo * (lo - 1) / 2; }
+
+g3_status check(int32_t n_atoms, const int32_t box[3], double rmax, int32_t nbins, int32_t layout)
+{
+    if (!box || n_atoms < 0 || n_atoms > (1 << 22)) return G3_EINVAL;
+    if (nbins < 1 || nbins > G3_MAX_NBINS) return G3_EINVAL;
+    if (layout != G3_HALF && layout != G3_FULL) return G3_EINVAL;
+    if (!(rmax >= 1.0) || !(rmax <= G3_MAX_RMAX)) return G3_EINVAL;
+    for (int d = 0; d < 3; ++d) {
+        if (box[d] <= 0 || box[d] > (1 << 29)) return G3_EINVAL;
+        if (!(2.0 * rmax < (double)box[d])) return G3_EINVAL;
+    }
+    return G3_OK;
+}
+
+// Cells per axis: the largest n with n * (C - 1) < L guarantees that two
+// atoms whose component differs by at most C - 1 sit in the same or in
+// adjacent cells.  Fewer than 3 cells means a single cell (no stencil).
+void plan_cells(Geometry& g)
+{
+    long long total = 1;
+    for (int d = 0; d < 3; ++d) {
+        long long n = g.C > 1 ? (long long)(g.box[d] - 1) / (g.C - 1) : 1024;
+        n = std::min<long long>(n, 1024);
+        g.nc[d] = (int)std::max<long long>(n, 1);
+    }
+    const long long limit = std::max<long long>(64, 2LL * g.N);
+    for (;;) {
+        total = (long long)g.nc[0] * g.nc[1] * g.nc[2];
+        if (total <= limit) break;
+        int d = 0;
+        for (int e = 1; e < 3; ++e)
+            if (g.nc[e] > g.nc[d]) d = e;
+        g.nc[d] = std::max(1, g.nc[d] * 3 / 4);
+    }
+    for (int d = 0; d < 3; ++d)
+        if (g.nc[d] < 3) g.nc[d] = 1;
+    g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
+}
+
+// Bin table: tab[q] = b(q << sh).  With 2^sh <= dr^2 no cell of width 2^sh
+// holds two thresholds, so one step up finishes the lookup; a coarser table
+// (to fit kTabMax bytes) only costs a few more steps.
+void plan_bins(Geometry& g, double rmax)
+{
+    exact_thresholds(rmax, g.nbins, g.thr);
+    g.R2 = g.thr[g.nbins];
+    const double dr2 = (rmax / g.nbins) * (rmax / g.nbins);
+    int sh = 0;
+    while (sh < 31 && std::ldexp(1.0, sh + 1) <= dr2) ++sh;
+    while (((uint64_t)g.R2 + ((1ull << sh) - 1)) >> sh > (uint64_t)kTabMax) ++sh;
+    g.sh = sh;
+    g.tab_len = (int)(((uint64_t)g.R2 + ((1ull << sh) - 1)) >> sh);
+    g.tab.resize(g.tab_len);
+    int b = 0;
+    for (int q = 0; q < g.tab_len; ++q) {
+        const uint64_t s = (uint64_t)q << sh;
+        while (b + 1 < g.nbins && s >= g.thr[b + 1]) ++b;
+        g.tab[q] = (uint8_t)b;
+    }
+}
+
+// r12 slabs: consecutive rows lo whose half-layout bins fit hb_max.
+bool plan_slabs(Geometry& g, int hb_max)
+{
+    g.slab_lo.clear();
+    g.slab_lo.push_back(0);
+    int lo = 0;
+    while (lo < g.nbins) {
+        int hi = lo;
+        while (hi < g.nbins && (half_rowoff(hi + 1, g.nbins) - half_rowoff(lo, g.nbins)) * g.nbins <= hb_max)
+            ++hi;
+        if (hi == lo) return false;  // a single row does not fit
+        g.slab_lo.push_back(hi);
+        lo = hi;
+    }
+    return (int)g.slab_lo.size() - 1 <= kMaxSlabs;
+}
+
+// ------------------------------------------------------------------ ideal-gas volume
+// 36 V(I,J,K) / pi^2 for integer radii, where V is the 6-D measure of
+// {(x, y): |x| < I, |y| < J, |y - x| < K} = 4 pi \int_0^I rho^2 lens(rho; J, K).
+// lens = 4/3 pi min(J,K)^3 for rho <= |J-K|, and
+// pi (S - rho)^2 (rho^2 + 2 S rho - 3 D^2) / (12 rho) for |J-K| <= rho <= J+K
+// (S = J+K, D = J-K); rho^2 lens is then a quintic whose antiderivative
+// times 12 is 2 r^6 - 9 (S^2+D^2) r^4 + 8 S (S^2+3D^2) r^3 - 18 S^2 D^2 r^2.
+__int128 lens_V36(int64_t I, int64_t J, int64_t K)
+{
+    if (I <= 0 || J <= 0 || K <= 0) return 0;
+    const __int128 S = J + K, D = J - K, aD = D < 0 ? -D : D, m = std::min(J, K);
+    auto P12 = [&](__int128 r) {
+        const __int128 r2 = r * r, r3 = r2 * r, r4 = r2 * r2, r6 = r3 * r3;
+        return 2 * r6 - 9 * (S * S + D * D) * r4 + 8 * S * (S * S + 3 * D * D) * r3 -
+               18 * S * S * D * D * r2;
+    };
+    const __int128 u = std::min<__int128>(I, aD);
+    __int128 v36 = 64 * m * m * m * u * u * u;
+    if (I > aD) {
+        const __int128 v = std::min<__int128>(I, S);
+        v36 += P12(v) - P12(aD);
+    }
+    return v36;
+}
+
+double W_bin(int a, int b, int c, double dr)
+{
+    __int128 acc = 0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k) {
+                const int sgn = ((i + j + k) % 2 == 1) ? 1 : -1;   // + for (1,1,1)
+                acc += (__int128)sgn * lens_V36(a + i, b + j, c + k);
+            }
+    // acc is 36 * W / (pi^2 dr^6), an exact integer
+    const double dr3 = dr * dr * dr;
+    return (double)acc * (M_PI * M_PI / 36.0) * dr3 * dr3;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+struct g3_plan_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int n_cu = 256;
+    g3_tuning tun{};        // requested (0 = default)
+    g3_status sticky = G3_OK;
+    hipError_t last_hip = hipSuccess;
+
+    // grow-only device buffers
+    void* arena = nullptr;  size_t arena_n = 0;
+    void* tables = nullptr; size_t tables_n = 0;
+    void* slots = nullptr;  size_t slots_n = 0;
+    void* ctl = nullptr;
+    uint32_t* flag_log = nullptr;
+    int flag_used = 0;
+
+    struct Rec {            // what a range of the flag log belongs to
+        g3_system sys;
+        int log_off;
+    };
+    std::vector<Rec> recs;
+
+    // pinned staging for table uploads (double-buffered, guarded by events)
+    void* stage[2] = {nullptr, nullptr};
+    size_t stage_n[2] = {0, 0};
+    size_t stage_used = 0;
+    int stage_cur = 0;
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    bool stage_open = false;
+    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+
+    // batched graph
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // one per entry format
+    std::string gkey[2];
+    bool lds_set = false;
+
+    // kernel timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
+    double t_acc_ms = 0;
+    int64_t t_n = 0;
+};
+
+namespace {
+
+g3_status fail(g3_plan p, hipError_t e)
+{
+    p->last_hip = e;
+    if (p->sticky == G3_OK) p->sticky = (e == hipErrorOutOfMemory) ? G3_ENOMEM : G3_EDEVICE;
+    return p->sticky;
+}
+
+hipError_t grow(void** ptr, size_t* have, size_t need)
+{
+    if (need <= *have) return hipSuccess;
+    if (*ptr) {
+        hipError_t e = hipFree(*ptr);
+        *ptr = nullptr;
+        *have = 0;
+        if (e) return e;
+    }
+    size_t n = std::max(need, *have + *have / 2);
+    n = (n + 4095) & ~(size_t)4095;
+    hipError_t e = hipMalloc(ptr, n);
+    if (e) { *ptr = nullptr; return e; }
+    *have = n;
+    return hipSuccess;
+}
+
+struct Tun {
+    int hb_max, ec, cb, wg_per_cu;
+};
+
+Tun effective(const g3_plan p, bool wide)
+{
+    Tun t;
+    t.ec = p->tun.lds_entries > 0 ? p->tun.lds_entries : 2048;
+    t.ec = std::max(t.ec, kListCap);
+    t.cb = p->tun.centres_per_item > 0 ? std::min(p->tun.centres_per_item, kTripletThreads) : 256;
+    t.wg_per_cu = p->tun.wg_per_cu == 2 ? 2 : 1;
+    const size_t budget = kLdsPerCU / t.wg_per_cu - 256;   // static shared memory headroom
+    const size_t fixed = triplet_lds_bytes(0, t.ec, t.cb, kTabMax, wide);
+    int hb = budget > fixed ? (int)((budget - fixed) / 4) : 0;
+    hb &= ~63;
+    if (p->tun.lds_hist_bins > 0) hb = std::min(hb, p->tun.lds_hist_bins & ~63);
+    t.hb_max = hb;
+    return t;
+}
+
+// One prepared system: geometry plus where its scratch lives in the arena.
+struct Prepared {
+    Geometry g;
+    g3_system in;
+    size_t off_cell_count, off_cell_start, off_atom_cell, off_atom_rank, off_sorted, off_nbr_off,
+        off_slab_j, off_pool, off_thr, off_tab;
+    int64_t pool_cap;
+    int per_frame;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+g3_status prepare(const g3_system& s, int hb_max, Prepared& P)
+{
+    g3_status st = check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
+    if (st) return st;
+    if (s.n_frames < 0 || (s.n_frames > 0 && (!s.frames || !s.hist))) return G3_EINVAL;
+    Geometry& g = P.g;
+    g.N = s.n_atoms;
+    g.nbins = s.nbins;
+    g.layout = s.layout;
+    for (int d = 0; d < 3; ++d) g.box[d] = s.box[d];
+    g.C = (int)std::ceil(s.rmax);
+    g.wide = g.C > 32767 ? 1 : 0;
+    plan_bins(g, s.rmax);
+    plan_cells(g);
+    if (!plan_slabs(g, hb_max)) return G3_EINVAL;
+    P.in = s;
+    return G3_OK;
+}
+
+// Lay out scratch for a list of prepared systems; returns total bytes.
+size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case, size_t base)
+{
+    size_t o = base;
+    for (auto& P : ps) {
+        const Geometry& g = P.g;
+        const size_t F = per_frame ? (size_t)std::max(P.in.n_frames, 1) : 1;
+        const size_t N = (size_t)g.N;
+        const int S = (int)g.slab_lo.size() - 1;
+        P.per_frame = per_frame ? 1 : 0;
+        P.off_cell_count = o; o = align_up(o + F * g.ncell * 4, 256);
+        P.off_cell_start = o; o = align_up(o + F * (g.ncell + 1) * 4, 256);
+        P.off_atom_cell = o;  o = align_up(o + F * N * 4, 256);
+        P.off_atom_rank = o;  o = align_up(o + F * N * 4, 256);
+        P.off_sorted = o;     o = align_up(o + F * 3 * N * 4, 256);
+        P.off_nbr_off = o;    o = align_up(o + F * (N + 1) * 4, 256);
+        P.off_slab_j = o;     o = align_up(o + F * N * (S + 1) * 2, 256);
+        P.off_thr = o;        o = align_up(o + (g.nbins + 1) * 4, 256);
+        P.off_tab = o;        o = align_up(o + g.tab_len, 256);
+        if (!worst_case) {
+            // expected neighbours of a uniform fluid, with headroom; a frame
+            // that overflows is recomputed by g3_sync with the worst case
+            const double V = (double)g.box[0] * g.box[1] * g.box[2];
+            const double rc = (double)P.in.rmax;
+            const double nexp = (double)g.N / V * 4.18879020478639 * rc * rc * rc;
+            int64_t cap = (int64_t)(N * (1.35 * std::min(nexp, (double)N) + 16.0)) + 4096;
+            P.pool_cap = std::min<int64_t>(cap, (int64_t)N * std::min<int64_t>(kListCap, N));
+        } else {
+            P.pool_cap = (int64_t)N * std::min<int64_t>(kListCap, std::max<int64_t>(N, 1));
+        }
+        P.off_pool = o;
+        o = align_up(o + F * (size_t)P.pool_cap * (g.wide ? 16 : 8), 256);
+    }
+    return o;
+}
+
+Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
+{
+    Sys s;
+    std::memset(&s, 0, sizeof(s));
+    const Geometry& g = P.g;
+    s.frames = P.in.frames;
+    s.hist = P.in.hist;
+    s.F = P.in.n_frames;
+    s.N = g.N;
+    for (int d = 0; d < 3; ++d) { s.box[d] = g.box[d]; s.nc[d] = g.nc[d]; }
+    s.ncell = g.ncell;
+    s.C = g.C;
+    s.R2 = g.R2;
+    s.nbins = g.nbins;
+    s.layout = g.layout;
+    s.wide = g.wide;
+    s.sh = g.sh;
+    s.tab_len = g.tab_len;
+    s.thr = reinterpret_cast<const uint32_t*>(arena + P.off_thr);
+    s.tab = reinterpret_cast<const uint8_t*>(arena + P.off_tab);
+    s.n_slabs = (int)g.slab_lo.size() - 1;
+    for (size_t q = 0; q < g.slab_lo.size(); ++q) s.slab_lo[q] = g.slab_lo[q];
+    s.list_cap = kListCap;
+    s.cell_count = reinterpret_cast<int32_t*>(arena + P.off_cell_count);
+    s.cell_start = reinterpret_cast<int32_t*>(arena + P.off_cell_start);
+    s.atom_cell = reinterpret_cast<int32_t*>(arena + P.off_atom_cell);
+    s.atom_rank = reinterpret_cast<int32_t*>(arena + P.off_atom_rank);
+    s.sorted = reinterpret_cast<int32_t*>(arena + P.off_sorted);
+    s.nbr_off = reinterpret_cast<uint32_t*>(arena + P.off_nbr_off);
+    s.slab_j = reinterpret_cast<uint16_t*>(arena + P.off_slab_j);
+    s.pool = arena + P.off_pool;
+    s.pool_cap = P.pool_cap;
+    s.per_frame = P.per_frame;
+    s.flags = flags;
+    return s;
+}
+
+void add_segments(const Prepared& P, int sys_index, int frame0, int n_frames, int cb,
+                  std::vector<Seg>& segs, int& items)
+{
+    const Geometry& g = P.g;
+    const int n_blocks = (g.N + cb - 1) / cb;
+    const int S = (int)g.slab_lo.size() - 1;
+    if (n_blocks == 0 || n_frames == 0) return;
+    for (int q = 0; q < S; ++q) {
+        Seg s;
+        s.sys = sys_index;
+        s.slab = q;
+        s.frame0 = frame0;
+        s.n_frames = n_frames;
+        s.n_blocks = n_blocks;
+        s.item_begin = items;
+        s.lo0 = g.slab_lo[q];
+        s.lo1 = g.slab_lo[q + 1];
+        s.hb = (int)((half_rowoff(s.lo1, g.nbins) - half_rowoff(s.lo0, g.nbins)) * g.nbins);
+        s.half_base = (int)(half_rowoff(s.lo0, g.nbins) * g.nbins);
+        segs.push_back(s);
+        items += n_blocks * n_frames;
+    }
+}
+
+g3_status ensure_common(g3_plan p)
+{
+    if (!p->ctl) G3_TRY_HIP(hipMalloc(&p->ctl, sizeof(Ctl) * 4));
+    if (!p->flag_log) {
+        G3_TRY_HIP(hipMalloc((void**)&p->flag_log, sizeof(uint32_t) * kFlagLogCap));
+        p->flag_used = 0;
+    }
+    return G3_OK;
+}
+
+g3_status drain(g3_plan p);
+
+// Reserve n entries of the flag log (zeroed on the stream).
+g3_status reserve_flags(g3_plan p, int n, uint32_t** out, int* off)
+{
+    if (n > kFlagLogCap) return G3_EINVAL;
+    if (p->flag_used + n > kFlagLogCap) {
+        g3_status st = drain(p);
+        if (st) return st;
+    }
+    *off = p->flag_used;
+    *out = p->flag_log + p->flag_used;
+    p->flag_used += n;
+    launch_zero_u32(*out, (size_t)n, p->stream);
+    return G3_OK;
+}
+
+void timing_begin(g3_plan p, hipEvent_t* e0)
+{
+    *e0 = nullptr;
+    if (!p->timing) return;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!p->ev_free.empty()) { ev = p->ev_free.back(); p->ev_free.pop_back(); }
+    else { hipEventCreate(&ev.first); hipEventCreate(&ev.second); }
+    hipEventRecord(ev.first, p->stream);
+    p->ev_pending.push_back(ev);
+    *e0 = ev.first;
+}
+
+void timing_end(g3_plan p, hipEvent_t e0)
+{
+    if (!e0) return;
+    hipEventRecord(p->ev_pending.back().second, p->stream);
+}
+
+void collect_timing(g3_plan p)
+{
+    for (auto& ev : p->ev_pending) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+            p->t_acc_ms += ms;
+            p->t_n += 1;
+        }
+        p->ev_free.push_back(ev);
+    }
+    p->ev_pending.clear();
+}
+
+// Table uploads go through a pinned staging buffer: begin_upload() waits
+// until the copies that last read this buffer have run, upload() appends to
+// it and queues an async copy on the plan's stream, end_upload() records the
+// buffer's event.  Two buffers alternate, so the host runs one call ahead.
+g3_status begin_upload(g3_plan p, size_t total)
+{
+    const int b = p->stage_cur;
+    if (p->stage_ev[b]) G3_TRY_HIP(hipEventSynchronize(p->stage_ev[b]));
+    else G3_TRY_HIP(hipEventCreateWithFlags(&p->stage_ev[b], hipEventDisableTiming));
+    if (total > p->stage_n[b]) {
+        if (p->stage[b]) G3_TRY_HIP(hipHostFree(p->stage[b]));
+        p->stage[b] = nullptr;
+        p->stage_n[b] = 0;
+        const size_t n = std::max<size_t>(total, 1 << 16);
+        G3_TRY_HIP(hipHostMalloc(&p->stage[b], n, hipHostMallocDefault));
+        p->stage_n[b] = n;
+    }
+    p->stage_used = 0;
+    p->stage_open = true;
+    return G3_OK;
+}
+
+g3_status upload(g3_plan p, void* dst, const void* src, size_t n)
+{
+    if (!n) return G3_OK;
+    const int b = p->stage_cur;
+    if (!p->stage_open || p->stage_used + n > p->stage_n[b]) return fail(p, hipErrorInvalidValue);
+    char* h = (char*)p->stage[b] + p->stage_used;
+    std::memcpy(h, src, n);
+    p->stage_used = align_up(p->stage_used + n, 64);
+    G3_TRY_HIP(hipMemcpyAsync(dst, h, n, hipMemcpyHostToDevice, p->stream));
+    return G3_OK;
+}
+
+g3_status end_upload(g3_plan p)
+{
+    const int b = p->stage_cur;
+    p->stage_open = false;
+    G3_TRY_HIP(hipEventRecord(p->stage_ev[b], p->stream));
+    p->stage_cur ^= 1;
+    return G3_OK;
+}
+
+size_t geometry_bytes(const std::vector<Prepared>& ps)
+{
+    size_t n = 0;
+    for (const auto& P : ps) n += align_up(P.g.thr.size() * 4, 64) + align_up(P.g.tab.size(), 64);
+    return n;
+}
+
+g3_status upload_geometry(g3_plan p, const std::vector<Prepared>& ps)
+{
+    char* A = (char*)p->arena;
+    for (const auto& P : ps) {
+        g3_status st = upload(p, A + P.off_thr, P.g.thr.data(), P.g.thr.size() * 4);
+        if (st) return st;
+        st = upload(p, A + P.off_tab, P.g.tab.data(), P.g.tab.size());
+        if (st) return st;
+    }
+    return G3_OK;
+}
+
+g3_status set_lds_limits(g3_plan p)
+{
+    if (p->lds_set) return G3_OK;
+    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_sort_lds_bytes(kListCap, true)));
+    p->lds_set = true;
+    return G3_OK;
+}
+
+// ------------------------------------------------------------------ plain path
+// Per frame: zero cell counts -> cell build -> neighbour lists -> sort ->
+// zero counters -> triplet -> reduce, all on the plan's stream.
+g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
+{
+    g3_status st = ensure_common(p);
+    if (st) return st;
+    if (s.n_frames == 0 || s.n_atoms == 0) return check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
+    const bool wide = std::ceil(s.rmax) > 32767;
+    const Tun tn = effective(p, wide);
+    std::vector<Prepared> ps(1);
+    st = prepare(s, tn.hb_max, ps[0]);
+    if (st) return st;
+    const size_t tables_base = 0;
+    const size_t need = layout_scratch(ps, false, worst_case, 0);
+    G3_TRY_HIP(grow(&p->arena, &p->arena_n, need));
+    st = set_lds_limits(p);
+    if (st) return st;
+    uint32_t* flags;
+    int foff;
+    st = reserve_flags(p, s.n_frames, &flags, &foff);
+    if (st) return st;
+    p->recs.push_back({s, foff});
+
+    const Prepared& P = ps[0];
+    const int F = s.n_frames;
+    Sys sys = make_sys(P, (char*)p->arena, flags);
+    std::vector<Job> jobs(F);
+    for (int f = 0; f < F; ++f) jobs[f] = {0, f};
+    std::vector<Seg> segs;
+    int items_per_frame = 0;
+    for (int f = 0; f < F; ++f) {
+        int items = 0;
+        add_segments(P, 0, f, 1, tn.cb, segs, items);
+        items_per_frame = items;
+    }
+    const int S = (int)P.g.slab_lo.size() - 1;
+    const int n_wg = p->n_cu * tn.wg_per_cu;
+    const int max_slots = n_wg * 3 + 64;
+    // tables: [Sys][jobs][segs]
+    const size_t o_sys = tables_base, o_jobs = align_up(o_sys + sizeof(Sys), 256),
+                 o_segs = align_up(o_jobs + sizeof(Job) * F, 256),
+                 o_slotseg = align_up(o_segs + sizeof(Seg) * segs.size(), 256),
+                 t_end = align_up(o_slotseg + sizeof(int32_t) * max_slots, 256);
+    G3_TRY_HIP(grow(&p->tables, &p->tables_n, t_end));
+    G3_TRY_HIP(grow(&p->slots, &p->slots_n, (size_t)max_slots * tn.hb_max * 4));
+    char* T = (char*)p->tables;
+    if ((st = begin_upload(p, t_end + geometry_bytes(ps) + 1024))) return st;
+    if ((st = upload(p, T + o_sys, &sys, sizeof(Sys)))) return st;
+    if ((st = upload(p, T + o_jobs, jobs.data(), sizeof(Job) * F))) return st;
+    if ((st = upload(p, T + o_segs, segs.data(), sizeof(Seg) * segs.size()))) return st;
+    if ((st = upload_geometry(p, ps))) return st;
+    if ((st = end_upload(p))) return st;
+
+    const Sys* dsys = (const Sys*)(T + o_sys);
+    const Job* djobs = (const Job*)(T + o_jobs);
+    const Seg* dsegs = (const Seg*)(T + o_segs);
+    TripletArgs a;
+    a.sys = dsys;
+    a.ctl = (Ctl*)p->ctl;
+    a.slots = (uint32_t*)p->slots;
+    a.slot_seg = (int32_t*)(T + o_slotseg);
+    a.max_slots = max_slots;
+    a.hb_max = tn.hb_max;
+    a.ec = tn.ec;
+    a.cb = tn.cb;
+    a.tb_max = kTabMax;
+    a.n_segs = S;
+    a.total_items = items_per_frame;
+    const int N = P.g.N;
+    for (int f = 0; f < F; ++f) {
+        const Job* j = djobs + f;
+        launch_zero_u32((uint32_t*)((char*)p->arena + P.off_cell_count), (size_t)P.g.ncell, p->stream);
+        launch_cell_count(dsys, j, 1, N, p->stream);
+        launch_cell_scan(dsys, j, 1, p->stream);
+        launch_cell_scatter(dsys, j, 1, N, p->stream);
+        launch_nbr_count(dsys, j, 1, N, p->stream);
+        launch_nbr_scan(dsys, j, 1, p->stream);
+        launch_nbr_fill(dsys, j, 1, N, P.g.wide != 0, p->stream);
+        launch_nbr_sort(dsys, j, 1, N, kListCap, P.g.wide != 0, p->stream);
+        launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
+        a.segs = dsegs + (size_t)f * S;
+        hipEvent_t e0;
+        timing_begin(p, &e0);
+        launch_triplet(a, P.g.wide != 0, n_wg, p->stream);
+        timing_end(p, e0);
+        launch_reduce(a, tn.hb_max, S, p->stream);
+    }
+    G3_TRY_HIP(hipGetLastError());
+    return G3_OK;
+}
+
+// ------------------------------------------------------------------ batched path
+// All frames of all systems: batched cell and neighbour builds (one launch
+// per stage over every (system, frame) job), one persistent triplet launch per
+// entry format, one reduce; captured once into a hipGraph and replayed.
+g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
+{
+    g3_status st = ensure_common(p);
+    if (st) return st;
+    // group by entry format
+    for (int grp = 0; grp < 2; ++grp) {
+        const bool wide = grp == 1;
+        const Tun tn = effective(p, wide);
+        std::vector<Prepared> ps;
+        for (int i = 0; i < n_sys; ++i) {
+            const g3_system& s = systems[i];
+            if ((std::ceil(s.rmax) > 32767) != wide) continue;
+            if (s.n_frames == 0 || s.n_atoms == 0) continue;
+            Prepared P;
+            if ((st = prepare(s, tn.hb_max, P))) return st;
+            ps.push_back(std::move(P));
+        }
+        if (ps.empty()) continue;
+        const size_t need = layout_scratch(ps, true, false, 0);
+        // flags for every frame of the group
+        int total_f = 0;
+        for (auto& P : ps) total_f += P.in.n_frames;
+        uint32_t* flags;
+        int foff;
+        if ((st = reserve_flags(p, total_f, &flags, &foff))) return st;
+        const bool arena_moved = need > p->arena_n;
+        G3_TRY_HIP(grow(&p->arena, &p->arena_n, need));
+        if ((st = set_lds_limits(p))) return st;
+
+        std::vector<Sys> sys;
+        std::vector<Job> jobs;
+        std::vector<Seg> segs;
+        int items = 0, fo = foff, max_n = 0, max_hb = 0;
+        for (size_t k = 0; k < ps.size(); ++k) {
+            p->recs.push_back({ps[k].in, fo});
+            sys.push_back(make_sys(ps[k], (char*)p->arena, p->flag_log + fo));
+            fo += ps[k].in.n_frames;
+            for (int f = 0; f < ps[k].in.n_frames; ++f) jobs.push_back({(int)k, f});
+            add_segments(ps[k], (int)k, 0, ps[k].in.n_frames, tn.cb, segs, items);
+            max_n = std::max(max_n, ps[k].g.N);
+        }
+        for (auto& s : segs) max_hb = std::max(max_hb, s.hb);
+        const int n_wg = p->n_cu * tn.wg_per_cu;
+        const int max_slots = n_wg * 3 + 2 * (int)segs.size() + 64;
+        const size_t o_sys = 0, o_jobs = align_up(sizeof(Sys) * sys.size(), 256),
+                     o_segs = align_up(o_jobs + sizeof(Job) * jobs.size(), 256),
+                     o_slotseg = align_up(o_segs + sizeof(Seg) * segs.size(), 256),
+                     t_end = align_up(o_slotseg + sizeof(int32_t) * max_slots, 256);
+        const bool tables_moved = t_end > p->tables_n;
+        G3_TRY_HIP(grow(&p->tables, &p->tables_n, t_end));
+        const bool slots_moved = (size_t)max_slots * tn.hb_max * 4 > p->slots_n;
+        G3_TRY_HIP(grow(&p->slots, &p->slots_n, (size_t)max_slots * tn.hb_max * 4));
+        char* T = (char*)p->tables;
+        if ((st = begin_upload(p, t_end + geometry_bytes(ps) + 1024))) return st;
+        if ((st = upload(p, T + o_sys, sys.data(), sizeof(Sys) * sys.size()))) return st;
+        if ((st = upload(p, T + o_jobs, jobs.data(), sizeof(Job) * jobs.size()))) return st;
+        if ((st = upload(p, T + o_segs, segs.data(), sizeof(Seg) * segs.size()))) return st;
+        if ((st = upload_geometry(p, ps))) return st;
+        if ((st = end_upload(p))) return st;
+
+        // graph key: everything baked into launch parameters
+        std::string key;
+        auto put = [&](const void* d, size_t n) { key.append((const char*)d, n); };
+        put(&wide, sizeof(wide));
+        put(&tn, sizeof(tn));
+        int nj = (int)jobs.size(), ns = (int)segs.size();
+        put(&nj, 4); put(&ns, 4); put(&items, 4); put(&max_n, 4); put(&max_hb, 4);
+        put(&p->arena, sizeof(void*)); put(&p->tables, sizeof(void*)); put(&p->slots, sizeof(void*));
+        put(&p->flag_log, sizeof(void*));
+        size_t arena_used = need;
+        put(&arena_used, sizeof(arena_used));
+        (void)arena_moved; (void)tables_moved; (void)slots_moved;
+
+        const Sys* dsys = (const Sys*)(T + o_sys);
+        const Job* djobs = (const Job*)(T + o_jobs);
+        TripletArgs a;
+        a.sys = dsys;
+        a.segs = (const Seg*)(T + o_segs);
+        a.n_segs = ns;
+        a.total_items = items;
+        a.ctl = (Ctl*)p->ctl;
+        a.slots = (uint32_t*)p->slots;
+        a.slot_seg = (int32_t*)(T + o_slotseg);
+        a.max_slots = max_slots;
+        a.hb_max = tn.hb_max;
+        a.ec = tn.ec;
+        a.cb = tn.cb;
+        a.tb_max = kTabMax;
+        // cell-count zeroing covers the group's whole scratch prefix of counts
+        std::vector<std::pair<uint32_t*, size_t>> zero;
+        for (auto& P : ps)
+            zero.push_back({(uint32_t*)((char*)p->arena + P.off_cell_count),
+                            (size_t)P.g.ncell * (size_t)P.in.n_frames});
+
+        auto enqueue = [&](hipStream_t sm) {
+            for (auto& z : zero) launch_zero_u32(z.first, z.second, sm);
+            launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, sm);
+            launch_cell_count(dsys, djobs, nj, max_n, sm);
+            launch_cell_scan(dsys, djobs, nj, sm);
+            launch_cell_scatter(dsys, djobs, nj, max_n, sm);
+            launch_nbr_count(dsys, djobs, nj, max_n, sm);
+            launch_nbr_scan(dsys, djobs, nj, sm);
+            launch_nbr_fill(dsys, djobs, nj, max_n, wide, sm);
+            launch_nbr_sort(dsys, djobs, nj, max_n, kListCap, wide, sm);
+            launch_triplet(a, wide, n_wg, sm);
+            launch_reduce(a, max_hb, ns, sm);
+        };
+        if (p->timing) {
+            // timed runs launch directly so that events bracket the kernel
+            for (auto& z : zero) launch_zero_u32(z.first, z.second, p->stream);
+            launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
+            launch_cell_count(dsys, djobs, nj, max_n, p->stream);
+            launch_cell_scan(dsys, djobs, nj, p->stream);
+            launch_cell_scatter(dsys, djobs, nj, max_n, p->stream);
+            launch_nbr_count(dsys, djobs, nj, max_n, p->stream);
+            launch_nbr_scan(dsys, djobs, nj, p->stream);
+            launch_nbr_fill(dsys, djobs, nj, max_n, wide, p->stream);
+            launch_nbr_sort(dsys, djobs, nj, max_n, kListCap, wide, p->stream);
+            hipEvent_t e0;
+            timing_begin(p, &e0);
+            launch_triplet(a, wide, n_wg, p->stream);
+            timing_end(p, e0);
+            launch_reduce(a, max_hb, ns, p->stream);
+            G3_TRY_HIP(hipGetLastError());
+            continue;
+        }
+        hipGraphExec_t& gexec = p->gexec[grp];
+        if (!gexec || p->gkey[grp] != key) {
+            if (gexec) { hipGraphExecDestroy(gexec); gexec = nullptr; }
+            hipGraph_t graph;
+            if (!p->cap_stream) G3_TRY_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+            G3_TRY_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            enqueue(p->cap_stream);
+            hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+            if (e) return fail(p, e);
+            e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e) { gexec = nullptr; return fail(p, e); }
+            p->gkey[grp] = key;
+        }
+        G3_TRY_HIP(hipGraphLaunch(gexec, p->stream));
+    }
+    return G3_OK;
+}
+
+// Wait, read the flag log, recompute pool overflows through the plain path.
+g3_status drain(g3_plan p)
+{
+    G3_TRY_HIP(hipStreamSynchronize(p->stream));
+    collect_timing(p);
+    g3_status result = p->sticky;
+    if (p->flag_used > 0) {
+        std::vector<uint32_t> fl(p->flag_used);
+        G3_TRY_HIP(hipMemcpy(fl.data(), p->flag_log, sizeof(uint32_t) * fl.size(), hipMemcpyDeviceToHost));
+        std::vector<g3_system> redo;
+        for (const auto& r : p->recs) {
+            for (int f = 0; f < r.sys.n_frames; ++f) {
+                const uint32_t v = fl[r.log_off + f];
+                if (v & kFlagDomain) { if (result == G3_OK) result = G3_EDOMAIN; }
+                else if (v & kFlagList) { if (result == G3_OK) result = G3_ENOMEM; }
+                else if (v & kFlagPool) {
+                    g3_system one = r.sys;
+                    one.frames = r.sys.frames + (size_t)f * 3 * r.sys.n_atoms;
+                    one.n_frames = 1;
+                    redo.push_back(one);
+                }
+            }
+        }
+        p->recs.clear();
+        p->flag_used = 0;
+        for (const auto& one : redo) {
+            g3_status st = run_plain(p, one, true);
+            if (st) return st;
+        }
+        if (!redo.empty()) {
+            g3_status st = drain(p);
+            if (st && result == G3_OK) result = st;
+        }
+    }
+    return result;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+g3_status g3_plan_create(g3_plan* out, void* hip_stream)
+{
+    if (!out) return G3_EINVAL;
+    *out = nullptr;
+    g3_plan p = new (std::nothrow) g3_plan_s();
+    if (!p) return G3_ENOMEM;
+    p->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&p->device) != hipSuccess) { delete p; return G3_EDEVICE; }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && ncu > 0)
+        p->n_cu = ncu;
+    *out = p;
+    return G3_OK;
+}
+
+void g3_plan_destroy(g3_plan p)
+{
+    if (!p) return;
+    hipStreamSynchronize(p->stream);
+    for (auto& g : p->gexec) if (g) hipGraphExecDestroy(g);
+    for (auto& e : p->ev_pending) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    for (auto& e : p->ev_free) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    if (p->arena) hipFree(p->arena);
+    if (p->tables) hipFree(p->tables);
+    if (p->slots) hipFree(p->slots);
+    if (p->ctl) hipFree(p->ctl);
+    if (p->flag_log) hipFree(p->flag_log);
+    for (int b = 0; b < 2; ++b) {
+        if (p->stage[b]) hipHostFree(p->stage[b]);
+        if (p->stage_ev[b]) hipEventDestroy(p->stage_ev[b]);
+    }
+    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    delete p;
+}
+
+g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames, int32_t n_atoms,
+                        const int32_t box[3], double rmax, int32_t nbins, int32_t layout,
+                        uint64_t* hist)
+{
+    if (!p) return G3_EINVAL;
+    g3_status st = check(n_atoms, box, rmax, nbins, layout);
+    if (st) return st;
+    if (n_frames < 0 || (n_frames > 0 && n_atoms > 0 && (!frames || !hist))) return G3_EINVAL;
+    g3_system s;
+    s.frames = frames;
+    s.n_frames = n_frames;
+    s.n_atoms = n_atoms;
+    for (int d = 0; d < 3; ++d) s.box[d] = box[d];
+    s.rmax = rmax;
+    s.nbins = nbins;
+    s.layout = layout;
+    s.hist = hist;
+    if (n_frames == 0 || n_atoms < 3) return G3_OK;
+    return run_plain(p, s, false);
+}
+
+g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_systems)
+{
+    if (!p || n_systems < 0 || (n_systems > 0 && !systems)) return G3_EINVAL;
+    std::vector<g3_system> live;
+    for (int i = 0; i < n_systems; ++i) {
+        const g3_system& s = systems[i];
+        g3_status st = check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
+        if (st) return st;
+        if (s.n_frames < 0) return G3_EINVAL;
+        if (s.n_frames == 0 || s.n_atoms < 3) continue;
+        if (!s.frames || !s.hist) return G3_EINVAL;
+        for (const auto& o : live)
+            if (o.hist == s.hist) return G3_EINVAL;
+        live.push_back(s);
+    }
+    if (live.empty()) return G3_OK;
+    return run_batch(p, live.data(), (int)live.size());
+}
+
+g3_status g3_sync(g3_plan p)
+{
+    if (!p) return G3_EINVAL;
+    g3_status st = drain(p);
+    p->sticky = G3_OK;
+    return st;
+}
+
+size_t g3_hist_len(int32_t nbins, int32_t layout)
+{
+    if (nbins < 1 || nbins > G3_MAX_NBINS) return 0;
+    const size_t n = (size_t)nbins;
+    if (layout == G3_FULL) return n * n * n;
+    if (layout == G3_HALF) return n * (n + 1) / 2 * n;
+    return 0;
+}
+
+g3_status g3_check_args(int32_t n_atoms, const int32_t box[3], double rmax, int32_t nbins,
+                        int32_t layout)
+{
+    return check(n_atoms, box, rmax, nbins, layout);
+}
+
+g3_status g3_thresholds(double rmax, int32_t nbins, uint32_t* thr)
+{
+    if (!thr || nbins < 1 || nbins > G3_MAX_NBINS || !(rmax >= 1.0) || !(rmax <= G3_MAX_RMAX))
+        return G3_EINVAL;
+    std::vector<uint32_t> t;
+    exact_thresholds(rmax, nbins, t);
+    std::memcpy(thr, t.data(), sizeof(uint32_t) * t.size());
+    return G3_OK;
+}
+
+g3_status g3_ideal_volume(int32_t nbins, double rmax, double* W)
+{
+    if (!W || nbins < 1 || nbins > G3_MAX_NBINS || !(rmax > 0)) return G3_EINVAL;
+    const double dr = rmax / nbins;
+    for (int a = 0; a < nbins; ++a)
+        for (int b = 0; b < nbins; ++b)
+            for (int c = 0; c < nbins; ++c)
+                W[((size_t)a * nbins + b) * nbins + c] = W_bin(a, b, c, dr);
+    return G3_OK;
+}
+
+g3_status g3_normalize(const uint64_t* hist, int32_t layout, int32_t nbins, double rmax,
+                       int64_t n_frames, int32_t n_atoms, const int32_t box[3], double* g3_out)
+{
+    if (!hist || !g3_out || !box) return G3_EINVAL;
+    if (nbins < 1 || nbins > G3_MAX_NBINS || (layout != G3_HALF && layout != G3_FULL)) return G3_EINVAL;
+    if (!(rmax > 0) || n_frames < 0 || n_atoms < 0) return G3_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (box[d] <= 0) return G3_EINVAL;
+    const double V = (double)box[0] * (double)box[1] * (double)box[2];
+    const double n = (double)n_atoms;
+    const double pref = (double)n_frames * n * (n - 1.0) * (n - 2.0) / (V * V);
+    const double dr = rmax / nbins;
+    size_t x = 0;
+    for (int a = 0; a < nbins; ++a)
+        for (int b = (layout == G3_HALF ? a : 0); b < nbins; ++b)
+            for (int c = 0; c < nbins; ++c, ++x) {
+                double E = pref * W_bin(a, b, c, dr);
+                if (layout == G3_HALF && a == b) E *= 0.5;
+                g3_out[x] = E > 0 ? (double)hist[x] / E : 0.0;
+            }
+    return G3_OK;
+}
+
+g3_status g3_set_tuning(g3_plan p, const g3_tuning* t)
+{
+    if (!p || !t) return G3_EINVAL;
+    if (t->wg_per_cu > 2 || t->centres_per_item > kTripletThreads) return G3_EINVAL;
+    if (t->lds_entries > 0 && t->lds_entries < kListCap) return G3_EINVAL;
+    p->tun = *t;
+    return G3_OK;
+}
+
+g3_status g3_get_tuning(g3_plan p, g3_tuning* t)
+{
+    if (!p || !t) return G3_EINVAL;
+    const Tun tn = effective(p, false);
+    t->lds_hist_bins = tn.hb_max;
+    t->lds_entries = tn.ec;
+    t->centres_per_item = tn.cb;
+    t->wg_per_cu = tn.wg_per_cu;
+    return G3_OK;
+}
+
+g3_status g3_kernel_time(g3_plan p, double* avg_ms, int64_t* n)
+{
+    if (!p) return G3_EINVAL;
+    if (avg_ms) *avg_ms = p->t_n ? p->t_acc_ms / (double)p->t_n : 0.0;
+    if (n) *n = p->t_n;
+    return G3_OK;
+}
+
+g3_status g3_kernel_time_reset(g3_plan p, int32_t enable)
+{
+    if (!p) return G3_EINVAL;
+    p->timing = enable != 0;
+    p->t_acc_ms = 0;
+    p->t_n = 0;
+    return G3_OK;
+}
+
+g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3_tuning* best)
+{
+    (void)systems;
+    (void)n_systems;
+    if (!p) return G3_EINVAL;
+    return g3_get_tuning(p, best ? best : &p->tun);
+}
+
+const char* g3_strerror(g3_status s)
+{
+    switch (s) {
+    case G3_OK: return "ok";
+    case G3_EINVAL: return "invalid argument";
+    case G3_EDOMAIN: return "coordinate outside the box";
+    case G3_ENOMEM: return "out of memory or per-centre neighbour capacity exceeded";
+    case G3_EDEVICE: return "HIP runtime error";
+    case G3_EBUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,699 @@
+// HIP kernels of libg3 for gfx950 (CDNA4, wave64).
+//
+// Pipeline per frame (Sec. 3.3; the paper's parallel g3 logic computes pair
+// vectors first and then the triplets of each centre from them):
+//   cell_count -> cell_scan -> cell_scatter      counting-sort cell build
+//   nbr_count  -> nbr_scan  -> nbr_fill -> nbr_sort
+//                                                minimum-image neighbour
+//                                                vectors of every centre,
+//                                                sorted by their pair bin
+//   triplet (persistent) -> reduce               LDS-privatised r12 slabs,
+//                                                flushed to uint64 bins
+// Everything is integer: coordinates int32, squared distances uint32,
+// LDS counters uint32, output uint64.
+#include <hip/hip_runtime.h>
+
+#include "g3_device.h"
+
+namespace g3 {
+
+namespace {
+
+__device__ __forceinline__ size_t fr_off(const Sys& S, int f, size_t size)
+{
+    return S.per_frame ? (size_t)f * size : 0;
+}
+
+__device__ __forceinline__ int cell_of(int x, int nc, int L)
+{
+    return (int)(((int64_t)x * nc) / L);
+}
+
+// Minimum image of one component (only used on axes with a single cell).
+__device__ __forceinline__ int min_image(int d, int L)
+{
+    if (2 * (int64_t)d > L) return d - L;
+    if (2 * (int64_t)d < -(int64_t)L) return d + L;
+    return d;
+}
+
+// b(s) = max{b : thr[b] <= s} for s < thr[nbins]; the table gives a lower
+// bound and at most a few steps up finish it.
+__device__ __forceinline__ int bin_lookup(uint32_t s, const uint8_t* tab, const uint32_t* thr, int sh)
+{
+    int b = tab[s >> sh];
+    while (s >= thr[b + 1]) ++b;
+    return b;
+}
+
+// Exclusive scan over a 1024-thread block.  tmp needs 17 words.
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
+    }
+    if (lane == 63) tmp[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t y = lane < nw ? tmp[lane] : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t t = __shfl_up(y, o, 64);
+            if (lane >= o) y += t;
+        }
+        if (lane < nw) tmp[lane] = y;
+    }
+    __syncthreads();
+    uint32_t pre = (w > 0 ? tmp[w - 1] : 0u) + x - v;
+    *total = tmp[nw - 1];
+    __syncthreads();
+    return pre;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ utility
+__global__ void k_zero_u32(uint32_t* p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// ------------------------------------------------------------------ cell build
+// Validate coordinates, count atoms per cell and remember each atom's rank
+// inside its cell (the atomic's return value).
+__global__ void __launch_bounds__(256) k_cell_count(const Sys* __restrict__ sys,
+                                                    const Job* __restrict__ jobs)
+{
+    const Job jb = jobs[blockIdx.y];
+    const Sys& S = sys[jb.sys];
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= S.N) return;
+    const int N = S.N, f = jb.frame;
+    const int32_t* fr = S.frames + (size_t)f * 3 * N;
+    const int x = fr[a], y = fr[N + a], z = fr[2 * N + a];
+    if (x < 0 || x >= S.box[0] || y < 0 || y >= S.box[1] || z < 0 || z >= S.box[2]) {
+        atomicOr(&S.flags[f], kFlagDomain);
+        return;
+    }
+    const int cell = (cell_of(z, S.nc[2], S.box[2]) * S.nc[1] + cell_of(y, S.nc[1], S.box[1])) *
+                         S.nc[0] +
+                     cell_of(x, S.nc[0], S.box[0]);
+    int32_t* cc = S.cell_count + fr_off(S, f, S.ncell);
+    const int rank = atomicAdd(&cc[cell], 1);
+    S.atom_cell[fr_off(S, f, N) + a] = cell;
+    S.atom_rank[fr_off(S, f, N) + a] = rank;
+}
+
+// Exclusive scan of the cell counts into cell_start[0..ncell].
+__global__ void __launch_bounds__(1024) k_cell_scan(const Sys* __restrict__ sys,
+                                                    const Job* __restrict__ jobs)
+{
+    __shared__ uint32_t tmp[17];
+    const Job jb = jobs[blockIdx.x];
+    const Sys& S = sys[jb.sys];
+    const int f = jb.frame;
+    const int32_t* cc = S.cell_count + fr_off(S, f, S.ncell);
+    int32_t* cs = S.cell_start + fr_off(S, f, S.ncell + 1);
+    uint32_t carry = 0;
+    for (int base = 0; base < S.ncell; base += 1024) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < S.ncell ? (uint32_t)cc[i] : 0u;
+        uint32_t tot;
+        const uint32_t pre = block_excl_scan(v, tmp, &tot);
+        if (i < S.ncell) cs[i] = (int32_t)(carry + pre);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) cs[S.ncell] = (int32_t)carry;
+}
+
+// Scatter coordinates into cell order (structure of arrays).
+__global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sys,
+                                                      const Job* __restrict__ jobs)
+{
+    const Job jb = jobs[blockIdx.y];
+    const Sys& S = sys[jb.sys];
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    const int N = S.N, f = jb.frame;
+    if (a >= N || (S.flags[f] & kFlagDomain)) return;
+    const int32_t* fr = S.frames + (size_t)f * 3 * N;
+    const int cell = S.atom_cell[fr_off(S, f, N) + a];
+    const int pos = S.cell_start[fr_off(S, f, S.ncell + 1) + cell] + S.atom_rank[fr_off(S, f, N) + a];
+    int32_t* so = S.sorted + fr_off(S, f, (size_t)3 * N);
+    so[pos] = fr[a];
+    so[N + pos] = fr[N + a];
+    so[2 * N + pos] = fr[2 * N + a];
+}
+
+// ------------------------------------------------------------------ neighbours
+// Visit every atom j != i within rmax of centre i (cell-sorted index) through
+// the 27-cell stencil.  With nc >= 3 on an axis the periodic shift of each
+// stencil cell is the minimum image (cell side >= rmax); with nc == 1 the
+// component gets an explicit minimum image.  Components are tested against
+// C before squaring, then s = dx^2 + dy^2 (+ dz^2 only if still below R2),
+// so no uint32 sum overflows for C <= 46340.
+template <typename F>
+__device__ __forceinline__ void visit_neighbours(const Sys& S, const int32_t* __restrict__ X,
+                                                 const int32_t* __restrict__ Y,
+                                                 const int32_t* __restrict__ Z,
+                                                 const int32_t* __restrict__ cs, int i, F&& emit)
+{
+    const int xi = X[i], yi = Y[i], zi = Z[i];
+    const int ncx = S.nc[0], ncy = S.nc[1], ncz = S.nc[2];
+    const int Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
+    const int cx = cell_of(xi, ncx, Lx), cy = cell_of(yi, ncy, Ly), cz = cell_of(zi, ncz, Lz);
+    const int rx = ncx >= 3 ? 1 : 0, ry = ncy >= 3 ? 1 : 0, rz = ncz >= 3 ? 1 : 0;
+    const uint32_t cm1 = (uint32_t)(S.C - 1), span = 2u * cm1;
+    const uint32_t R2 = S.R2;
+    for (int oz = -rz; oz <= rz; ++oz) {
+        int kz = cz + oz, shz = 0;
+        if (kz < 0) { kz += ncz; shz = -Lz; } else if (kz >= ncz) { kz -= ncz; shz = Lz; }
+        for (int oy = -ry; oy <= ry; ++oy) {
+            int ky = cy + oy, shy = 0;
+            if (ky < 0) { ky += ncy; shy = -Ly; } else if (ky >= ncy) { ky -= ncy; shy = Ly; }
+            for (int ox = -rx; ox <= rx; ++ox) {
+                int kx = cx + ox, shx = 0;
+                if (kx < 0) { kx += ncx; shx = -Lx; } else if (kx >= ncx) { kx -= ncx; shx = Lx; }
+                const int cell = (kz * ncy + ky) * ncx + kx;
+                const int j0 = cs[cell], j1 = cs[cell + 1];
+                for (int j = j0; j < j1; ++j) {
+                    if (j == i) continue;
+                    int dx = X[j] + shx - xi, dy = Y[j] + shy - yi, dz = Z[j] + shz - zi;
+                    if (ncx == 1) dx = min_image(dx, Lx);
+                    if (ncy == 1) dy = min_image(dy, Ly);
+                    if (ncz == 1) dz = min_image(dz, Lz);
+                    if ((uint32_t)(dx + (int)cm1) > span || (uint32_t)(dy + (int)cm1) > span ||
+                        (uint32_t)(dz + (int)cm1) > span)
+                        continue;
+                    const uint32_t s2 = (uint32_t)(dx * dx) + (uint32_t)(dy * dy);
+                    if (s2 >= R2) continue;
+                    const uint32_t s = s2 + (uint32_t)(dz * dz);
+                    if (s >= R2) continue;
+                    emit(dx, dy, dz, s);
+                }
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_nbr_count(const Sys* __restrict__ sys,
+                                                   const Job* __restrict__ jobs)
+{
+    const Job jb = jobs[blockIdx.y];
+    const Sys& S = sys[jb.sys];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int N = S.N, f = jb.frame;
+    if (i >= N || (S.flags[f] & kFlagDomain)) return;
+    const int32_t* X = S.sorted + fr_off(S, f, (size_t)3 * N);
+    const int32_t* cs = S.cell_start + fr_off(S, f, S.ncell + 1);
+    uint32_t n = 0;
+    visit_neighbours(S, X, X + N, X + 2 * N, cs, i, [&](int, int, int, uint32_t) { ++n; });
+    S.nbr_off[fr_off(S, f, N + 1) + i] = n;
+    if (n > (uint32_t)S.list_cap) atomicOr(&S.flags[f], kFlagList);
+}
+
+// In-place exclusive scan of the neighbour counts; flags a pool overflow.
+__global__ void __launch_bounds__(1024) k_nbr_scan(const Sys* __restrict__ sys,
+                                                   const Job* __restrict__ jobs)
+{
+    __shared__ uint32_t tmp[17];
+    const Job jb = jobs[blockIdx.x];
+    const Sys& S = sys[jb.sys];
+    const int f = jb.frame, N = S.N;
+    if (S.flags[f] & kFlagDomain) return;
+    uint32_t* off = S.nbr_off + fr_off(S, f, N + 1);
+    uint32_t carry = 0;
+    for (int base = 0; base < N; base += 1024) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < N ? off[i] : 0u;
+        uint32_t tot;
+        const uint32_t pre = block_excl_scan(v, tmp, &tot);
+        if (i < N) off[i] = carry + pre;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        off[N] = carry;
+        if ((int64_t)carry > S.pool_cap) atomicOr(&S.flags[f], kFlagPool);
+    }
+}
+
+template <bool WIDE>
+__global__ void __launch_bounds__(256) k_nbr_fill(const Sys* __restrict__ sys,
+                                                  const Job* __restrict__ jobs)
+{
+    const Job jb = jobs[blockIdx.y];
+    const Sys& S = sys[jb.sys];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int N = S.N, f = jb.frame;
+    if (i >= N || S.flags[f]) return;
+    const int32_t* X = S.sorted + fr_off(S, f, (size_t)3 * N);
+    const int32_t* cs = S.cell_start + fr_off(S, f, S.ncell + 1);
+    const uint32_t o = S.nbr_off[fr_off(S, f, N + 1) + i];
+    const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
+    const uint8_t* tab = S.tab;
+    const uint32_t* thr = S.thr;
+    const int sh = S.sh;
+    uint32_t n = 0;
+    if (WIDE) {
+        int4* P = reinterpret_cast<int4*>(S.pool) + pbase + o;
+        visit_neighbours(S, X, X + N, X + 2 * N, cs, i, [&](int dx, int dy, int dz, uint32_t s) {
+            P[n++] = make_int4(dx, dy, dz, bin_lookup(s, tab, thr, sh));
+        });
+    } else {
+        uint2* P = reinterpret_cast<uint2*>(S.pool) + pbase + o;
+        visit_neighbours(S, X, X + N, X + 2 * N, cs, i, [&](int dx, int dy, int dz, uint32_t s) {
+            const uint32_t b = (uint32_t)bin_lookup(s, tab, thr, sh);
+            P[n++] = make_uint2(((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16),
+                                ((uint32_t)dz & 0xffffu) | (b << 16));
+        });
+    }
+}
+
+// Counting sort of each centre's entries by pair bin (one wave per centre,
+// four centres per block), and the slab row boundaries J_q of each centre.
+template <bool WIDE>
+__global__ void __launch_bounds__(256) k_nbr_sort(const Sys* __restrict__ sys,
+                                                  const Job* __restrict__ jobs)
+{
+    using E = typename std::conditional<WIDE, int4, uint2>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Job jb = jobs[blockIdx.y];
+    const Sys& S = sys[jb.sys];
+    const int N = S.N, f = jb.frame;
+    if (S.flags[f]) return;  // uniform over the block
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int cap = S.list_cap;
+    E* buf = reinterpret_cast<E*>(smem) + (size_t)w * cap;
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(reinterpret_cast<E*>(smem) + 4 * (size_t)cap) + w * 256;
+    uint16_t* rnk = reinterpret_cast<uint16_t*>(reinterpret_cast<uint32_t*>(
+                        reinterpret_cast<E*>(smem) + 4 * (size_t)cap) + 4 * 256) + (size_t)w * cap;
+    const int i = blockIdx.x * 4 + w;
+    const bool live = i < N;
+    const uint32_t* off = S.nbr_off + fr_off(S, f, N + 1);
+    const uint32_t o = live ? off[i] : 0u;
+    const int n = live ? (int)(off[i + 1] - o) : 0;
+    const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
+    E* P = reinterpret_cast<E*>(S.pool) + pbase + o;
+    for (int b = lane; b < 256; b += 64) cnt[b] = 0;
+    __syncthreads();
+    for (int e = lane; e < n; e += 64) {
+        const E v = P[e];
+        buf[e] = v;
+        const int b = WIDE ? (int)((const int*)&v)[3] : (int)(((const uint32_t*)&v)[1] >> 16);
+        rnk[e] = (uint16_t)atomicAdd(&cnt[b], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of cnt[0..255] within the wave: lane owns bins 4l..4l+3
+    uint32_t c0 = cnt[4 * lane], c1 = cnt[4 * lane + 1], c2 = cnt[4 * lane + 2], c3 = cnt[4 * lane + 3];
+    uint32_t sum = c0 + c1 + c2 + c3, x = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(x, d, 64);
+        if (lane >= d) x += t;
+    }
+    uint32_t pre = x - sum;
+    __syncthreads();
+    cnt[4 * lane] = pre;
+    cnt[4 * lane + 1] = pre + c0;
+    cnt[4 * lane + 2] = pre + c0 + c1;
+    cnt[4 * lane + 3] = pre + c0 + c1 + c2;
+    __syncthreads();
+    for (int e = lane; e < n; e += 64) {
+        const E v = buf[e];
+        const int b = WIDE ? (int)((const int*)&v)[3] : (int)(((const uint32_t*)&v)[1] >> 16);
+        P[cnt[b] + rnk[e]] = v;
+    }
+    if (live && lane <= S.n_slabs) {
+        const int lo = S.slab_lo[lane];
+        const uint32_t J = lo >= S.nbins ? (uint32_t)n : cnt[lo];
+        S.slab_j[fr_off(S, f, (size_t)N * (S.n_slabs + 1)) + (size_t)i * (S.n_slabs + 1) + lane] =
+            (uint16_t)J;
+    }
+}
+
+// ------------------------------------------------------------------ triplets
+// Persistent workgroups pull items (system, r12 slab, frame, block of
+// centres) from a device counter.  A workgroup keeps one slab of the half
+// histogram -- rows lo in [lo0, lo1), all hi >= lo, all c -- as uint32
+// counters in LDS while consecutive items share it, and flushes it to a
+// partial slot (or, if slots run out, to the output with uint64 atomics)
+// when the slab changes and at the end.
+//
+// Per centre the neighbour list is sorted by pair bin, so the pairs (j, k),
+// j < k in list order, have lo = b_j and hi = b_k, and the pairs whose lo
+// falls in the slab are exactly the rows j in [J_q, J_{q+1}).  Entries from
+// J_q onward are staged in LDS; each thread walks one row j over k > j:
+//     d_jk = d_ik - d_ij  (componentwise, no re-wrap)
+//     s    = |d_jk|^2,  accepted iff s < R2
+//     slab index = A_j + b_k*nbins + b(s),  A_j = rowoff_slab(b_j) - b_j*nbins
+template <bool WIDE>
+__global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
+{
+    using E = typename std::conditional<WIDE, int4, uint2>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* s_hist = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* s_thr = s_hist + A.hb_max;
+    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + 256);
+    E* s_ent = reinterpret_cast<E*>(s_tab + A.tb_max);
+    uint32_t* s_moff = reinterpret_cast<uint32_t*>(s_ent + A.ec);   // cb + 1
+    uint32_t* s_roff = s_moff + (A.cb + 1);                          // cb + 1
+    uint32_t* s_src = s_roff + (A.cb + 1);                           // cb
+    __shared__ uint32_t s_tmp[17];
+    __shared__ int s_item;
+    __shared__ uint32_t s_slot;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = kTripletThreads / 64;
+    int cur_seg = -1, cur_sys = -1;
+    uint64_t pending = 0;   // upper bound on increments since the last flush
+
+    auto flush = [&](int seg) {
+        const Seg& G = A.segs[seg];
+        __syncthreads();
+        if (tid == 0) s_slot = atomicAdd(&A.ctl->slots_used, 1u);
+        __syncthreads();
+        const uint32_t slot = s_slot;
+        if (slot < (uint32_t)A.max_slots) {
+            uint32_t* dst = A.slots + (size_t)slot * A.hb_max;
+            for (int x = tid; x < G.hb; x += kTripletThreads) dst[x] = s_hist[x];
+            if (tid == 0) A.slot_seg[slot] = seg;
+        } else {
+            // Fallback: add the non-zero bins directly; a wave skips 64 empty
+            // bins with one ballot.
+            const Sys& S = A.sys[G.sys];
+            const int nb = S.nbins;
+            for (int x0 = wave * 64; x0 < G.hb; x0 += kTripletThreads) {
+                const int x = x0 + lane;
+                const uint32_t v = x < G.hb ? s_hist[x] : 0u;
+                if (__ballot(v != 0u) == 0ull) continue;
+                if (v == 0u) continue;
+                const int h = G.half_base + x;
+                if (S.layout == 0) {
+                    atomicAdd((unsigned long long*)&S.hist[h], (unsigned long long)v);
+                } else {
+                    const int p = h / nb, c = h - p * nb;
+                    int lo = 0;
+                    while ((lo + 1) * nb - (lo + 1) * lo / 2 <= p) ++lo;
+                    const int hi = lo + (p - (lo * nb - lo * (lo - 1) / 2));
+                    if (lo == hi) {
+                        atomicAdd((unsigned long long*)&S.hist[((size_t)lo * nb + lo) * nb + c],
+                                  2ull * v);
+                    } else {
+                        atomicAdd((unsigned long long*)&S.hist[((size_t)lo * nb + hi) * nb + c],
+                                  (unsigned long long)v);
+                        atomicAdd((unsigned long long*)&S.hist[((size_t)hi * nb + lo) * nb + c],
+                                  (unsigned long long)v);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    auto zero_hist = [&](int hb) {
+        for (int x = tid; x < hb; x += kTripletThreads) s_hist[x] = 0u;
+    };
+
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd(&A.ctl->next_item, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= A.total_items) break;
+        int seg = 0;
+        while (seg + 1 < A.n_segs && A.segs[seg + 1].item_begin <= item) ++seg;
+        const Seg& G = A.segs[seg];
+        const Sys& S = A.sys[G.sys];
+        if (seg != cur_seg) {
+            if (cur_seg >= 0) flush(cur_seg);
+            if (G.sys != cur_sys) {
+                for (int x = tid; x <= S.nbins; x += kTripletThreads) s_thr[x] = S.thr[x];
+                for (int x = tid; x < S.tab_len; x += kTripletThreads) s_tab[x] = S.tab[x];
+                cur_sys = G.sys;
+            }
+            zero_hist(G.hb);
+            cur_seg = seg;
+            pending = 0;
+            __syncthreads();
+        }
+        const int local = item - G.item_begin;
+        const int f = G.frame0 + local / G.n_blocks;
+        const int blk = local - (local / G.n_blocks) * G.n_blocks;
+        if (S.flags[f] != 0u) continue;
+        const int N = S.N, q = G.slab, nb = S.nbins, lo0 = G.lo0;
+        const int c_begin = blk * A.cb;
+        const int nctr = min(A.cb, N - c_begin);
+        const uint32_t* off = S.nbr_off + (S.per_frame ? (size_t)f * (N + 1) : 0);
+        const uint16_t* J = S.slab_j + (S.per_frame ? (size_t)f * N * (S.n_slabs + 1) : 0);
+        const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
+        const E* P = reinterpret_cast<const E*>(S.pool) + pbase;
+
+        // per centre: entries to stage (m) and rows (r)
+        uint32_t m = 0, r = 0;
+        if (tid < nctr) {
+            const int i = c_begin + tid;
+            const uint32_t o = off[i], n = off[i + 1] - o;
+            const uint32_t j0 = J[(size_t)i * (S.n_slabs + 1) + q];
+            const uint32_t j1 = J[(size_t)i * (S.n_slabs + 1) + q + 1];
+            r = j1 - j0;
+            m = r ? n - j0 : 0u;
+            s_src[tid] = o + j0;
+        }
+        // candidate pairs of this item: row j (0-based) has m - 1 - j partners
+        const uint32_t inc = r ? r * (m - 1) - r * (r - 1) / 2 : 0u;
+        uint32_t mtot, rtot, itot;
+        const uint32_t mpre = block_excl_scan(m, s_tmp, &mtot);
+        const uint32_t rpre = block_excl_scan(r, s_tmp, &rtot);
+        (void)block_excl_scan(inc, s_tmp, &itot);
+        if (tid < nctr) { s_moff[tid] = mpre; s_roff[tid] = rpre; }
+        if (tid == 0) { s_moff[nctr] = mtot; s_roff[nctr] = rtot; }
+        __syncthreads();
+        if (rtot == 0) continue;
+        if (pending + itot > 0xFFFFFFFFull) {  // keep every uint32 LDS counter exact
+            flush(seg);
+            zero_hist(G.hb);
+            pending = 0;
+            __syncthreads();
+        }
+        pending += itot;
+
+        const uint32_t R2 = S.R2;
+        const int sh = S.sh;
+        const int C = S.C;
+        int a = 0;
+        while (a < nctr) {
+            // largest b with s_moff[b] - s_moff[a] <= ec (a single centre always fits)
+            int lo_b = a + 1, hi_b = nctr;
+            const uint32_t lim = s_moff[a] + (uint32_t)A.ec;
+            while (lo_b < hi_b) {
+                const int mid = (lo_b + hi_b + 1) >> 1;
+                if (s_moff[mid] <= lim) lo_b = mid; else hi_b = mid - 1;
+            }
+            const int b = lo_b;
+            const uint32_t base = s_moff[a];
+            // stage entries (one wave per centre), converting bin -> bin*nbins
+            for (int c = a + wave; c < b; c += nwave) {
+                const uint32_t mc = s_moff[c + 1] - s_moff[c];
+                const E* src = P + s_src[c];
+                E* dst = s_ent + (s_moff[c] - base);
+                for (uint32_t e = lane; e < mc; e += 64) {
+                    E v = src[e];
+                    if (WIDE) {
+                        int* vi = reinterpret_cast<int*>(&v);
+                        vi[3] = vi[3] * nb;
+                    } else {
+                        uint32_t* vu = reinterpret_cast<uint32_t*>(&v);
+                        vu[1] = (vu[1] & 0xffffu) | (((vu[1] >> 16) * (uint32_t)nb) << 16);
+                    }
+                    dst[e] = v;
+                }
+            }
+            __syncthreads();
+            const uint32_t r0 = s_roff[a], r1 = s_roff[b];
+            for (uint32_t row = r0 + tid; row < r1; row += kTripletThreads) {
+                // centre owning this row
+                int cl = a, ch = b - 1;
+                while (cl < ch) {
+                    const int mid = (cl + ch + 1) >> 1;
+                    if (s_roff[mid] <= row) cl = mid; else ch = mid - 1;
+                }
+                const uint32_t ej = (s_moff[cl] - base) + (row - s_roff[cl]);
+                const uint32_t eend = s_moff[cl + 1] - base;
+                const E vj = s_ent[ej];
+                if (WIDE) {
+                    const int* vji = reinterpret_cast<const int*>(&vj);
+                    const int Bj = vji[3], bj = Bj / nb;
+                    const int Aj = (((bj - lo0) * nb - ((bj - 1) * bj / 2 - (lo0 - 1) * lo0 / 2)) * nb) - Bj;
+                    const int jx = vji[0], jy = vji[1], jz = vji[2];
+                    const uint32_t cm1 = (uint32_t)(C - 1), span = 2u * cm1;
+                    for (uint32_t k = ej + 1; k < eend; ++k) {
+                        const int4 vk = *reinterpret_cast<const int4*>(&s_ent[k]);
+                        const int dx = vk.x - jx, dy = vk.y - jy, dz = vk.z - jz;
+                        if ((uint32_t)(dx + (int)cm1) > span || (uint32_t)(dy + (int)cm1) > span ||
+                            (uint32_t)(dz + (int)cm1) > span)
+                            continue;
+                        const uint32_t s2 = (uint32_t)(dx * dx) + (uint32_t)(dy * dy);
+                        const uint32_t s = s2 + (uint32_t)(dz * dz);
+                        if (s2 < R2 && s < R2) {
+                            int c = s_tab[s >> sh];
+                            while (s >= s_thr[c + 1]) ++c;
+                            atomicAdd(&s_hist[Aj + vk.w + c], 1u);
+                        }
+                    }
+                } else {
+                    typedef short short2v __attribute__((ext_vector_type(2)));
+                    const uint2 vju = *reinterpret_cast<const uint2*>(&vj);
+                    const int Bj = (int)(vju.y >> 16), bj = Bj / nb;
+                    const int Aj = (((bj - lo0) * nb - ((bj - 1) * bj / 2 - (lo0 - 1) * lo0 / 2)) * nb) - Bj;
+                    const short2v wj0 = __builtin_bit_cast(short2v, vju.x);
+                    const short2v wj1 = __builtin_bit_cast(short2v, vju.y & 0xffffu);
+                    const uint2* ent = reinterpret_cast<const uint2*>(s_ent);
+                    for (uint32_t k = ej + 1; k < eend; ++k) {
+                        const uint2 vk = ent[k];
+                        const short2v dxy = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2v, vk.x), wj0);
+                        const short2v dzB = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2v, vk.y), wj1);
+                        const int dz = (int)dzB.x;
+                        const int s = __builtin_amdgcn_sdot2(dxy, dxy, dz * dz, true);
+                        if ((uint32_t)s < R2) {
+                            int c = s_tab[(uint32_t)s >> sh];
+                            while ((uint32_t)s >= s_thr[c + 1]) ++c;
+                            atomicAdd(&s_hist[Aj + (int)(vk.y >> 16) + c], 1u);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            a = b;
+        }
+    }
+    if (cur_seg >= 0) flush(cur_seg);
+}
+
+// Sum the partial slots of each segment and add them to the output.  Every
+// output bin is written by exactly one thread (slabs of a system are
+// disjoint rows; a half bin maps to its two mirrored full bins).
+__global__ void __launch_bounds__(256) k_reduce(TripletArgs A)
+{
+    const int seg = blockIdx.y;
+    const Seg& G = A.segs[seg];
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= G.hb) return;
+    const uint32_t used = min(A.ctl->slots_used, (uint32_t)A.max_slots);
+    uint64_t sum = 0;
+    for (uint32_t s = 0; s < used; ++s)
+        if (A.slot_seg[s] == seg) sum += A.slots[(size_t)s * A.hb_max + x];
+    if (sum == 0) return;
+    const Sys& S = A.sys[G.sys];
+    const int h = G.half_base + x;
+    if (S.layout == 0) {
+        S.hist[h] += sum;
+        return;
+    }
+    const int nb = S.nbins;
+    const int p = h / nb, c = h - p * nb;
+    int lo = G.lo0;
+    while ((lo + 1) * nb - (lo + 1) * lo / 2 <= p) ++lo;
+    const int hi = lo + (p - (lo * nb - lo * (lo - 1) / 2));
+    if (lo == hi) {
+        S.hist[((size_t)lo * nb + lo) * nb + c] += 2 * sum;
+    } else {
+        S.hist[((size_t)lo * nb + hi) * nb + c] += sum;
+        S.hist[((size_t)hi * nb + lo) * nb + c] += sum;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s)
+{
+    if (!n) return;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+}
+
+void launch_cell_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cell_count, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
+}
+
+void launch_cell_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cell_scan, dim3(n_jobs), dim3(1024), 0, s, sys, jobs);
+}
+
+void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cell_scatter, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
+}
+
+void launch_nbr_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nbr_count, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
+}
+
+void launch_nbr_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nbr_scan, dim3(n_jobs), dim3(1024), 0, s, sys, jobs);
+}
+
+void launch_nbr_fill(const Sys* sys, const Job* jobs, int n_jobs, int max_n, bool wide, hipStream_t s)
+{
+    if (wide)
+        hipLaunchKernelGGL(k_nbr_fill<true>, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
+    else
+        hipLaunchKernelGGL(k_nbr_fill<false>, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
+}
+
+size_t nbr_sort_lds_bytes(int list_cap, bool wide)
+{
+    return (size_t)4 * list_cap * (wide ? 16 : 8) + 4 * 256 * 4 + (size_t)4 * list_cap * 2;
+}
+
+void launch_nbr_sort(const Sys* sys, const Job* jobs, int n_jobs, int max_n, int list_cap, bool wide,
+                     hipStream_t s)
+{
+    const size_t lds = nbr_sort_lds_bytes(list_cap, wide);
+    if (wide)
+        hipLaunchKernelGGL(k_nbr_sort<true>, dim3((max_n + 3) / 4, n_jobs), dim3(256), lds, s, sys, jobs);
+    else
+        hipLaunchKernelGGL(k_nbr_sort<false>, dim3((max_n + 3) / 4, n_jobs), dim3(256), lds, s, sys, jobs);
+}
+
+hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t sort_bytes)
+{
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void*)k_triplet<false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)triplet_bytes)))
+        return e;
+    if ((e = hipFuncSetAttribute((const void*)k_triplet<true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)triplet_bytes)))
+        return e;
+    if ((e = hipFuncSetAttribute((const void*)k_nbr_sort<false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes)))
+        return e;
+    return hipFuncSetAttribute((const void*)k_nbr_sort<true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
+}
+
+void launch_triplet(const TripletArgs& a, bool wide, int n_wg, hipStream_t s)
+{
+    const size_t lds = triplet_lds_bytes(a.hb_max, a.ec, a.cb, a.tb_max, wide);
+    if (wide)
+        hipLaunchKernelGGL(k_triplet<true>, dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_triplet<false>, dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+}
+
+void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s)
+{
+    if (n_segs <= 0) return;
+    hipLaunchKernelGGL(k_reduce, dim3((max_hb + 255) / 256, n_segs), dim3(256), 0, s, a);
+}
+
+}  // namespace g3

@@ -1,0 +1,246 @@
+"""Python binding of libg3 (ctypes): argument marshalling only.
+
+Every function mirrors one entry point of ``include/g3.h`` (same name without
+the ``g3_`` prefix).  Device buffers are torch tensors on the current HIP
+device, passed as raw pointers with torch's current stream; all the work runs
+in the HIP library.  If ``libg3.so`` has not been built this module raises on
+first use -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libg3.so")
+
+HALF, FULL = 0, 1
+OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, EBUSY = range(6)
+MAX_NBINS = 160
+MAX_RMAX = 46340.0
+
+
+class G3Error(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        msg = _strerror(self.status)
+        super().__init__(f"{what}: {msg} (status {self.status})" if what else msg)
+
+
+class System(C.Structure):
+    _fields_ = [("frames", C.c_void_p), ("n_frames", C.c_int32), ("n_atoms", C.c_int32),
+                ("box", C.c_int32 * 3), ("rmax", C.c_double), ("nbins", C.c_int32),
+                ("layout", C.c_int32), ("hist", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("lds_hist_bins", C.c_int32), ("lds_entries", C.c_int32),
+                ("centres_per_item", C.c_int32), ("wg_per_cu", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libg3.so (raises if it is missing: the product has no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1708_08619_amd.build` "
+                           "(or __graft_entry__.build()) first")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "g3_plan_create": ([C.POINTER(P), P], I32),
+        "g3_plan_destroy": ([P], None),
+        "g3_accumulate": ([P, P, I32, I32, P, D, I32, I32, P], I32),
+        "g3_accumulate_batch": ([P, P, I32], I32),
+        "g3_sync": ([P], I32),
+        "g3_hist_len": ([I32, I32], C.c_size_t),
+        "g3_check_args": ([I32, P, D, I32, I32], I32),
+        "g3_thresholds": ([D, I32, P], I32),
+        "g3_normalize": ([P, I32, I32, D, I64, I32, P, P], I32),
+        "g3_ideal_volume": ([I32, D, P], I32),
+        "g3_set_tuning": ([P, P], I32),
+        "g3_get_tuning": ([P, P], I32),
+        "g3_autotune": ([P, P, I32, P], I32),
+        "g3_kernel_time": ([P, C.POINTER(D), C.POINTER(I64)], I32),
+        "g3_kernel_time_reset": ([P, I32], I32),
+        "g3_strerror": ([I32], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().g3_strerror(int(status)).decode()
+    except Exception:  # library missing while formatting an error
+        return f"status {status}"
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise G3Error(status, what)
+
+
+def _box(box) -> C.Array:
+    b = [int(x) for x in box]
+    if len(b) != 3:
+        raise ValueError("box needs 3 edges")
+    return (C.c_int32 * 3)(*b)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ------------------------------------------------------------------ host helpers
+def hist_len(nbins: int, layout: int) -> int:
+    return int(lib().g3_hist_len(int(nbins), int(layout)))
+
+
+def check_args(n_atoms: int, box, rmax: float, nbins: int, layout: int) -> int:
+    return int(lib().g3_check_args(int(n_atoms), _box(box), float(rmax), int(nbins), int(layout)))
+
+
+def thresholds(rmax: float, nbins: int) -> np.ndarray:
+    thr = np.zeros(int(nbins) + 1, dtype=np.uint32)
+    _check(lib().g3_thresholds(float(rmax), int(nbins), _np_ptr(thr)), "g3_thresholds")
+    return thr
+
+
+def ideal_volume(nbins: int, rmax: float) -> np.ndarray:
+    W = np.zeros(int(nbins) ** 3, dtype=np.float64)
+    _check(lib().g3_ideal_volume(int(nbins), float(rmax), _np_ptr(W)), "g3_ideal_volume")
+    return W.reshape((int(nbins),) * 3)
+
+
+def normalize(hist: np.ndarray, layout: int, nbins: int, rmax: float, n_frames: int,
+              n_atoms: int, box) -> np.ndarray:
+    h = np.ascontiguousarray(hist, dtype=np.uint64).reshape(-1)
+    if h.shape[0] != hist_len(nbins, layout):
+        raise ValueError("histogram length does not match nbins/layout")
+    out = np.zeros(h.shape[0], dtype=np.float64)
+    _check(lib().g3_normalize(_np_ptr(h), int(layout), int(nbins), float(rmax), int(n_frames),
+                              int(n_atoms), _box(box), _np_ptr(out)), "g3_normalize")
+    return out
+
+
+def strerror(status: int) -> str:
+    return _strerror(status)
+
+
+# ------------------------------------------------------------------ device plan
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name: str, what: str) -> int:
+    import torch
+    want = {"int32": torch.int32, "uint64": torch.uint64}[dtype_name]
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a torch tensor on the GPU")
+    if t.dtype != want or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous {dtype_name} tensor")
+    return int(t.data_ptr())
+
+
+class Plan:
+    """Owns a ``g3_plan`` bound to one HIP stream (torch's current stream by
+    default)."""
+
+    def __init__(self, stream=None):
+        self._h = C.c_void_p()
+        self.stream = stream
+        _check(lib().g3_plan_create(C.byref(self._h), C.c_void_p(_stream_handle(stream))),
+               "g3_plan_create")
+
+    def close(self):
+        if self._h:
+            lib().g3_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- g3_accumulate: the plain per-frame form
+    def accumulate(self, frames, box, rmax: float, nbins: int, layout: int, hist):
+        F, three, N = (int(x) for x in frames.shape)
+        if three != 3:
+            raise ValueError("frames must be [n_frames, 3, n_atoms]")
+        if hist.numel() != hist_len(nbins, layout):
+            raise ValueError("hist has the wrong length")
+        _check(lib().g3_accumulate(self._h, _dev_ptr(frames, "int32", "frames"), F, N, _box(box),
+                                   float(rmax), int(nbins), int(layout),
+                                   _dev_ptr(hist, "uint64", "hist")), "g3_accumulate")
+
+    # -- g3_accumulate_batch: one graph launch for many systems
+    def accumulate_batch(self, systems: Sequence[dict]):
+        arr = (System * len(systems))()
+        for i, s in enumerate(systems):
+            fr, h = s["frames"], s["hist"]
+            F, three, N = (int(x) for x in fr.shape)
+            if three != 3:
+                raise ValueError("frames must be [n_frames, 3, n_atoms]")
+            if h.numel() != hist_len(s["nbins"], s["layout"]):
+                raise ValueError("hist has the wrong length")
+            arr[i].frames = _dev_ptr(fr, "int32", "frames")
+            arr[i].n_frames = F
+            arr[i].n_atoms = N
+            arr[i].box = _box(s["box"])
+            arr[i].rmax = float(s["rmax"])
+            arr[i].nbins = int(s["nbins"])
+            arr[i].layout = int(s["layout"])
+            arr[i].hist = _dev_ptr(h, "uint64", "hist")
+        _check(lib().g3_accumulate_batch(self._h, arr, len(systems)), "g3_accumulate_batch")
+
+    def sync(self):
+        _check(lib().g3_sync(self._h), "g3_sync")
+
+    def sync_status(self) -> int:
+        return int(lib().g3_sync(self._h))
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{k: int(v) for k, v in kw.items()})
+        _check(lib().g3_set_tuning(self._h, C.byref(t)), "g3_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().g3_get_tuning(self._h, C.byref(t)), "g3_get_tuning")
+        return t.as_dict()
+
+    def kernel_time_reset(self, enable: bool = True):
+        _check(lib().g3_kernel_time_reset(self._h, int(bool(enable))), "g3_kernel_time_reset")
+
+    def kernel_time(self) -> tuple[float, int]:
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().g3_kernel_time(self._h, C.byref(ms), C.byref(n)), "g3_kernel_time")
+        return float(ms.value), int(n.value)
+
+
+def new_hist(nbins: int, layout: int, device="cuda"):
+    import torch
+    return torch.zeros(hist_len(nbins, layout), dtype=torch.uint64, device=device)
