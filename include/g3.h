@@ -158,6 +158,12 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems,
 g3_status g3_kernel_time(g3_plan p, double* avg_ms, int64_t* n_launches);
 g3_status g3_kernel_time_reset(g3_plan p, int32_t enable);
 
+/* Candidate pairs evaluated by the triplet kernel since the last
+ * g3_kernel_time_reset: one per (centre i, unordered {j,k}) with both j and k
+ * within rmax of i -- the pairs whose third side the method must test.
+ * Synchronises the plan's stream. */
+g3_status g3_candidates(g3_plan p, uint64_t* n);
+
 const char* g3_strerror(g3_status s);
 
 #ifdef __cplusplus

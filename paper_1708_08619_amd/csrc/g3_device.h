@@ -91,6 +91,7 @@ struct TripletArgs {
     int32_t ec;              // LDS entries
     int32_t cb;              // centres per item
     int32_t tb_max;          // bytes reserved for the bin table
+    unsigned long long* cand;  // running count of candidate (centre, {j,k}) pairs evaluated
 };
 
 // LDS bytes used by the triplet kernel for a configuration.

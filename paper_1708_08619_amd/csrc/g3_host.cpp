@@ -223,6 +223,7 @@ struct g3_plan_s {
     void* tables = nullptr; size_t tables_n = 0;
     void* slots = nullptr;  size_t slots_n = 0;
     void* ctl = nullptr;
+    unsigned long long* cand = nullptr;   // candidate pairs evaluated since the last reset
     uint32_t* flag_log = nullptr;
     int flag_used = 0;
 
@@ -430,6 +431,10 @@ void add_segments(const Prepared& P, int sys_index, int frame0, int n_frames, in
 g3_status ensure_common(g3_plan p)
 {
     if (!p->ctl) G3_TRY_HIP(hipMalloc(&p->ctl, sizeof(Ctl) * 4));
+    if (!p->cand) {
+        G3_TRY_HIP(hipMalloc((void**)&p->cand, sizeof(unsigned long long)));
+        G3_TRY_HIP(hipMemsetAsync(p->cand, 0, sizeof(unsigned long long), p->stream));
+    }
     if (!p->flag_log) {
         G3_TRY_HIP(hipMalloc((void**)&p->flag_log, sizeof(uint32_t) * kFlagLogCap));
         p->flag_used = 0;
@@ -622,6 +627,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     a.ec = tn.ec;
     a.cb = tn.cb;
     a.tb_max = kTabMax;
+    a.cand = p->cand;
     a.n_segs = S;
     a.total_items = items_per_frame;
     const int N = P.g.N;
@@ -739,6 +745,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         a.ec = tn.ec;
         a.cb = tn.cb;
         a.tb_max = kTabMax;
+        a.cand = p->cand;
         // cell-count zeroing covers the group's whole scratch prefix of counts
         std::vector<std::pair<uint32_t*, size_t>> zero;
         for (auto& P : ps)
@@ -864,6 +871,7 @@ void g3_plan_destroy(g3_plan p)
     if (p->tables) hipFree(p->tables);
     if (p->slots) hipFree(p->slots);
     if (p->ctl) hipFree(p->ctl);
+    if (p->cand) hipFree(p->cand);
     if (p->flag_log) hipFree(p->flag_log);
     for (int b = 0; b < 2; ++b) {
         if (p->stage[b]) hipHostFree(p->stage[b]);
@@ -1008,9 +1016,25 @@ g3_status g3_kernel_time(g3_plan p, double* avg_ms, int64_t* n)
     return G3_OK;
 }
 
+g3_status g3_candidates(g3_plan p, uint64_t* n)
+{
+    if (!p || !n) return G3_EINVAL;
+    *n = 0;
+    if (!p->cand) return G3_OK;
+    unsigned long long v = 0;
+    G3_TRY_HIP(hipStreamSynchronize(p->stream));
+    G3_TRY_HIP(hipMemcpy(&v, p->cand, sizeof(v), hipMemcpyDeviceToHost));
+    *n = v;
+    return G3_OK;
+}
+
 g3_status g3_kernel_time_reset(g3_plan p, int32_t enable)
 {
     if (!p) return G3_EINVAL;
+    if (p->cand) {
+        G3_TRY_HIP(hipStreamSynchronize(p->stream));
+        G3_TRY_HIP(hipMemset(p->cand, 0, sizeof(unsigned long long)));
+    }
     p->timing = enable != 0;
     p->t_acc_ms = 0;
     p->t_n = 0;

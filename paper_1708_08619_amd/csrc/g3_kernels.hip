@@ -372,6 +372,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
     const int lane = tid & 63, wave = tid >> 6, nwave = kTripletThreads / 64;
     int cur_seg = -1, cur_sys = -1;
     uint64_t pending = 0;   // upper bound on increments since the last flush
+    uint64_t evaluated = 0; // candidate pairs of the items this workgroup processed
 
     auto flush = [&](int seg) {
         const Seg& G = A.segs[seg];
@@ -482,6 +483,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             __syncthreads();
         }
         pending += itot;
+        evaluated += itot;
 
         const uint32_t R2 = S.R2;
         const int sh = S.sh;
@@ -573,6 +575,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         }
     }
     if (cur_seg >= 0) flush(cur_seg);
+    if (tid == 0 && evaluated) atomicAdd(A.cand, (unsigned long long)evaluated);
 }
 
 // Sum the partial slots of each segment and add them to the output.  Every

@@ -55,6 +55,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1708_08619_amd.build` "
                            "(or __graft_entry__.build()) first")
+    # torch ships its own HIP runtime.  Loading it first makes libg3's
+    # libamdhip64.so.7 / libhsa-runtime64.so.1 resolve (by soname) to the
+    # copies torch already loaded, so the process has exactly one runtime and
+    # torch's device pointers and streams are valid inside libg3.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
@@ -73,6 +81,7 @@ def lib():
         "g3_autotune": ([P, P, I32, P], I32),
         "g3_kernel_time": ([P, C.POINTER(D), C.POINTER(I64)], I32),
         "g3_kernel_time_reset": ([P, I32], I32),
+        "g3_candidates": ([P, C.POINTER(C.c_uint64)], I32),
         "g3_strerror": ([I32], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -234,6 +243,11 @@ class Plan:
 
     def kernel_time_reset(self, enable: bool = True):
         _check(lib().g3_kernel_time_reset(self._h, int(bool(enable))), "g3_kernel_time_reset")
+
+    def candidates(self) -> int:
+        n = C.c_uint64()
+        _check(lib().g3_candidates(self._h, C.byref(n)), "g3_candidates")
+        return int(n.value)
 
     def kernel_time(self) -> tuple[float, int]:
         ms, n = C.c_double(), C.c_int64()
