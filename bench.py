@@ -1,0 +1,162 @@
+"""Benchmark: g3 triplets binned per second on one MI355X.
+
+Workload: N = 65536 Lennard-Jones-like fluid at rho = 0.85 sigma^-3, 50 frames
+of jittered FCC (sd 0.15 sigma), rmax = 3.0 sigma, dr = 0.05 sigma (60 bins),
+half layout, int32 coordinates at sigma/4096, uint64 counts.  One step is one
+pass of the whole hot path (cell build, neighbour lists, triplet binning,
+flush) over all 50 frames.
+
+Reported: the batched form (one hipGraph launch per step) as the headline,
+the plain per-frame form beside it, the triplet kernel's HIP-event duration
+against the int32 VALU roofline, and the CPU oracle on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic int32 operations of the method (see the design notes):
+#   per candidate pair (centre, unordered {j,k} within rmax of the centre):
+#     d_jk = d_ik - d_ij (3 sub), |d_jk|^2 (3 mul + 2 add), compare with R2 (1)
+#   per binned triplet: exact bin of |d_jk|^2 (table + compare: 2),
+#     histogram address (1), increment (1)
+OPS_PER_CANDIDATE = 9
+OPS_PER_BINNED = 4
+# int32 VALU peak of MI355X: 256 CUs x 64 lanes/clk x 2.4 GHz
+INT32_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-centres", type=int, default=16384)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(frames would shard across GPUs with one uint64 all-reduce of the "
+              "histogram; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1708_08619_amd import g3, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.lj_large(n_frames=args.frames)
+    frames = torch.from_numpy(w.frames).to(dev)
+    hist = g3.new_hist(w.nbins, w.layout, dev)
+    system = dict(frames=frames, box=w.box, rmax=w.rmax, nbins=w.nbins, layout=w.layout,
+                  hist=hist)
+    plan = g3.Plan()
+
+    # triplets binned per step = total of the half histogram of one pass
+    plan.accumulate_batch([system])
+    plan.sync()
+    binned = int(hist.sum().item())
+    hist.zero_()
+
+    def timed(step_fn, steps, warmup):
+        for _ in range(warmup):
+            step_fn()
+        plan.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step_fn()
+        plan.sync()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    batched_s = timed(lambda: plan.accumulate_batch([system]), args.steps, args.warmup)
+
+    # triplet-kernel duration: HIP events around the kernel on the plan's stream
+    # (direct launches of the same kernels with the same arguments)
+    plan.kernel_time_reset(True)
+    timed(lambda: plan.accumulate_batch([system]), max(3, args.steps // 2), 0)
+    kern_ms, kern_n = plan.kernel_time()
+    cand = plan.candidates() // max(kern_n, 1)
+    plan.kernel_time_reset(False)
+
+    plain = None
+    if not args.no_plain:
+        plain_s = timed(lambda: plan.accumulate(frames, w.box, w.rmax, w.nbins, w.layout, hist),
+                        max(2, args.steps // 2), 1)
+        plan.kernel_time_reset(True)
+        timed(lambda: plan.accumulate(frames, w.box, w.rmax, w.nbins, w.layout, hist), 1, 0)
+        pk_ms, pk_n = plan.kernel_time()
+        plan.kernel_time_reset(False)
+        plain = {"value": binned / plain_s / 1e9, "ms_per_step": plain_s * 1e3,
+                 "triplet_kernel_ms_per_frame": pk_ms, "launches_per_step": 11 * w.n_frames}
+
+    ops = OPS_PER_CANDIDATE * cand + OPS_PER_BINNED * binned
+    achieved = ops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
+    roofline = {"bound": "alu", "achieved": achieved, "peak": INT32_VALU_PEAK_TOPS,
+                "unit": "Tops/s (int32)", "frac": achieved / INT32_VALU_PEAK_TOPS if achieved else None,
+                "traffic": None, "kernel": "k_triplet", "kernel_ms": kern_ms,
+                "candidates_per_launch": cand, "binned_per_launch": binned}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, args.cpu_centres)
+
+    line = {
+        "metric": "G triplets binned/s at N=65536 (plain vs batched); p50/p99 served latency",
+        "value": binned / batched_s / 1e9,
+        "unit": "G triplets binned/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": batched_s * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "lj65536_jittered_fcc", "n_atoms": w.n_atoms,
+                   "n_frames": w.n_frames, "rho_sigma3": 0.85, "jitter_sigma": 0.15,
+                   "rmax_sigma": 3.0, "nbins": w.nbins, "layout": "half",
+                   "form": "batched (one hipGraph launch per step)"},
+        "triplets_binned_per_step": binned,
+        "plain": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(w, n_centres: int):
+    """The oracle (plain C, OpenMP over centres) on a bounded sample: the
+    contribution of the first ``n_centres`` centres of frame 0."""
+    import oracle
+    oracle.lib()
+    nt = oracle.max_threads()
+    centres = np.arange(min(n_centres, w.n_atoms), dtype=np.int32)
+    t0 = time.perf_counter()
+    H = oracle.hist_full(w.frames[:1], w.box, w.rmax, w.nbins, n_threads=nt, centres=centres)
+    dt = time.perf_counter() - t0
+    binned = int(H.sum()) // 2                  # unordered pairs = half-layout total
+    return {"value": binned / dt / 1e9, "unit": "G triplets binned/s", "cores": nt,
+            "kind": "oracle", "seconds": dt,
+            "sample": f"frame 0, centres 0..{len(centres) - 1} of {w.n_atoms} "
+                      f"({binned} triplets binned)"}
+
+
+if __name__ == "__main__":
+    main()
