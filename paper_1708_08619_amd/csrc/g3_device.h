@@ -34,6 +34,7 @@ struct Sys {
     uint32_t R2;             // thr[nbins]: s accepted iff s < R2
     int32_t nbins, layout, wide;
     int32_t sh, tab_len;     // bin table: tab[s >> sh] is b(s) or b(s)-1 or lower
+    int32_t one_step;        // 1: tab[s >> sh] is b(s) or b(s)-1
     const uint32_t* thr;     // device [nbins + 1]
     const uint8_t* tab;      // device [tab_len]
     int32_t n_slabs;
@@ -68,8 +69,8 @@ struct Seg {
     int32_t n_blocks;        // centre blocks per frame
     int32_t item_begin;      // first global item index
     int32_t lo0, lo1;        // slab rows
-    int32_t hb;              // histogram bins of the slab
-    int32_t half_base;       // half-layout index of (lo0, lo0, 0)
+    int32_t hb;              // LDS bins of the slab: (lo1 - lo0) * rl
+    int32_t rl;              // bins per slab row: (nbins - lo0) * nbins
 };
 
 struct Ctl {
@@ -113,7 +114,7 @@ void launch_nbr_fill(const Sys* sys, const Job* jobs, int n_jobs, int max_n, boo
 size_t nbr_sort_lds_bytes(int list_cap, bool wide);
 void launch_nbr_sort(const Sys* sys, const Job* jobs, int n_jobs, int max_n, int list_cap, bool wide,
                      hipStream_t s);
-void launch_triplet(const TripletArgs& a, bool wide, int n_wg, hipStream_t s);
+void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t sort_bytes);
 

@@ -83,13 +83,11 @@ struct Geometry {
     int box[3] = {0, 0, 0}, nc[3] = {1, 1, 1}, ncell = 1;
     int C = 0;
     uint32_t R2 = 0;
-    int sh = 0, tab_len = 0;
+    int sh = 0, tab_len = 0, one_step = 0;
     std::vector<uint32_t> thr;
     std::vector<uint8_t> tab;
     std::vector<int> slab_lo;  // n_slabs + 1 boundaries
 };
-
-inline int64_t half_rowoff(int lo, int nb) { return (int64_t)lo * nb - (int64_t)lo * (lo - 1) / 2; }
 
 g3_status check(int32_t n_atoms, const int32_t box[3], double rmax, int32_t nbins, int32_t layout)
 {
@@ -149,9 +147,18 @@ void plan_bins(Geometry& g, double rmax)
         while (b + 1 < g.nbins && s >= g.thr[b + 1]) ++b;
         g.tab[q] = (uint8_t)b;
     }
+    // one threshold step suffices iff no table cell holds two thresholds
+    // strictly after its first value
+    const uint32_t mask = (1u << sh) - 1u;
+    g.one_step = 1;
+    for (int k = 1; k + 1 <= g.nbins - 1; ++k)
+        if ((g.thr[k] >> sh) == (g.thr[k + 1] >> sh) && (g.thr[k] & mask) != 0u) g.one_step = 0;
 }
 
-// r12 slabs: consecutive rows lo whose half-layout bins fit hb_max.
+// r12 slabs: consecutive rows lo0..lo1-1, each held as an extended row of
+// (nbins - lo0) * nbins bins, as many as fit hb_max.
+inline int64_t slab_bins(int lo0, int lo1, int nb) { return (int64_t)(lo1 - lo0) * (nb - lo0) * nb; }
+
 bool plan_slabs(Geometry& g, int hb_max)
 {
     g.slab_lo.clear();
@@ -159,7 +166,7 @@ bool plan_slabs(Geometry& g, int hb_max)
     int lo = 0;
     while (lo < g.nbins) {
         int hi = lo;
-        while (hi < g.nbins && (half_rowoff(hi + 1, g.nbins) - half_rowoff(lo, g.nbins)) * g.nbins <= hb_max)
+        while (hi < g.nbins && slab_bins(lo, hi + 1, g.nbins) <= hb_max)
             ++hi;
         if (hi == lo) return false;  // a single row does not fit
         g.slab_lo.push_back(hi);
@@ -287,7 +294,7 @@ struct Tun {
 Tun effective(const g3_plan p, bool wide)
 {
     Tun t;
-    t.ec = p->tun.lds_entries > 0 ? p->tun.lds_entries : 2048;
+    t.ec = p->tun.lds_entries > 0 ? p->tun.lds_entries : (wide ? 2048 : 4096);
     t.ec = std::max(t.ec, kListCap);
     t.cb = p->tun.centres_per_item > 0 ? std::min(p->tun.centres_per_item, kTripletThreads) : 256;
     t.wg_per_cu = p->tun.wg_per_cu == 2 ? 2 : 1;
@@ -385,6 +392,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
     s.wide = g.wide;
     s.sh = g.sh;
     s.tab_len = g.tab_len;
+    s.one_step = g.one_step;
     s.thr = reinterpret_cast<const uint32_t*>(arena + P.off_thr);
     s.tab = reinterpret_cast<const uint8_t*>(arena + P.off_tab);
     s.n_slabs = (int)g.slab_lo.size() - 1;
@@ -421,8 +429,8 @@ void add_segments(const Prepared& P, int sys_index, int frame0, int n_frames, in
         s.item_begin = items;
         s.lo0 = g.slab_lo[q];
         s.lo1 = g.slab_lo[q + 1];
-        s.hb = (int)((half_rowoff(s.lo1, g.nbins) - half_rowoff(s.lo0, g.nbins)) * g.nbins);
-        s.half_base = (int)(half_rowoff(s.lo0, g.nbins) * g.nbins);
+        s.hb = (int)slab_bins(s.lo0, s.lo1, g.nbins);
+        s.rl = (g.nbins - s.lo0) * g.nbins;
         segs.push_back(s);
         items += n_blocks * n_frames;
     }
@@ -645,7 +653,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
         a.segs = dsegs + (size_t)f * S;
         hipEvent_t e0;
         timing_begin(p, &e0);
-        launch_triplet(a, P.g.wide != 0, n_wg, p->stream);
+        launch_triplet(a, P.g.wide != 0, P.g.one_step != 0, n_wg, p->stream);
         timing_end(p, e0);
         launch_reduce(a, tn.hb_max, S, p->stream);
     }
@@ -699,6 +707,8 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             max_n = std::max(max_n, ps[k].g.N);
         }
         for (auto& s : segs) max_hb = std::max(max_hb, s.hb);
+        bool one_step = true;
+        for (auto& P : ps) one_step = one_step && P.g.one_step;
         const int n_wg = p->n_cu * tn.wg_per_cu;
         const int max_slots = n_wg * 3 + 2 * (int)segs.size() + 64;
         const size_t o_sys = 0, o_jobs = align_up(sizeof(Sys) * sys.size(), 256),
@@ -721,6 +731,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         std::string key;
         auto put = [&](const void* d, size_t n) { key.append((const char*)d, n); };
         put(&wide, sizeof(wide));
+        put(&one_step, sizeof(one_step));
         put(&tn, sizeof(tn));
         int nj = (int)jobs.size(), ns = (int)segs.size();
         put(&nj, 4); put(&ns, 4); put(&items, 4); put(&max_n, 4); put(&max_hb, 4);
@@ -762,7 +773,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_nbr_scan(dsys, djobs, nj, sm);
             launch_nbr_fill(dsys, djobs, nj, max_n, wide, sm);
             launch_nbr_sort(dsys, djobs, nj, max_n, kListCap, wide, sm);
-            launch_triplet(a, wide, n_wg, sm);
+            launch_triplet(a, wide, one_step, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
         };
         if (p->timing) {
@@ -778,7 +789,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_nbr_sort(dsys, djobs, nj, max_n, kListCap, wide, p->stream);
             hipEvent_t e0;
             timing_begin(p, &e0);
-            launch_triplet(a, wide, n_wg, p->stream);
+            launch_triplet(a, wide, one_step, n_wg, p->stream);
             timing_end(p, e0);
             launch_reduce(a, max_hb, ns, p->stream);
             G3_TRY_HIP(hipGetLastError());

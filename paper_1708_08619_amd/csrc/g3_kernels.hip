@@ -339,28 +339,93 @@ __global__ void __launch_bounds__(256) k_nbr_sort(const Sys* __restrict__ sys,
 
 // ------------------------------------------------------------------ triplets
 // Persistent workgroups pull items (system, r12 slab, frame, block of
-// centres) from a device counter.  A workgroup keeps one slab of the half
-// histogram -- rows lo in [lo0, lo1), all hi >= lo, all c -- as uint32
-// counters in LDS while consecutive items share it, and flushes it to a
-// partial slot (or, if slots run out, to the output with uint64 atomics)
-// when the slab changes and at the end.
+// centres) from a device counter.  A workgroup keeps one slab of the
+// histogram in LDS as uint32 counters while consecutive items share it, and
+// flushes it to a partial slot (or, if slots run out, to the output with
+// uint64 atomics) when the slab changes and at the end.
 //
-// Per centre the neighbour list is sorted by pair bin, so the pairs (j, k),
-// j < k in list order, have lo = b_j and hi = b_k, and the pairs whose lo
-// falls in the slab are exactly the rows j in [J_q, J_{q+1}).  Entries from
-// J_q onward are staged in LDS; each thread walks one row j over k > j:
-//     d_jk = d_ik - d_ij  (componentwise, no re-wrap)
-//     s    = |d_jk|^2,  accepted iff s < R2
-//     slab index = A_j + b_k*nbins + b(s),  A_j = rowoff_slab(b_j) - b_j*nbins
+// Slab layout ("extended rows"): rows a in [lo0, lo1), columns b in
+// [lo0, nbins), all c: index (a - lo0) * RL + (b - lo0) * nbins + c with
+// RL = (nbins - lo0) * nbins.  An unordered pair is counted once, at
+// (b_j, b_k) for the row j it was evaluated from; the reduce folds (a, b) and
+// (b, a) into the half-layout bin (min, max, c).
+//
+// Per centre the neighbour list is sorted by pair bin.  The pairs whose
+// smaller bin lies in the slab are those with at least one member among the
+// slab rows, entries [J_q, J_q+1) (local 0..r-1 after staging from J_q):
+//   triangle:  both members in the slab rows -- row j takes k = j+1 ... j+h
+//              (mod r), h = (r-1)/2, plus k = j + r/2 for j < r/2 when r is
+//              even, so each unordered pair is visited exactly once;
+//   rectangle: j a slab row, k = r .. m-1 (bins >= lo1).
+// Every row of a centre therefore has the same length, m - r + ~r/2.
+// Per candidate: d_jk = d_ik - d_ij (no re-wrap), s = |d_jk|^2 exact,
+// accepted iff s < R2, bin c from the table plus one threshold step.
+namespace {
+
 template <bool WIDE>
+struct Ent;
+
+template <>
+struct Ent<false> {
+    typedef uint2 T;
+    typedef short short2v __attribute__((ext_vector_type(2)));
+    // squared length of (k - j); saturating 16-bit differences and a clamped
+    // dot product keep out-of-range candidates >= R2 (C <= 32767)
+    static __device__ __forceinline__ uint32_t dist2(T vk, uint32_t jx, uint32_t jz, int)
+    {
+        const short2v dxy = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2v, vk.x),
+                                                          __builtin_bit_cast(short2v, jx));
+        const short2v dzB = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2v, vk.y),
+                                                          __builtin_bit_cast(short2v, jz));
+        const int dz = (int)dzB.x;
+        return (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, dz * dz, true);
+    }
+    static __device__ __forceinline__ int col(T v) { return (int)(v.y >> 16); }
+};
+
+template <>
+struct Ent<true> {
+    typedef int4 T;
+    // component pre-test against C, then s = dx^2 + dy^2 (+ dz^2): exact
+    // in uint32 for C <= 46340; rejected candidates return 0xffffffff
+    static __device__ __forceinline__ uint32_t dist2(T vk, int jx, int jy, int jz, int cm1)
+    {
+        const int dx = vk.x - jx, dy = vk.y - jy, dz = vk.z - jz;
+        const uint32_t span = 2u * (uint32_t)cm1;
+        if ((uint32_t)(dx + cm1) > span || (uint32_t)(dy + cm1) > span || (uint32_t)(dz + cm1) > span)
+            return 0xffffffffu;
+        const uint32_t s2 = (uint32_t)(dx * dx) + (uint32_t)(dy * dy);
+        const uint32_t s = s2 + (uint32_t)(dz * dz);
+        return s < s2 ? 0xffffffffu : s;   // s < s2 only if adding dz^2 wrapped
+    }
+    static __device__ __forceinline__ int col(T v) { return v.w; }
+};
+
+// Bin of an accepted squared distance s (< R2) from the LDS tables.
+template <bool ONE_STEP>
+__device__ __forceinline__ int lds_bin(uint32_t s, uint32_t sclamp, const uint8_t* tab,
+                                       const uint32_t* thr, int sh)
+{
+    int c = tab[sclamp >> sh];
+    if (ONE_STEP) {
+        c += (s >= thr[c + 1]) ? 1 : 0;
+    } else {
+        while (sclamp >= thr[c + 1]) ++c;
+    }
+    return c;
+}
+
+}  // namespace
+
+template <bool WIDE, bool ONE_STEP>
 __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
 {
-    using E = typename std::conditional<WIDE, int4, uint2>::type;
+    using E = typename Ent<WIDE>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* s_hist = reinterpret_cast<uint32_t*>(smem);
     uint32_t* s_thr = s_hist + A.hb_max;
     uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + 256);
-    E* s_ent = reinterpret_cast<E*>(s_tab + A.tb_max);
+    E* s_ent = reinterpret_cast<E*>(__builtin_assume_aligned(s_tab + A.tb_max, 16));
     uint32_t* s_moff = reinterpret_cast<uint32_t*>(s_ent + A.ec);   // cb + 1
     uint32_t* s_roff = s_moff + (A.cb + 1);                          // cb + 1
     uint32_t* s_src = s_roff + (A.cb + 1);                           // cb
@@ -371,8 +436,8 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = kTripletThreads / 64;
     int cur_seg = -1, cur_sys = -1;
-    uint64_t pending = 0;   // upper bound on increments since the last flush
-    uint64_t evaluated = 0; // candidate pairs of the items this workgroup processed
+    uint64_t pending = 0;    // upper bound on increments since the last flush
+    uint64_t evaluated = 0;  // candidate pairs of the items this workgroup processed
 
     auto flush = [&](int seg) {
         const Seg& G = A.segs[seg];
@@ -388,29 +453,25 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             // Fallback: add the non-zero bins directly; a wave skips 64 empty
             // bins with one ballot.
             const Sys& S = A.sys[G.sys];
-            const int nb = S.nbins;
+            const int nb = S.nbins, RL = G.rl;
             for (int x0 = wave * 64; x0 < G.hb; x0 += kTripletThreads) {
                 const int x = x0 + lane;
                 const uint32_t v = x < G.hb ? s_hist[x] : 0u;
                 if (__ballot(v != 0u) == 0ull) continue;
                 if (v == 0u) continue;
-                const int h = G.half_base + x;
+                const int a = G.lo0 + x / RL, rem = x - (x / RL) * RL;
+                const int b = G.lo0 + rem / nb, c = rem - (rem / nb) * nb;
+                const int lo = min(a, b), hi = max(a, b);
                 if (S.layout == 0) {
+                    const size_t h = ((size_t)lo * nb - (size_t)lo * (lo - 1) / 2 + (hi - lo)) * nb + c;
                     atomicAdd((unsigned long long*)&S.hist[h], (unsigned long long)v);
+                } else if (lo == hi) {
+                    atomicAdd((unsigned long long*)&S.hist[((size_t)lo * nb + lo) * nb + c], 2ull * v);
                 } else {
-                    const int p = h / nb, c = h - p * nb;
-                    int lo = 0;
-                    while ((lo + 1) * nb - (lo + 1) * lo / 2 <= p) ++lo;
-                    const int hi = lo + (p - (lo * nb - lo * (lo - 1) / 2));
-                    if (lo == hi) {
-                        atomicAdd((unsigned long long*)&S.hist[((size_t)lo * nb + lo) * nb + c],
-                                  2ull * v);
-                    } else {
-                        atomicAdd((unsigned long long*)&S.hist[((size_t)lo * nb + hi) * nb + c],
-                                  (unsigned long long)v);
-                        atomicAdd((unsigned long long*)&S.hist[((size_t)hi * nb + lo) * nb + c],
-                                  (unsigned long long)v);
-                    }
+                    atomicAdd((unsigned long long*)&S.hist[((size_t)lo * nb + hi) * nb + c],
+                              (unsigned long long)v);
+                    atomicAdd((unsigned long long*)&S.hist[((size_t)hi * nb + lo) * nb + c],
+                              (unsigned long long)v);
                 }
             }
         }
@@ -455,7 +516,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
         const E* P = reinterpret_cast<const E*>(S.pool) + pbase;
 
-        // per centre: entries to stage (m) and rows (r)
+        // per centre: entries to stage (m, from J_q on) and slab rows (r)
         uint32_t m = 0, r = 0;
         if (tid < nctr) {
             const int i = c_begin + tid;
@@ -466,8 +527,8 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             m = r ? n - j0 : 0u;
             s_src[tid] = o + j0;
         }
-        // candidate pairs of this item: row j (0-based) has m - 1 - j partners
-        const uint32_t inc = r ? r * (m - 1) - r * (r - 1) / 2 : 0u;
+        // candidate pairs of this item: r(r-1)/2 + r(m-r) per centre
+        const uint32_t inc = r ? r * (r - 1) / 2 + r * (m - r) : 0u;
         uint32_t mtot, rtot, itot;
         const uint32_t mpre = block_excl_scan(m, s_tmp, &mtot);
         const uint32_t rpre = block_excl_scan(r, s_tmp, &rtot);
@@ -485,9 +546,10 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         pending += itot;
         evaluated += itot;
 
-        const uint32_t R2 = S.R2;
+        const uint32_t R2 = S.R2, R2m1 = S.R2 - 1u;
         const int sh = S.sh;
-        const int C = S.C;
+        const int cm1 = S.C - 1;
+        const int colmul = nb - lo0;        // A_j = (b_j - lo0) * RL = B'_j * (nbins - lo0)
         int a = 0;
         while (a < nctr) {
             // largest b with s_moff[b] - s_moff[a] <= ec (a single centre always fits)
@@ -499,7 +561,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             }
             const int b = lo_b;
             const uint32_t base = s_moff[a];
-            // stage entries (one wave per centre), converting bin -> bin*nbins
+            // stage entries (one wave per centre), bin b -> (b - lo0) * nbins
             for (int c = a + wave; c < b; c += nwave) {
                 const uint32_t mc = s_moff[c + 1] - s_moff[c];
                 const E* src = P + s_src[c];
@@ -508,10 +570,10 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     E v = src[e];
                     if (WIDE) {
                         int* vi = reinterpret_cast<int*>(&v);
-                        vi[3] = vi[3] * nb;
+                        vi[3] = (vi[3] - lo0) * nb;
                     } else {
                         uint32_t* vu = reinterpret_cast<uint32_t*>(&v);
-                        vu[1] = (vu[1] & 0xffffu) | (((vu[1] >> 16) * (uint32_t)nb) << 16);
+                        vu[1] = (vu[1] & 0xffffu) | ((((vu[1] >> 16) - (uint32_t)lo0) * (uint32_t)nb) << 16);
                     }
                     dst[e] = v;
                 }
@@ -519,56 +581,78 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             __syncthreads();
             const uint32_t r0 = s_roff[a], r1 = s_roff[b];
             for (uint32_t row = r0 + tid; row < r1; row += kTripletThreads) {
-                // centre owning this row
                 int cl = a, ch = b - 1;
                 while (cl < ch) {
                     const int mid = (cl + ch + 1) >> 1;
                     if (s_roff[mid] <= row) cl = mid; else ch = mid - 1;
                 }
-                const uint32_t ej = (s_moff[cl] - base) + (row - s_roff[cl]);
-                const uint32_t eend = s_moff[cl + 1] - base;
-                const E vj = s_ent[ej];
+                const E* ent = s_ent + (s_moff[cl] - base);
+                const int mm = (int)(s_moff[cl + 1] - s_moff[cl]);
+                const int rr = (int)(s_roff[cl + 1] - s_roff[cl]);
+                const int j = (int)(row - s_roff[cl]);
+                const E vj = ent[j];
+                const int Aj = Ent<WIDE>::col(vj) * colmul;
+                uint32_t jx, jy = 0, jz;
                 if (WIDE) {
                     const int* vji = reinterpret_cast<const int*>(&vj);
-                    const int Bj = vji[3], bj = Bj / nb;
-                    const int Aj = (((bj - lo0) * nb - ((bj - 1) * bj / 2 - (lo0 - 1) * lo0 / 2)) * nb) - Bj;
-                    const int jx = vji[0], jy = vji[1], jz = vji[2];
-                    const uint32_t cm1 = (uint32_t)(C - 1), span = 2u * cm1;
-                    for (uint32_t k = ej + 1; k < eend; ++k) {
-                        const int4 vk = *reinterpret_cast<const int4*>(&s_ent[k]);
-                        const int dx = vk.x - jx, dy = vk.y - jy, dz = vk.z - jz;
-                        if ((uint32_t)(dx + (int)cm1) > span || (uint32_t)(dy + (int)cm1) > span ||
-                            (uint32_t)(dz + (int)cm1) > span)
-                            continue;
-                        const uint32_t s2 = (uint32_t)(dx * dx) + (uint32_t)(dy * dy);
-                        const uint32_t s = s2 + (uint32_t)(dz * dz);
-                        if (s2 < R2 && s < R2) {
-                            int c = s_tab[s >> sh];
-                            while (s >= s_thr[c + 1]) ++c;
-                            atomicAdd(&s_hist[Aj + vk.w + c], 1u);
-                        }
-                    }
+                    jx = (uint32_t)vji[0]; jy = (uint32_t)vji[1]; jz = (uint32_t)vji[2];
                 } else {
-                    typedef short short2v __attribute__((ext_vector_type(2)));
-                    const uint2 vju = *reinterpret_cast<const uint2*>(&vj);
-                    const int Bj = (int)(vju.y >> 16), bj = Bj / nb;
-                    const int Aj = (((bj - lo0) * nb - ((bj - 1) * bj / 2 - (lo0 - 1) * lo0 / 2)) * nb) - Bj;
-                    const short2v wj0 = __builtin_bit_cast(short2v, vju.x);
-                    const short2v wj1 = __builtin_bit_cast(short2v, vju.y & 0xffffu);
-                    const uint2* ent = reinterpret_cast<const uint2*>(s_ent);
-                    for (uint32_t k = ej + 1; k < eend; ++k) {
-                        const uint2 vk = ent[k];
-                        const short2v dxy = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2v, vk.x), wj0);
-                        const short2v dzB = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2v, vk.y), wj1);
-                        const int dz = (int)dzB.x;
-                        const int s = __builtin_amdgcn_sdot2(dxy, dxy, dz * dz, true);
-                        if ((uint32_t)s < R2) {
-                            int c = s_tab[(uint32_t)s >> sh];
-                            while ((uint32_t)s >= s_thr[c + 1]) ++c;
-                            atomicAdd(&s_hist[Aj + (int)(vk.y >> 16) + c], 1u);
-                        }
-                    }
+                    const uint2 vu = *reinterpret_cast<const uint2*>(&vj);
+                    jx = vu.x; jz = vu.y & 0xffffu;
                 }
+                auto d2 = [&](const E& vk) -> uint32_t {
+                    if constexpr (WIDE)
+                        return Ent<true>::dist2(vk, (int)jx, (int)jy, (int)jz, cm1);
+                    else
+                        return Ent<false>::dist2(vk, jx, jz, 0);
+                };
+                // four candidates at a time: loads, distances, table, threshold,
+                // then the (predicated) LDS increments
+                auto eval4 = [&](const E (&v)[4]) {
+                    uint32_t s[4], sc[4];
+                    int c[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) { s[u] = d2(v[u]); sc[u] = min(s[u], R2m1); }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) c[u] = lds_bin<ONE_STEP>(s[u], sc[u], s_tab, s_thr, sh);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (s[u] < R2) atomicAdd(&s_hist[Aj + Ent<WIDE>::col(v[u]) + c[u]], 1u);
+                };
+                auto eval1 = [&](const E& v) {
+                    const uint32_t s = d2(v);
+                    if (s < R2) {
+                        const int c = lds_bin<ONE_STEP>(s, s, s_tab, s_thr, sh);
+                        atomicAdd(&s_hist[Aj + Ent<WIDE>::col(v) + c], 1u);
+                    }
+                };
+                // triangle (circular within the slab rows)
+                const int H = (rr - 1) / 2 + (((rr & 1) == 0 && j < rr / 2) ? 1 : 0);
+                int t = 1;
+                for (; t + 4 <= H + 1; t += 4) {
+                    E v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        int k = j + t + u;
+                        k -= (k >= rr) ? rr : 0;
+                        v[u] = ent[k];
+                    }
+                    eval4(v);
+                }
+                for (; t <= H; ++t) {
+                    int k = j + t;
+                    k -= (k >= rr) ? rr : 0;
+                    eval1(ent[k]);
+                }
+                // rectangle
+                int k = rr;
+                for (; k + 4 <= mm; k += 4) {
+                    E v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = ent[k + u];
+                    eval4(v);
+                }
+                for (; k < mm; ++k) eval1(ent[k]);
             }
             __syncthreads();
             a = b;
@@ -578,36 +662,39 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
     if (tid == 0 && evaluated) atomicAdd(A.cand, (unsigned long long)evaluated);
 }
 
-// Sum the partial slots of each segment and add them to the output.  Every
-// output bin is written by exactly one thread (slabs of a system are
-// disjoint rows; a half bin maps to its two mirrored full bins).
+// Sum the partial slots of each segment and add them to the output.  The
+// thread of slab bin (a, b, c) with a <= b owns half bin (a, b, c): it adds
+// the mirror (b, a, c) when b is a slab row too, and writes the output
+// (half, or both mirrored full bins), so every output bin has one writer.
 __global__ void __launch_bounds__(256) k_reduce(TripletArgs A)
 {
     const int seg = blockIdx.y;
     const Seg& G = A.segs[seg];
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= G.hb) return;
+    const Sys& S = A.sys[G.sys];
+    const int nb = S.nbins, RL = G.rl;
+    const int a = G.lo0 + x / RL, rem = x - (x / RL) * RL;
+    const int b = G.lo0 + rem / nb, c = rem - (rem / nb) * nb;
+    if (b < a) return;
+    const bool mirror = b != a && b < G.lo1;
+    const int xm = (b - G.lo0) * RL + (a - G.lo0) * nb + c;
     const uint32_t used = min(A.ctl->slots_used, (uint32_t)A.max_slots);
     uint64_t sum = 0;
     for (uint32_t s = 0; s < used; ++s)
-        if (A.slot_seg[s] == seg) sum += A.slots[(size_t)s * A.hb_max + x];
+        if (A.slot_seg[s] == seg) {
+            const uint32_t* sl = A.slots + (size_t)s * A.hb_max;
+            sum += sl[x];
+            if (mirror) sum += sl[xm];
+        }
     if (sum == 0) return;
-    const Sys& S = A.sys[G.sys];
-    const int h = G.half_base + x;
     if (S.layout == 0) {
-        S.hist[h] += sum;
-        return;
-    }
-    const int nb = S.nbins;
-    const int p = h / nb, c = h - p * nb;
-    int lo = G.lo0;
-    while ((lo + 1) * nb - (lo + 1) * lo / 2 <= p) ++lo;
-    const int hi = lo + (p - (lo * nb - lo * (lo - 1) / 2));
-    if (lo == hi) {
-        S.hist[((size_t)lo * nb + lo) * nb + c] += 2 * sum;
+        S.hist[((size_t)a * nb - (size_t)a * (a - 1) / 2 + (b - a)) * nb + c] += sum;
+    } else if (a == b) {
+        S.hist[((size_t)a * nb + a) * nb + c] += 2 * sum;
     } else {
-        S.hist[((size_t)lo * nb + hi) * nb + c] += sum;
-        S.hist[((size_t)hi * nb + lo) * nb + c] += sum;
+        S.hist[((size_t)a * nb + b) * nb + c] += sum;
+        S.hist[((size_t)b * nb + a) * nb + c] += sum;
     }
 }
 
@@ -670,13 +757,12 @@ void launch_nbr_sort(const Sys* sys, const Job* jobs, int n_jobs, int max_n, int
 
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t sort_bytes)
 {
+    const void* trip[4] = {(const void*)k_triplet<false, false>, (const void*)k_triplet<false, true>,
+                           (const void*)k_triplet<true, false>, (const void*)k_triplet<true, true>};
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void*)k_triplet<false>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)triplet_bytes)))
-        return e;
-    if ((e = hipFuncSetAttribute((const void*)k_triplet<true>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)triplet_bytes)))
-        return e;
+    for (const void* k : trip)
+        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)triplet_bytes)))
+            return e;
     if ((e = hipFuncSetAttribute((const void*)k_nbr_sort<false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes)))
         return e;
@@ -684,13 +770,20 @@ hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t sort_bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
 }
 
-void launch_triplet(const TripletArgs& a, bool wide, int n_wg, hipStream_t s)
+void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s)
 {
     const size_t lds = triplet_lds_bytes(a.hb_max, a.ec, a.cb, a.tb_max, wide);
-    if (wide)
-        hipLaunchKernelGGL(k_triplet<true>, dim3(n_wg), dim3(kTripletThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_triplet<false>, dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+    if (wide) {
+        if (one_step)
+            hipLaunchKernelGGL((k_triplet<true, true>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_triplet<true, false>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+    } else {
+        if (one_step)
+            hipLaunchKernelGGL((k_triplet<false, true>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_triplet<false, false>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+    }
 }
 
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s)
