@@ -107,7 +107,7 @@ def main():
         pk_ms, pk_n = plan.kernel_time()
         plan.kernel_time_reset(False)
         plain = {"value": binned / plain_s / 1e9, "ms_per_step": plain_s * 1e3,
-                 "triplet_kernel_ms_per_frame": pk_ms, "launches_per_step": 11 * w.n_frames}
+                 "triplet_kernel_ms_per_frame": pk_ms}
 
     ops = OPS_PER_CANDIDATE * cand + OPS_PER_BINNED * binned
     achieved = ops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None

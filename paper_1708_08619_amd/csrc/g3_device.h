@@ -12,6 +12,7 @@ namespace g3 {
 constexpr int kMaxSlabs = 24;          // r12 slabs per system
 constexpr int kTripletThreads = 1024;  // threads of the triplet workgroup
 constexpr int kWave = 64;
+constexpr int kCursorStride = 32;   // uint32 words between per-frame pool cursors (one 128 B line each)
 
 // Per-frame status bits (one uint32 per frame and system).
 constexpr uint32_t kFlagDomain = 1u;   // coordinate outside [0, L)
@@ -46,8 +47,11 @@ struct Sys {
     int32_t* atom_cell;      // [N]
     int32_t* atom_rank;      // [N]
     int32_t* sorted;         // [3][N]
-    uint32_t* nbr_off;       // [N + 1]  (offsets into the frame's pool slot)
-    uint16_t* slab_j;        // [N][n_slabs + 1]  J_q = #entries with bin < slab_lo[q]
+    uint32_t* nbr_off;       // [N]  offset of each centre's list in the frame's pool slot
+    uint32_t* nbr_cnt;       // [N]  its length
+    uint32_t* cursor;        // [F * kCursorStride]  pool slot fill level (always per frame)
+    uint16_t* slab_j;        // [N][n_slabs + 1]  J_q = #entries with bin < slab_lo[q];
+                             // a list is partitioned by slab: slab q holds [J_q, J_q+1)
     void* pool;              // entries, 8 or 16 bytes each
     int64_t pool_cap;        // entries per frame slot
     int32_t per_frame;       // 1: every frame has its own scratch; 0: reused
@@ -103,19 +107,28 @@ inline size_t triplet_lds_bytes(int hb_max, int ec, int cb, int tb_max, bool wid
     return b;
 }
 
+// Neighbour build launch shape: workgroups per frame (each loops over cells),
+// waves per workgroup and the pool entries a wave reserves at a time.
+constexpr int kBuildWavesPerWG = 4;
+constexpr uint32_t kBuildChunk = 2048;
+inline int build_wgs_per_job(int n_jobs, int max_cells)
+{
+    // about 4 resident workgroups per CU on 256 CUs, all in one round
+    int per_job = 1024 / (n_jobs > 0 ? n_jobs : 1);
+    if (per_job > max_cells) per_job = max_cells;
+    return per_job < 1 ? 1 : per_job;
+}
+
 // Launch wrappers (defined in g3_kernels.hip).
 void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
 void launch_cell_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
 void launch_cell_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s);
 void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
-void launch_nbr_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
-void launch_nbr_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s);
-void launch_nbr_fill(const Sys* sys, const Job* jobs, int n_jobs, int max_n, bool wide, hipStream_t s);
-size_t nbr_sort_lds_bytes(int list_cap, bool wide);
-void launch_nbr_sort(const Sys* sys, const Job* jobs, int n_jobs, int max_n, int list_cap, bool wide,
-                     hipStream_t s);
+size_t nbr_build_lds_bytes(int stg_cap);
+void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int stg_cap, bool wide,
+                      bool one_step, hipStream_t s);
 void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
-hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t sort_bytes);
+hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes);
 
 }  // namespace g3

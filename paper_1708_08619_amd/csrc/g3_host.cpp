@@ -21,7 +21,8 @@ namespace {
 
 using namespace g3;
 
-constexpr int kListCap = 1024;       // neighbours per centre held by the sort and triplet kernels
+constexpr int kListCap = 1024;       // neighbours per centre held by the triplet kernel
+constexpr int kStageCap = 1024;      // stencil atoms staged in LDS by the neighbour build
 constexpr int kTabMax = 8192;        // bytes of the bin lookup table in LDS
 constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
 constexpr size_t kLdsPerCU = 160 * 1024;
@@ -312,7 +313,7 @@ struct Prepared {
     Geometry g;
     g3_system in;
     size_t off_cell_count, off_cell_start, off_atom_cell, off_atom_rank, off_sorted, off_nbr_off,
-        off_slab_j, off_pool, off_thr, off_tab;
+        off_nbr_cnt, off_cursor, off_slab_j, off_pool, off_thr, off_tab;
     int64_t pool_cap;
     int per_frame;
 };
@@ -342,6 +343,13 @@ g3_status prepare(const g3_system& s, int hb_max, Prepared& P)
 size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case, size_t base)
 {
     size_t o = base;
+    // unused tails of the per-wave pool chunks of the neighbour build
+    int n_jobs = 0, max_cells = 1;
+    for (auto& P : ps) {
+        n_jobs += per_frame ? std::max(P.in.n_frames, 1) : 1;
+        max_cells = std::max(max_cells, P.g.ncell);
+    }
+    const int64_t slack = (int64_t)build_wgs_per_job(n_jobs, max_cells) * kBuildWavesPerWG * kBuildChunk;
     for (auto& P : ps) {
         const Geometry& g = P.g;
         const size_t F = per_frame ? (size_t)std::max(P.in.n_frames, 1) : 1;
@@ -353,7 +361,9 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         P.off_atom_cell = o;  o = align_up(o + F * N * 4, 256);
         P.off_atom_rank = o;  o = align_up(o + F * N * 4, 256);
         P.off_sorted = o;     o = align_up(o + F * 3 * N * 4, 256);
-        P.off_nbr_off = o;    o = align_up(o + F * (N + 1) * 4, 256);
+        P.off_nbr_off = o;    o = align_up(o + F * N * 4, 256);
+        P.off_nbr_cnt = o;    o = align_up(o + F * N * 4, 256);
+        P.off_cursor = o;     o = align_up(o + (size_t)std::max(P.in.n_frames, 1) * kCursorStride * 4, 256);
         P.off_slab_j = o;     o = align_up(o + F * N * (S + 1) * 2, 256);
         P.off_thr = o;        o = align_up(o + (g.nbins + 1) * 4, 256);
         P.off_tab = o;        o = align_up(o + g.tab_len, 256);
@@ -363,10 +373,10 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
             const double V = (double)g.box[0] * g.box[1] * g.box[2];
             const double rc = (double)P.in.rmax;
             const double nexp = (double)g.N / V * 4.18879020478639 * rc * rc * rc;
-            int64_t cap = (int64_t)(N * (1.35 * std::min(nexp, (double)N) + 16.0)) + 4096;
-            P.pool_cap = std::min<int64_t>(cap, (int64_t)N * std::min<int64_t>(kListCap, N));
+            int64_t cap = (int64_t)(N * (1.35 * std::min(nexp, (double)N) + 16.0)) + 4096 + slack;
+            P.pool_cap = std::min<int64_t>(cap, (int64_t)N * std::min<int64_t>(kListCap, N) + slack);
         } else {
-            P.pool_cap = (int64_t)N * std::min<int64_t>(kListCap, std::max<int64_t>(N, 1));
+            P.pool_cap = (int64_t)N * std::min<int64_t>(kListCap, std::max<int64_t>(N, 1)) + slack;
         }
         P.off_pool = o;
         o = align_up(o + F * (size_t)P.pool_cap * (g.wide ? 16 : 8), 256);
@@ -404,6 +414,8 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
     s.atom_rank = reinterpret_cast<int32_t*>(arena + P.off_atom_rank);
     s.sorted = reinterpret_cast<int32_t*>(arena + P.off_sorted);
     s.nbr_off = reinterpret_cast<uint32_t*>(arena + P.off_nbr_off);
+    s.nbr_cnt = reinterpret_cast<uint32_t*>(arena + P.off_nbr_cnt);
+    s.cursor = reinterpret_cast<uint32_t*>(arena + P.off_cursor);
     s.slab_j = reinterpret_cast<uint16_t*>(arena + P.off_slab_j);
     s.pool = arena + P.off_pool;
     s.pool_cap = P.pool_cap;
@@ -563,7 +575,7 @@ g3_status upload_geometry(g3_plan p, const std::vector<Prepared>& ps)
 g3_status set_lds_limits(g3_plan p)
 {
     if (p->lds_set) return G3_OK;
-    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_sort_lds_bytes(kListCap, true)));
+    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_build_lds_bytes(kStageCap)));
     p->lds_set = true;
     return G3_OK;
 }
@@ -639,16 +651,14 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     a.n_segs = S;
     a.total_items = items_per_frame;
     const int N = P.g.N;
+    launch_zero_u32((uint32_t*)((char*)p->arena + P.off_cursor), (size_t)F * kCursorStride, p->stream);
     for (int f = 0; f < F; ++f) {
         const Job* j = djobs + f;
         launch_zero_u32((uint32_t*)((char*)p->arena + P.off_cell_count), (size_t)P.g.ncell, p->stream);
         launch_cell_count(dsys, j, 1, N, p->stream);
         launch_cell_scan(dsys, j, 1, p->stream);
         launch_cell_scatter(dsys, j, 1, N, p->stream);
-        launch_nbr_count(dsys, j, 1, N, p->stream);
-        launch_nbr_scan(dsys, j, 1, p->stream);
-        launch_nbr_fill(dsys, j, 1, N, P.g.wide != 0, p->stream);
-        launch_nbr_sort(dsys, j, 1, N, kListCap, P.g.wide != 0, p->stream);
+        launch_nbr_build(dsys, j, 1, P.g.ncell, kStageCap, P.g.wide != 0, P.g.one_step != 0, p->stream);
         launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
         a.segs = dsegs + (size_t)f * S;
         hipEvent_t e0;
@@ -707,6 +717,8 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             max_n = std::max(max_n, ps[k].g.N);
         }
         for (auto& s : segs) max_hb = std::max(max_hb, s.hb);
+        int max_cells = 0;
+        for (auto& P : ps) max_cells = std::max(max_cells, P.g.ncell);
         bool one_step = true;
         for (auto& P : ps) one_step = one_step && P.g.one_step;
         const int n_wg = p->n_cu * tn.wg_per_cu;
@@ -734,7 +746,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         put(&one_step, sizeof(one_step));
         put(&tn, sizeof(tn));
         int nj = (int)jobs.size(), ns = (int)segs.size();
-        put(&nj, 4); put(&ns, 4); put(&items, 4); put(&max_n, 4); put(&max_hb, 4);
+        put(&nj, 4); put(&ns, 4); put(&items, 4); put(&max_n, 4); put(&max_hb, 4); put(&max_cells, 4);
         put(&p->arena, sizeof(void*)); put(&p->tables, sizeof(void*)); put(&p->slots, sizeof(void*));
         put(&p->flag_log, sizeof(void*));
         size_t arena_used = need;
@@ -759,9 +771,11 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         a.cand = p->cand;
         // cell-count zeroing covers the group's whole scratch prefix of counts
         std::vector<std::pair<uint32_t*, size_t>> zero;
-        for (auto& P : ps)
+        for (auto& P : ps) {
             zero.push_back({(uint32_t*)((char*)p->arena + P.off_cell_count),
                             (size_t)P.g.ncell * (size_t)P.in.n_frames});
+            zero.push_back({(uint32_t*)((char*)p->arena + P.off_cursor), (size_t)P.in.n_frames * kCursorStride});
+        }
 
         auto enqueue = [&](hipStream_t sm) {
             for (auto& z : zero) launch_zero_u32(z.first, z.second, sm);
@@ -769,10 +783,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_count(dsys, djobs, nj, max_n, sm);
             launch_cell_scan(dsys, djobs, nj, sm);
             launch_cell_scatter(dsys, djobs, nj, max_n, sm);
-            launch_nbr_count(dsys, djobs, nj, max_n, sm);
-            launch_nbr_scan(dsys, djobs, nj, sm);
-            launch_nbr_fill(dsys, djobs, nj, max_n, wide, sm);
-            launch_nbr_sort(dsys, djobs, nj, max_n, kListCap, wide, sm);
+            launch_nbr_build(dsys, djobs, nj, max_cells, kStageCap, wide, one_step, sm);
             launch_triplet(a, wide, one_step, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
         };
@@ -783,10 +794,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_count(dsys, djobs, nj, max_n, p->stream);
             launch_cell_scan(dsys, djobs, nj, p->stream);
             launch_cell_scatter(dsys, djobs, nj, max_n, p->stream);
-            launch_nbr_count(dsys, djobs, nj, max_n, p->stream);
-            launch_nbr_scan(dsys, djobs, nj, p->stream);
-            launch_nbr_fill(dsys, djobs, nj, max_n, wide, p->stream);
-            launch_nbr_sort(dsys, djobs, nj, max_n, kListCap, wide, p->stream);
+            launch_nbr_build(dsys, djobs, nj, max_cells, kStageCap, wide, one_step, p->stream);
             hipEvent_t e0;
             timing_begin(p, &e0);
             launch_triplet(a, wide, one_step, n_wg, p->stream);

@@ -3,8 +3,7 @@
 // Pipeline per frame (Sec. 3.3; the paper's parallel g3 logic computes pair
 // vectors first and then the triplets of each centre from them):
 //   cell_count -> cell_scan -> cell_scatter      counting-sort cell build
-//   nbr_count  -> nbr_scan  -> nbr_fill -> nbr_sort
-//                                                minimum-image neighbour
+//   nbr_build                                    minimum-image neighbour
 //                                                vectors of every centre,
 //                                                sorted by their pair bin
 //   triplet (persistent) -> reduce               LDS-privatised r12 slabs,
@@ -35,15 +34,6 @@ __device__ __forceinline__ int min_image(int d, int L)
     if (2 * (int64_t)d > L) return d - L;
     if (2 * (int64_t)d < -(int64_t)L) return d + L;
     return d;
-}
-
-// b(s) = max{b : thr[b] <= s} for s < thr[nbins]; the table gives a lower
-// bound and at most a few steps up finish it.
-__device__ __forceinline__ int bin_lookup(uint32_t s, const uint8_t* tab, const uint32_t* thr, int sh)
-{
-    int b = tab[s >> sh];
-    while (s >= thr[b + 1]) ++b;
-    return b;
 }
 
 // Exclusive scan over a 1024-thread block.  tmp needs 17 words.
@@ -152,188 +142,284 @@ __global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sy
 }
 
 // ------------------------------------------------------------------ neighbours
-// Visit every atom j != i within rmax of centre i (cell-sorted index) through
-// the 27-cell stencil.  With nc >= 3 on an axis the periodic shift of each
-// stencil cell is the minimum image (cell side >= rmax); with nc == 1 the
-// component gets an explicit minimum image.  Components are tested against
-// C before squaring, then s = dx^2 + dy^2 (+ dz^2 only if still below R2),
-// so no uint32 sum overflows for C <= 46340.
-template <typename F>
-__device__ __forceinline__ void visit_neighbours(const Sys& S, const int32_t* __restrict__ X,
-                                                 const int32_t* __restrict__ Y,
-                                                 const int32_t* __restrict__ Z,
-                                                 const int32_t* __restrict__ cs, int i, F&& emit)
+// Workgroups loop over the cells of a frame.  The 27-cell stencil of the home
+// cell is flattened into one list of candidate atoms whose coordinates carry
+// the periodic shift of their stencil cell: with >= 3 cells on an axis and a
+// cell side of at least C - 1 units that shift is the minimum image of every
+// pair closer than rmax; an axis with a single cell gets an explicit minimum
+// image.  The list is staged in LDS when it fits (else read from the
+// cell-sorted arrays in global memory).  Each wave takes one centre:
+//   one pass over the candidates accepts |d|^2 < R2, bins it, counts it per
+//   r12 slab and compacts it into a per-wave LDS buffer (ballot + mbcnt);
+//   one atomic on the frame's pool cursor reserves the list;
+//   the slab counts are scanned into the boundaries J_q and every neighbour
+//   is written at J_{slab(b)} + its rank in the slab: the list comes out
+//   partitioned by slab, which is all the triplet kernel needs.
+// A centre with more neighbours than the buffer re-evaluates its candidates
+// for the write.  Components are tested against C before squaring, then
+// s = dx^2 + dy^2 (+ dz^2 only if still below R2): exact in uint32 for
+// C <= 46340, products on the 24-bit multiplier (|d| < 2^16).
+namespace {
+
+struct Stencil {
+    int n;                 // stencil cells
+    int start[27], pre[28];
+    int shx[27], shy[27], shz[27];
+};
+
+// Orders the LDS traffic of one wave (lanes exchange data through LDS);
+// global memory is not waited for.
+__device__ __forceinline__ void wave_sync()
 {
-    const int xi = X[i], yi = Y[i], zi = Z[i];
-    const int ncx = S.nc[0], ncy = S.nc[1], ncz = S.nc[2];
-    const int Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
-    const int cx = cell_of(xi, ncx, Lx), cy = cell_of(yi, ncy, Ly), cz = cell_of(zi, ncz, Lz);
-    const int rx = ncx >= 3 ? 1 : 0, ry = ncy >= 3 ? 1 : 0, rz = ncz >= 3 ? 1 : 0;
-    const uint32_t cm1 = (uint32_t)(S.C - 1), span = 2u * cm1;
-    const uint32_t R2 = S.R2;
-    for (int oz = -rz; oz <= rz; ++oz) {
-        int kz = cz + oz, shz = 0;
-        if (kz < 0) { kz += ncz; shz = -Lz; } else if (kz >= ncz) { kz -= ncz; shz = Lz; }
-        for (int oy = -ry; oy <= ry; ++oy) {
-            int ky = cy + oy, shy = 0;
-            if (ky < 0) { ky += ncy; shy = -Ly; } else if (ky >= ncy) { ky -= ncy; shy = Ly; }
-            for (int ox = -rx; ox <= rx; ++ox) {
-                int kx = cx + ox, shx = 0;
-                if (kx < 0) { kx += ncx; shx = -Lx; } else if (kx >= ncx) { kx -= ncx; shx = Lx; }
-                const int cell = (kz * ncy + ky) * ncx + kx;
-                const int j0 = cs[cell], j1 = cs[cell + 1];
-                for (int j = j0; j < j1; ++j) {
-                    if (j == i) continue;
-                    int dx = X[j] + shx - xi, dy = Y[j] + shy - yi, dz = Z[j] + shz - zi;
-                    if (ncx == 1) dx = min_image(dx, Lx);
-                    if (ncy == 1) dy = min_image(dy, Ly);
-                    if (ncz == 1) dz = min_image(dz, Lz);
-                    if ((uint32_t)(dx + (int)cm1) > span || (uint32_t)(dy + (int)cm1) > span ||
-                        (uint32_t)(dz + (int)cm1) > span)
-                        continue;
-                    const uint32_t s2 = (uint32_t)(dx * dx) + (uint32_t)(dy * dy);
-                    if (s2 >= R2) continue;
-                    const uint32_t s = s2 + (uint32_t)(dz * dz);
-                    if (s >= R2) continue;
-                    emit(dx, dy, dz, s);
-                }
-            }
-        }
-    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
 }
 
-__global__ void __launch_bounds__(256) k_nbr_count(const Sys* __restrict__ sys,
-                                                   const Job* __restrict__ jobs)
+template <bool ONE_STEP>
+__device__ __forceinline__ int bin_of(uint32_t s, const uint8_t* tab, const uint32_t* thr, int sh)
 {
-    const Job jb = jobs[blockIdx.y];
-    const Sys& S = sys[jb.sys];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int N = S.N, f = jb.frame;
-    if (i >= N || (S.flags[f] & kFlagDomain)) return;
-    const int32_t* X = S.sorted + fr_off(S, f, (size_t)3 * N);
-    const int32_t* cs = S.cell_start + fr_off(S, f, S.ncell + 1);
-    uint32_t n = 0;
-    visit_neighbours(S, X, X + N, X + 2 * N, cs, i, [&](int, int, int, uint32_t) { ++n; });
-    S.nbr_off[fr_off(S, f, N + 1) + i] = n;
-    if (n > (uint32_t)S.list_cap) atomicOr(&S.flags[f], kFlagList);
-}
-
-// In-place exclusive scan of the neighbour counts; flags a pool overflow.
-__global__ void __launch_bounds__(1024) k_nbr_scan(const Sys* __restrict__ sys,
-                                                   const Job* __restrict__ jobs)
-{
-    __shared__ uint32_t tmp[17];
-    const Job jb = jobs[blockIdx.x];
-    const Sys& S = sys[jb.sys];
-    const int f = jb.frame, N = S.N;
-    if (S.flags[f] & kFlagDomain) return;
-    uint32_t* off = S.nbr_off + fr_off(S, f, N + 1);
-    uint32_t carry = 0;
-    for (int base = 0; base < N; base += 1024) {
-        const int i = base + threadIdx.x;
-        const uint32_t v = i < N ? off[i] : 0u;
-        uint32_t tot;
-        const uint32_t pre = block_excl_scan(v, tmp, &tot);
-        if (i < N) off[i] = carry + pre;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        off[N] = carry;
-        if ((int64_t)carry > S.pool_cap) atomicOr(&S.flags[f], kFlagPool);
-    }
-}
-
-template <bool WIDE>
-__global__ void __launch_bounds__(256) k_nbr_fill(const Sys* __restrict__ sys,
-                                                  const Job* __restrict__ jobs)
-{
-    const Job jb = jobs[blockIdx.y];
-    const Sys& S = sys[jb.sys];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int N = S.N, f = jb.frame;
-    if (i >= N || S.flags[f]) return;
-    const int32_t* X = S.sorted + fr_off(S, f, (size_t)3 * N);
-    const int32_t* cs = S.cell_start + fr_off(S, f, S.ncell + 1);
-    const uint32_t o = S.nbr_off[fr_off(S, f, N + 1) + i];
-    const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
-    const uint8_t* tab = S.tab;
-    const uint32_t* thr = S.thr;
-    const int sh = S.sh;
-    uint32_t n = 0;
-    if (WIDE) {
-        int4* P = reinterpret_cast<int4*>(S.pool) + pbase + o;
-        visit_neighbours(S, X, X + N, X + 2 * N, cs, i, [&](int dx, int dy, int dz, uint32_t s) {
-            P[n++] = make_int4(dx, dy, dz, bin_lookup(s, tab, thr, sh));
-        });
+    int b = tab[s >> sh];
+    if (ONE_STEP) {
+        b += (s >= thr[b + 1]) ? 1 : 0;
     } else {
-        uint2* P = reinterpret_cast<uint2*>(S.pool) + pbase + o;
-        visit_neighbours(S, X, X + N, X + 2 * N, cs, i, [&](int dx, int dy, int dz, uint32_t s) {
-            const uint32_t b = (uint32_t)bin_lookup(s, tab, thr, sh);
-            P[n++] = make_uint2(((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16),
-                                ((uint32_t)dz & 0xffffu) | (b << 16));
-        });
+        while (s >= thr[b + 1]) ++b;
     }
+    return b;
 }
 
-// Counting sort of each centre's entries by pair bin (one wave per centre,
-// four centres per block), and the slab row boundaries J_q of each centre.
-template <bool WIDE>
-__global__ void __launch_bounds__(256) k_nbr_sort(const Sys* __restrict__ sys,
-                                                  const Job* __restrict__ jobs)
+}  // namespace
+
+constexpr int kBuildThreads = 256;
+constexpr int kBuildWaves = kBuildWavesPerWG;
+static_assert(kBuildThreads == 64 * kBuildWavesPerWG, "build workgroup shape");
+constexpr int kWaveBuf = 256;      // neighbours buffered per wave before the write
+constexpr uint32_t kChunk = kBuildChunk;
+
+template <bool WIDE, bool ONE_STEP>
+__global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restrict__ sys,
+                                                             const Job* __restrict__ jobs, int stg_cap)
 {
     using E = typename std::conditional<WIDE, int4, uint2>::type;
     extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                    // [256]
+    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + 256);               // [8192]
+    uint8_t* s_slab = s_tab + 8192;                                          // [256] bin -> slab
+    E* s_buf = reinterpret_cast<E*>(s_slab + 256);                           // [waves][kWaveBuf]
+    uint32_t* s_scnt = reinterpret_cast<uint32_t*>(s_buf + kBuildWaves * kWaveBuf);  // [waves][32]
+    int32_t* s_x = reinterpret_cast<int32_t*>(s_scnt + kBuildWaves * 32);
+    int32_t* s_y = s_x + stg_cap;
+    int32_t* s_z = s_y + stg_cap;
+    __shared__ Stencil st;
+
     const Job jb = jobs[blockIdx.y];
     const Sys& S = sys[jb.sys];
-    const int N = S.N, f = jb.frame;
-    if (S.flags[f]) return;  // uniform over the block
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int cap = S.list_cap;
-    E* buf = reinterpret_cast<E*>(smem) + (size_t)w * cap;
-    uint32_t* cnt = reinterpret_cast<uint32_t*>(reinterpret_cast<E*>(smem) + 4 * (size_t)cap) + w * 256;
-    uint16_t* rnk = reinterpret_cast<uint16_t*>(reinterpret_cast<uint32_t*>(
-                        reinterpret_cast<E*>(smem) + 4 * (size_t)cap) + 4 * 256) + (size_t)w * cap;
-    const int i = blockIdx.x * 4 + w;
-    const bool live = i < N;
-    const uint32_t* off = S.nbr_off + fr_off(S, f, N + 1);
-    const uint32_t o = live ? off[i] : 0u;
-    const int n = live ? (int)(off[i + 1] - o) : 0;
-    const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
-    E* P = reinterpret_cast<E*>(S.pool) + pbase + o;
-    for (int b = lane; b < 256; b += 64) cnt[b] = 0;
-    __syncthreads();
-    for (int e = lane; e < n; e += 64) {
-        const E v = P[e];
-        buf[e] = v;
-        const int b = WIDE ? (int)((const int*)&v)[3] : (int)(((const uint32_t*)&v)[1] >> 16);
-        rnk[e] = (uint16_t)atomicAdd(&cnt[b], 1u);
+    const int f = jb.frame, N = S.N;
+    if (S.flags[f] & kFlagDomain) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ncx = S.nc[0], ncy = S.nc[1], ncz = S.nc[2], ncell = S.ncell;
+    const int Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
+    const int32_t* cs = S.cell_start + fr_off(S, f, ncell + 1);
+    const int32_t* X = S.sorted + fr_off(S, f, (size_t)3 * N);
+    const int32_t* Y = X + N;
+    const int32_t* Z = Y + N;
+    const int cm1 = S.C - 1;
+    const uint32_t span = 2u * (uint32_t)cm1;
+    const uint32_t R2 = S.R2;
+    const int sh = S.sh, nb = S.nbins, n_slabs = S.n_slabs, list_cap = S.list_cap;
+    const int64_t pool_cap = S.pool_cap;
+    uint32_t* scnt = s_scnt + wave * 32;
+    E* buf = s_buf + wave * kWaveBuf;
+    uint32_t* flags = S.flags + f;
+    uint32_t* cursor = S.cursor + (size_t)f * kCursorStride;
+    uint32_t chunk_base = 0, chunk_left = 0;   // this wave's slice of the pool
+    uint32_t* nbr_off = S.nbr_off + fr_off(S, f, N);
+    uint32_t* nbr_cnt = S.nbr_cnt + fr_off(S, f, N);
+    uint16_t* slab_j = S.slab_j + fr_off(S, f, (size_t)N * (n_slabs + 1));
+    const size_t pbase = S.per_frame ? (size_t)f * (size_t)pool_cap : 0;
+    E* pool = reinterpret_cast<E*>(S.pool) + pbase;
+
+    // bin tables and the bin -> slab map, once per workgroup
+    for (int x = tid; x <= nb; x += kBuildThreads) s_thr[x] = S.thr[x];
+    {
+        const int n16 = (S.tab_len + 15) / 16;
+        const uint4* src = reinterpret_cast<const uint4*>(S.tab);
+        for (int x = tid; x < n16; x += kBuildThreads) reinterpret_cast<uint4*>(s_tab)[x] = src[x];
     }
-    __syncthreads();
-    // exclusive scan of cnt[0..255] within the wave: lane owns bins 4l..4l+3
-    uint32_t c0 = cnt[4 * lane], c1 = cnt[4 * lane + 1], c2 = cnt[4 * lane + 2], c3 = cnt[4 * lane + 3];
-    uint32_t sum = c0 + c1 + c2 + c3, x = sum;
+    for (int b = tid; b < 256; b += kBuildThreads) {
+        int q = 0;
+        while (q + 1 < n_slabs && S.slab_lo[q + 1] <= b) ++q;
+        s_slab[b] = (uint8_t)q;
+    }
+    const int rx = ncx >= 3 ? 1 : 0, ry = ncy >= 3 ? 1 : 0, rz = ncz >= 3 ? 1 : 0;
+    const int nst = (2 * rx + 1) * (2 * ry + 1) * (2 * rz + 1);
+    const int home = nst / 2;   // (0,0,0) sits in the middle of the odd stencil grid
+
+    for (int cell = blockIdx.x; cell < ncell; cell += gridDim.x) {
+        const int c0 = cs[cell], c1 = cs[cell + 1];
+        if (c0 == c1) continue;   // uniform over the workgroup
+        // stencil table: lane e of wave 0 fills entry e, then a prefix sum
+        if (wave == 0) {
+            int cnt_e = 0;
+            if (lane < nst) {
+                const int kx = cell % ncx, ky = (cell / ncx) % ncy, kz = cell / (ncx * ncy);
+                const int ox = lane % (2 * rx + 1) - rx;
+                const int oy = (lane / (2 * rx + 1)) % (2 * ry + 1) - ry;
+                const int oz = lane / ((2 * rx + 1) * (2 * ry + 1)) - rz;
+                int x = kx + ox, y = ky + oy, z = kz + oz, shx = 0, shy = 0, shz = 0;
+                if (x < 0) { x += ncx; shx = -Lx; } else if (x >= ncx) { x -= ncx; shx = Lx; }
+                if (y < 0) { y += ncy; shy = -Ly; } else if (y >= ncy) { y -= ncy; shy = Ly; }
+                if (z < 0) { z += ncz; shz = -Lz; } else if (z >= ncz) { z -= ncz; shz = Lz; }
+                const int c = (z * ncy + y) * ncx + x;
+                const int a = cs[c];
+                cnt_e = cs[c + 1] - a;
+                st.start[lane] = a;
+                st.shx[lane] = shx; st.shy[lane] = shy; st.shz[lane] = shz;
+            }
+            int incl = cnt_e;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(x, d, 64);
-        if (lane >= d) x += t;
-    }
-    uint32_t pre = x - sum;
-    __syncthreads();
-    cnt[4 * lane] = pre;
-    cnt[4 * lane + 1] = pre + c0;
-    cnt[4 * lane + 2] = pre + c0 + c1;
-    cnt[4 * lane + 3] = pre + c0 + c1 + c2;
-    __syncthreads();
-    for (int e = lane; e < n; e += 64) {
-        const E v = buf[e];
-        const int b = WIDE ? (int)((const int*)&v)[3] : (int)(((const uint32_t*)&v)[1] >> 16);
-        P[cnt[b] + rnk[e]] = v;
-    }
-    if (live && lane <= S.n_slabs) {
-        const int lo = S.slab_lo[lane];
-        const uint32_t J = lo >= S.nbins ? (uint32_t)n : cnt[lo];
-        S.slab_j[fr_off(S, f, (size_t)N * (S.n_slabs + 1)) + (size_t)i * (S.n_slabs + 1) + lane] =
-            (uint16_t)J;
+            for (int d = 1; d < 32; d <<= 1) {
+                const int y = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += y;
+            }
+            if (lane < nst) st.pre[lane] = incl - cnt_e;
+            if (lane == nst - 1) { st.pre[nst] = incl; st.n = nst; }
+        }
+        __syncthreads();
+        const int T = st.pre[nst];
+        const bool staged = T <= stg_cap;
+        auto cell_of_t = [&](int t) {
+            int r = 0;
+            while (st.pre[r + 1] <= t) ++r;
+            return r;
+        };
+        if (staged) {
+            for (int t = tid; t < T; t += kBuildThreads) {
+                const int r = cell_of_t(t);
+                const int j = st.start[r] + (t - st.pre[r]);
+                s_x[t] = X[j] + st.shx[r];
+                s_y[t] = Y[j] + st.shy[r];
+                s_z[t] = Z[j] + st.shz[r];
+            }
+        }
+        __syncthreads();
+
+        for (int ci = c0 + wave; ci < c1; ci += kBuildWaves) {
+            // the centre is part of its own stencil (home cell, no shift)
+            const int tself = st.pre[home] + (ci - st.start[home]);
+            const int xi = staged ? s_x[tself] : X[ci];
+            const int yi = staged ? s_y[tself] : Y[ci];
+            const int zi = staged ? s_z[tself] : Z[ci];
+            // candidate t: accepted -> true with the entry and its bin
+            auto test = [&](int t, E& e, int& b) -> bool {
+                if (t >= T || t == tself) return false;
+                int x, y, z;
+                if (staged) {
+                    x = s_x[t]; y = s_y[t]; z = s_z[t];
+                } else {
+                    const int r = cell_of_t(t);
+                    const int j = st.start[r] + (t - st.pre[r]);
+                    x = X[j] + st.shx[r]; y = Y[j] + st.shy[r]; z = Z[j] + st.shz[r];
+                }
+                int dx = x - xi, dy = y - yi, dz = z - zi;
+                if (ncx == 1) dx = min_image(dx, Lx);
+                if (ncy == 1) dy = min_image(dy, Ly);
+                if (ncz == 1) dz = min_image(dz, Lz);
+                if ((uint32_t)(dx + cm1) > span || (uint32_t)(dy + cm1) > span ||
+                    (uint32_t)(dz + cm1) > span)
+                    return false;
+                const uint32_t s2 = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy);
+                if (s2 >= R2) return false;
+                const uint32_t s = s2 + (uint32_t)__mul24(dz, dz);
+                if (s >= R2) return false;
+                b = bin_of<ONE_STEP>(s, s_tab, s_thr, sh);
+                if constexpr (WIDE) {
+                    e = make_int4(dx, dy, dz, b);
+                } else {
+                    e = make_uint2(((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16),
+                                   ((uint32_t)dz & 0xffffu) | ((uint32_t)b << 16));
+                }
+                return true;
+            };
+            auto bin_of_entry = [&](const E& e) -> int {
+                if constexpr (WIDE) return e.w;
+                else return (int)(e.y >> 16);
+            };
+            if (lane < 32) scnt[lane] = 0u;
+            wave_sync();
+            // the one evaluation pass: count per slab, compact into the buffer
+            uint32_t n = 0;
+            for (int t0 = 0; t0 < T; t0 += 64) {
+                E e;
+                int b = 0;
+                const bool acc = test(t0 + lane, e, b);
+                const uint64_t mask = __ballot(acc);
+                if (acc) {
+                    const uint32_t pos = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    if (pos < (uint32_t)kWaveBuf) buf[pos] = e;
+                    atomicAdd(&scnt[s_slab[b]], 1u);
+                }
+                n += (uint32_t)__popcll(mask);
+            }
+            wave_sync();
+            if (n > (uint32_t)list_cap) {
+                if (lane == 0) {
+                    atomicOr(flags, kFlagList);
+                    nbr_off[ci] = 0u;
+                    nbr_cnt[ci] = 0u;
+                }
+                continue;
+            }
+            // bump-allocate from the wave's chunk; one global atomic per chunk
+            if (n > chunk_left) {
+                const uint32_t want = n > kChunk ? n : kChunk;
+                uint32_t got = 0;
+                if (lane == 0) got = atomicAdd(cursor, want);
+                chunk_base = __shfl(got, 0, 64);
+                chunk_left = want;
+            }
+            const uint32_t base = chunk_base;
+            chunk_base += n;
+            chunk_left -= n;
+            if ((int64_t)base + n > pool_cap) {
+                if (lane == 0) atomicOr(flags, kFlagPool);
+                continue;
+            }
+            // slab boundaries J_q (exclusive scan of the slab counts)
+            {
+                const uint32_t v = lane < n_slabs ? scnt[lane] : 0u;
+                uint32_t x = v;
+#pragma unroll
+                for (int d = 1; d < 32; d <<= 1) {
+                    const uint32_t y = __shfl_up(x, d, 64);
+                    if (lane >= d) x += y;
+                }
+                const uint32_t J = x - v;       // lane n_slabs gets the total n
+                if (lane <= n_slabs) slab_j[(size_t)ci * (n_slabs + 1) + lane] = (uint16_t)J;
+                wave_sync();
+                if (lane < n_slabs) scnt[lane] = J;
+                wave_sync();
+            }
+            E* P = pool + base;
+            if (n <= (uint32_t)kWaveBuf) {
+                for (uint32_t e = lane; e < n; e += 64) {
+                    const E v = buf[e];
+                    P[atomicAdd(&scnt[s_slab[bin_of_entry(v)]], 1u)] = v;
+                }
+            } else {
+                for (int t0 = 0; t0 < T; t0 += 64) {
+                    E e;
+                    int b = 0;
+                    if (test(t0 + lane, e, b)) P[atomicAdd(&scnt[s_slab[b]], 1u)] = e;
+                }
+            }
+            if (lane == 0) {
+                nbr_off[ci] = base;
+                nbr_cnt[ci] = n;
+            }
+            wave_sync();
+        }
+        __syncthreads();   // the next cell restages s_x/s_y/s_z and st
     }
 }
 
@@ -394,8 +480,8 @@ struct Ent<true> {
         const uint32_t span = 2u * (uint32_t)cm1;
         if ((uint32_t)(dx + cm1) > span || (uint32_t)(dy + cm1) > span || (uint32_t)(dz + cm1) > span)
             return 0xffffffffu;
-        const uint32_t s2 = (uint32_t)(dx * dx) + (uint32_t)(dy * dy);
-        const uint32_t s = s2 + (uint32_t)(dz * dz);
+        const uint32_t s2 = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy);
+        const uint32_t s = s2 + (uint32_t)__mul24(dz, dz);
         return s < s2 ? 0xffffffffu : s;   // s < s2 only if adding dz^2 wrapped
     }
     static __device__ __forceinline__ int col(T v) { return v.w; }
@@ -511,7 +597,8 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const int N = S.N, q = G.slab, nb = S.nbins, lo0 = G.lo0;
         const int c_begin = blk * A.cb;
         const int nctr = min(A.cb, N - c_begin);
-        const uint32_t* off = S.nbr_off + (S.per_frame ? (size_t)f * (N + 1) : 0);
+        const uint32_t* off = S.nbr_off + (S.per_frame ? (size_t)f * N : 0);
+        const uint32_t* cnt = S.nbr_cnt + (S.per_frame ? (size_t)f * N : 0);
         const uint16_t* J = S.slab_j + (S.per_frame ? (size_t)f * N * (S.n_slabs + 1) : 0);
         const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
         const E* P = reinterpret_cast<const E*>(S.pool) + pbase;
@@ -520,7 +607,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         uint32_t m = 0, r = 0;
         if (tid < nctr) {
             const int i = c_begin + tid;
-            const uint32_t o = off[i], n = off[i + 1] - o;
+            const uint32_t o = off[i], n = cnt[i];
             const uint32_t j0 = J[(size_t)i * (S.n_slabs + 1) + q];
             const uint32_t j1 = J[(size_t)i * (S.n_slabs + 1) + q + 1];
             r = j1 - j0;
@@ -722,40 +809,29 @@ void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n,
     hipLaunchKernelGGL(k_cell_scatter, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
 }
 
-void launch_nbr_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s)
+size_t nbr_build_lds_bytes(int stg_cap)
 {
-    hipLaunchKernelGGL(k_nbr_count, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
+    return 256 * 4 + 8192 + 256 + (size_t)kBuildWaves * kWaveBuf * 16 + kBuildWaves * 32 * 4 +
+           (size_t)3 * stg_cap * 4;
 }
 
-void launch_nbr_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s)
+void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int stg_cap, bool wide,
+                      bool one_step, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_nbr_scan, dim3(n_jobs), dim3(1024), 0, s, sys, jobs);
+    // enough workgroups per frame to fill the chip, each looping over cells
+    const int per_job = build_wgs_per_job(n_jobs, max_cells);
+    const size_t lds = nbr_build_lds_bytes(stg_cap);
+    const dim3 g(per_job, n_jobs), b(kBuildThreads);
+    if (wide) {
+        if (one_step) hipLaunchKernelGGL((k_nbr_build<true, true>), g, b, lds, s, sys, jobs, stg_cap);
+        else hipLaunchKernelGGL((k_nbr_build<true, false>), g, b, lds, s, sys, jobs, stg_cap);
+    } else {
+        if (one_step) hipLaunchKernelGGL((k_nbr_build<false, true>), g, b, lds, s, sys, jobs, stg_cap);
+        else hipLaunchKernelGGL((k_nbr_build<false, false>), g, b, lds, s, sys, jobs, stg_cap);
+    }
 }
 
-void launch_nbr_fill(const Sys* sys, const Job* jobs, int n_jobs, int max_n, bool wide, hipStream_t s)
-{
-    if (wide)
-        hipLaunchKernelGGL(k_nbr_fill<true>, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
-    else
-        hipLaunchKernelGGL(k_nbr_fill<false>, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
-}
-
-size_t nbr_sort_lds_bytes(int list_cap, bool wide)
-{
-    return (size_t)4 * list_cap * (wide ? 16 : 8) + 4 * 256 * 4 + (size_t)4 * list_cap * 2;
-}
-
-void launch_nbr_sort(const Sys* sys, const Job* jobs, int n_jobs, int max_n, int list_cap, bool wide,
-                     hipStream_t s)
-{
-    const size_t lds = nbr_sort_lds_bytes(list_cap, wide);
-    if (wide)
-        hipLaunchKernelGGL(k_nbr_sort<true>, dim3((max_n + 3) / 4, n_jobs), dim3(256), lds, s, sys, jobs);
-    else
-        hipLaunchKernelGGL(k_nbr_sort<false>, dim3((max_n + 3) / 4, n_jobs), dim3(256), lds, s, sys, jobs);
-}
-
-hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t sort_bytes)
+hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
 {
     const void* trip[4] = {(const void*)k_triplet<false, false>, (const void*)k_triplet<false, true>,
                            (const void*)k_triplet<true, false>, (const void*)k_triplet<true, true>};
@@ -763,11 +839,12 @@ hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t sort_bytes)
     for (const void* k : trip)
         if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)triplet_bytes)))
             return e;
-    if ((e = hipFuncSetAttribute((const void*)k_nbr_sort<false>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes)))
-        return e;
-    return hipFuncSetAttribute((const void*)k_nbr_sort<true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_bytes);
+    const void* build[4] = {(const void*)k_nbr_build<false, false>, (const void*)k_nbr_build<false, true>,
+                            (const void*)k_nbr_build<true, false>, (const void*)k_nbr_build<true, true>};
+    for (const void* k : build)
+        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)build_bytes)))
+            return e;
+    return hipSuccess;
 }
 
 void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s)
