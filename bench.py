@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-centres", type=int, default=16384)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -69,6 +71,13 @@ def main():
     system = dict(frames=frames, box=w.box, rmax=w.rmax, nbins=w.nbins, layout=w.layout,
                   hist=hist)
     plan = g3.Plan()
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # triplets binned per step = total of the half histogram of one pass
     plan.accumulate_batch([system])

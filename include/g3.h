@@ -144,11 +144,16 @@ g3_status g3_ideal_volume(int32_t nbins, double rmax, double* W_out);
 g3_status g3_set_tuning(g3_plan p, const g3_tuning* t);
 g3_status g3_get_tuning(g3_plan p, g3_tuning* t);
 
-/* Autotuner: time the batched form on the given systems (which must be
- * valid; their histograms are used as scratch and restored to zero-added
- * state is NOT guaranteed -- pass scratch histograms) over a built-in grid of
- * tunings, keep the fastest in the plan and return it in *best (may be NULL).
- * Results never depend on the tuning; only time does. */
+/* Autotuner (the batched form's tile and slab choice): runs the batched form
+ * on the given systems into internal scratch histograms (the systems' hist
+ * pointers are ignored and never written) over a grid of tunings -- resident
+ * workgroups per CU, centres per work item, LDS histogram size (which sets
+ * the r12 slab boundaries) -- checks that every tuning yields the identical
+ * histogram (G3_EDEVICE if not), keeps the fastest in the plan, caches it
+ * under a signature of the workload (entry format, nbins, layout, N and
+ * neighbour-count buckets, frames) and returns it in *best (may be NULL).
+ * A repeated call with the same signature returns the cached tuning at once.
+ * Synchronises the plan's stream. */
 g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems,
                       g3_tuning* best);
 

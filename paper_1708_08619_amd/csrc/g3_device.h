@@ -11,6 +11,7 @@ namespace g3 {
 
 constexpr int kMaxSlabs = 24;          // r12 slabs per system
 constexpr int kTripletThreads = 1024;  // threads of the triplet workgroup
+constexpr int kTabBytes = 8192;        // LDS bytes of the bin lookup table
 constexpr int kWave = 64;
 constexpr int kCursorStride = 32;   // uint32 words between per-frame pool cursors (one 128 B line each)
 
@@ -19,10 +20,9 @@ constexpr uint32_t kFlagDomain = 1u;   // coordinate outside [0, L)
 constexpr uint32_t kFlagPool = 2u;     // neighbour lists exceed the frame's pool slot
 constexpr uint32_t kFlagList = 4u;     // one centre exceeds the per-centre capacity
 
-// Neighbour entry as stored in HBM and LDS.
-//  narrow (C <= 32767): x = (dx & 0xffff) | dy << 16, y = (dz & 0xffff) | v << 16
-//                       with v = bin b in HBM and v = b * nbins in LDS
-//  wide:                int4 {dx, dy, dz, v}
+// Neighbour entry (minimum-image vector d_ij and its pair bin b):
+//  narrow (C <= 32767): x = (dx & 0xffff) | dy << 16, y = (dz & 0xffff) | (b * nbins) << 16
+//  wide:                int4 {dx, dy, dz, b * nbins}
 struct Sys {
     // inputs
     const int32_t* frames;   // [F][3][N]
@@ -102,9 +102,9 @@ struct TripletArgs {
 // LDS bytes used by the triplet kernel for a configuration.
 inline size_t triplet_lds_bytes(int hb_max, int ec, int cb, int tb_max, bool wide)
 {
-    size_t b = (size_t)hb_max * 4 + 256 * 4 + (size_t)tb_max + (size_t)ec * (wide ? 16 : 8) +
-               (size_t)(3 * cb + 2) * 4;
-    return b;
+    (void)ec;
+    (void)wide;
+    return 256 * 4 + (size_t)tb_max + (size_t)hb_max * 4 + (size_t)(3 * cb + 1) * 4;
 }
 
 // Neighbour build launch shape: workgroups per frame (each loops over cells),

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "g3_device.h"
@@ -223,6 +224,7 @@ struct g3_plan_s {
     int device = 0;
     int n_cu = 256;
     g3_tuning tun{};        // requested (0 = default)
+    std::map<std::string, g3_tuning> tuned;   // autotuner results by workload signature
     g3_status sticky = G3_OK;
     hipError_t last_hip = hipSuccess;
 
@@ -297,7 +299,7 @@ Tun effective(const g3_plan p, bool wide)
     Tun t;
     t.ec = p->tun.lds_entries > 0 ? p->tun.lds_entries : (wide ? 2048 : 4096);
     t.ec = std::max(t.ec, kListCap);
-    t.cb = p->tun.centres_per_item > 0 ? std::min(p->tun.centres_per_item, kTripletThreads) : 256;
+    t.cb = p->tun.centres_per_item > 0 ? std::min(p->tun.centres_per_item, kTripletThreads) : 512;
     t.wg_per_cu = p->tun.wg_per_cu == 2 ? 2 : 1;
     const size_t budget = kLdsPerCU / t.wg_per_cu - 256;   // static shared memory headroom
     const size_t fixed = triplet_lds_bytes(0, t.ec, t.cb, kTabMax, wide);
@@ -1060,12 +1062,103 @@ g3_status g3_kernel_time_reset(g3_plan p, int32_t enable)
     return G3_OK;
 }
 
+// Workload signature for the autotuner cache: per system the entry format,
+// nbins, layout, log2 of N and of the expected neighbour count, and frames.
+static std::string tune_key(const g3_system* sys, int n)
+{
+    std::string k;
+    for (int i = 0; i < n; ++i) {
+        const g3_system& s = sys[i];
+        const double V = (double)s.box[0] * s.box[1] * s.box[2];
+        const double nexp = (double)s.n_atoms / V * 4.18879020478639 * s.rmax * s.rmax * s.rmax;
+        char buf[96];
+        std::snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%d;", s.rmax > 32767 ? 1 : 0, s.nbins, s.layout,
+                      (int)std::lround(std::log2(std::max(1, s.n_atoms))),
+                      (int)std::lround(2 * std::log2(std::max(1.0, nexp))), s.n_frames);
+        k += buf;
+    }
+    return k;
+}
+
 g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3_tuning* best)
 {
-    (void)systems;
-    (void)n_systems;
-    if (!p) return G3_EINVAL;
-    return g3_get_tuning(p, best ? best : &p->tun);
+    if (!p || n_systems <= 0 || !systems) return G3_EINVAL;
+    for (int i = 0; i < n_systems; ++i) {
+        const g3_system& s = systems[i];
+        g3_status st = check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
+        if (st) return st;
+        if (s.n_frames < 0 || (s.n_frames > 0 && !s.frames)) return G3_EINVAL;
+    }
+    const std::string key = tune_key(systems, n_systems);
+    auto hit = p->tuned.find(key);
+    if (hit != p->tuned.end()) {
+        p->tun = hit->second;
+        if (best) *best = hit->second;
+        return G3_OK;
+    }
+    g3_status st = drain(p);
+    if (st) return st;
+    // scratch histograms: the caller's are never written
+    std::vector<g3_system> sys(systems, systems + n_systems);
+    std::vector<size_t> len(n_systems);
+    size_t total = 0;
+    for (int i = 0; i < n_systems; ++i) {
+        len[i] = g3_hist_len(sys[i].nbins, sys[i].layout);
+        total += len[i];
+    }
+    uint64_t* scratch = nullptr;
+    G3_TRY_HIP(hipMalloc((void**)&scratch, total * sizeof(uint64_t)));
+    size_t o = 0;
+    for (int i = 0; i < n_systems; ++i) { sys[i].hist = scratch + o; o += len[i]; }
+    std::vector<uint64_t> ref(total), got(total);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+
+    const g3_tuning saved = p->tun;
+    const int cbs[3] = {256, 512, 1024};
+    const int wgs[2] = {1, 2};
+    const int fracs[2] = {4, 3};           // LDS histogram: all of it, or 3/4
+    g3_tuning best_t = saved;
+    double best_ms = 1e30;
+    bool have_ref = false;
+    for (int wi = 0; wi < 2 && st == G3_OK; ++wi)
+        for (int ci = 0; ci < 3 && st == G3_OK; ++ci)
+            for (int fi = 0; fi < 2 && st == G3_OK; ++fi) {
+                g3_tuning t{};
+                t.wg_per_cu = wgs[wi];
+                t.centres_per_item = cbs[ci];
+                p->tun = t;
+                const Tun full = effective(p, false);
+                t.lds_hist_bins = (full.hb_max * fracs[fi] / 4) & ~63;
+                p->tun = t;
+                hipMemsetAsync(scratch, 0, total * sizeof(uint64_t), p->stream);
+                // one untimed run (also the correctness check), then two timed
+                if ((st = run_batch(p, sys.data(), n_systems))) break;
+                if ((st = drain(p))) break;
+                if (hipMemcpy(got.data(), scratch, total * sizeof(uint64_t), hipMemcpyDeviceToHost)) {
+                    st = G3_EDEVICE;
+                    break;
+                }
+                if (!have_ref) { ref = got; have_ref = true; }
+                else if (got != ref) { st = G3_EDEVICE; break; }   // a tuning changed the result
+                hipEventRecord(e0, p->stream);
+                for (int rep = 0; rep < 2 && st == G3_OK; ++rep) st = run_batch(p, sys.data(), n_systems);
+                hipEventRecord(e1, p->stream);
+                if (st) break;
+                if ((st = drain(p))) break;
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) { best_ms = ms; best_t = t; }
+            }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(scratch);
+    if (st) { p->tun = saved; return st; }
+    p->tun = best_t;
+    p->tuned[key] = best_t;
+    if (best) *best = best_t;
+    return G3_OK;
 }
 
 const char* g3_strerror(g3_status s)

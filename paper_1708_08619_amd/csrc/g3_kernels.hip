@@ -333,16 +333,16 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 if (s >= R2) return false;
                 b = bin_of<ONE_STEP>(s, s_tab, s_thr, sh);
                 if constexpr (WIDE) {
-                    e = make_int4(dx, dy, dz, b);
+                    e = make_int4(dx, dy, dz, b * nb);
                 } else {
                     e = make_uint2(((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16),
-                                   ((uint32_t)dz & 0xffffu) | ((uint32_t)b << 16));
+                                   ((uint32_t)dz & 0xffffu) | ((uint32_t)(b * nb) << 16));
                 }
                 return true;
             };
             auto bin_of_entry = [&](const E& e) -> int {
-                if constexpr (WIDE) return e.w;
-                else return (int)(e.y >> 16);
+                if constexpr (WIDE) return e.w / nb;
+                else return (int)(e.y >> 16) / nb;
             };
             if (lane < 32) scnt[lane] = 0u;
             wave_sync();
@@ -487,6 +487,36 @@ struct Ent<true> {
     static __device__ __forceinline__ int col(T v) { return v.w; }
 };
 
+// Entries read straight from the neighbour pool with global (not flat)
+// loads.
+template <bool WIDE>
+struct GEnt;
+
+template <>
+struct GEnt<false> {
+    typedef const __attribute__((address_space(1))) unsigned long long* P;
+    const char* base;
+    __device__ __forceinline__ GEnt at(uint32_t k) const { return GEnt{base + (size_t)k * 8}; }
+    __device__ __forceinline__ uint2 operator[](int k) const
+    {
+        const unsigned long long v = ((P)base)[k];
+        return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    }
+};
+
+template <>
+struct GEnt<true> {
+    typedef int int4v __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) int4v* P;
+    const char* base;
+    __device__ __forceinline__ GEnt at(uint32_t k) const { return GEnt{base + (size_t)k * 16}; }
+    __device__ __forceinline__ int4 operator[](int k) const
+    {
+        const int4v v = ((P)base)[k];
+        return make_int4(v.x, v.y, v.z, v.w);
+    }
+};
+
 // Bin of an accepted squared distance s (< R2) from the LDS tables.
 template <bool ONE_STEP>
 __device__ __forceinline__ int lds_bin(uint32_t s, uint32_t sclamp, const uint8_t* tab,
@@ -508,19 +538,20 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
 {
     using E = typename Ent<WIDE>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* s_hist = reinterpret_cast<uint32_t*>(smem);
-    uint32_t* s_thr = s_hist + A.hb_max;
-    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + 256);
-    E* s_ent = reinterpret_cast<E*>(__builtin_assume_aligned(s_tab + A.tb_max, 16));
-    uint32_t* s_moff = reinterpret_cast<uint32_t*>(s_ent + A.ec);   // cb + 1
-    uint32_t* s_roff = s_moff + (A.cb + 1);                          // cb + 1
-    uint32_t* s_src = s_roff + (A.cb + 1);                           // cb
+    // tables first, at fixed offsets, so their addresses fold into the
+    // instructions' immediate offsets
+    uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                      // 256
+    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + 256);                 // kTabBytes
+    uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_tab + kTabBytes);        // hb_max
+    uint32_t* s_src = s_hist + A.hb_max;                                      // cb: list start
+    uint32_t* s_m = s_src + A.cb;                                             // cb: entries from J_q
+    uint32_t* s_roff = s_m + A.cb;                                            // cb + 1: row prefix
     __shared__ uint32_t s_tmp[17];
     __shared__ int s_item;
     __shared__ uint32_t s_slot;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6, nwave = kTripletThreads / 64;
+    const int lane = tid & 63, wave = tid >> 6;
     int cur_seg = -1, cur_sys = -1;
     uint64_t pending = 0;    // upper bound on increments since the last flush
     uint64_t evaluated = 0;  // candidate pairs of the items this workgroup processed
@@ -601,9 +632,9 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const uint32_t* cnt = S.nbr_cnt + (S.per_frame ? (size_t)f * N : 0);
         const uint16_t* J = S.slab_j + (S.per_frame ? (size_t)f * N * (S.n_slabs + 1) : 0);
         const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
-        const E* P = reinterpret_cast<const E*>(S.pool) + pbase;
+        const GEnt<WIDE> pool{reinterpret_cast<const char*>(S.pool) + pbase * sizeof(E)};
 
-        // per centre: entries to stage (m, from J_q on) and slab rows (r)
+        // per centre: its entries from J_q on (m) and its slab rows (r)
         uint32_t m = 0, r = 0;
         if (tid < nctr) {
             const int i = c_begin + tid;
@@ -613,15 +644,15 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             r = j1 - j0;
             m = r ? n - j0 : 0u;
             s_src[tid] = o + j0;
+            s_m[tid] = m;
         }
         // candidate pairs of this item: r(r-1)/2 + r(m-r) per centre
         const uint32_t inc = r ? r * (r - 1) / 2 + r * (m - r) : 0u;
-        uint32_t mtot, rtot, itot;
-        const uint32_t mpre = block_excl_scan(m, s_tmp, &mtot);
+        uint32_t rtot, itot;
         const uint32_t rpre = block_excl_scan(r, s_tmp, &rtot);
         (void)block_excl_scan(inc, s_tmp, &itot);
-        if (tid < nctr) { s_moff[tid] = mpre; s_roff[tid] = rpre; }
-        if (tid == 0) { s_moff[nctr] = mtot; s_roff[nctr] = rtot; }
+        if (tid < nctr) s_roff[tid] = rpre;
+        if (tid == 0) s_roff[nctr] = rtot;
         __syncthreads();
         if (rtot == 0) continue;
         if (pending + itot > 0xFFFFFFFFull) {  // keep every uint32 LDS counter exact
@@ -636,114 +667,105 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const uint32_t R2 = S.R2, R2m1 = S.R2 - 1u;
         const int sh = S.sh;
         const int cm1 = S.C - 1;
-        const int colmul = nb - lo0;        // A_j = (b_j - lo0) * RL = B'_j * (nbins - lo0)
-        int a = 0;
-        while (a < nctr) {
-            // largest b with s_moff[b] - s_moff[a] <= ec (a single centre always fits)
-            int lo_b = a + 1, hi_b = nctr;
-            const uint32_t lim = s_moff[a] + (uint32_t)A.ec;
-            while (lo_b < hi_b) {
-                const int mid = (lo_b + hi_b + 1) >> 1;
-                if (s_moff[mid] <= lim) lo_b = mid; else hi_b = mid - 1;
+        // slab index of (b_j, b_k, c) = (b_j - lo0) RL + (b_k - lo0) nb + c; the
+        // entries carry b_k * nb, so the row constant absorbs -lo0 * nb
+        const int RL = G.rl;
+        // Work units: every row is cut into Pp parts of its candidate sequence
+        // (circular triangle part, then the rectangle), Pp chosen so that the
+        // item has about two units per thread.  Units of a centre are
+        // part-major, so neighbouring lanes take neighbouring rows of one part
+        // and read the same rectangle entries.
+        const int Pp = (int)min(16u, max(1u, (2u * kTripletThreads + rtot - 1) / rtot));
+        const uint32_t U = rtot * (uint32_t)Pp;
+        for (uint32_t w = tid; w < U; w += kTripletThreads) {
+            int cl = 0, ch = nctr - 1;
+            while (cl < ch) {
+                const int mid = (cl + ch + 1) >> 1;
+                if (s_roff[mid] * (uint32_t)Pp <= w) cl = mid; else ch = mid - 1;
             }
-            const int b = lo_b;
-            const uint32_t base = s_moff[a];
-            // stage entries (one wave per centre), bin b -> (b - lo0) * nbins
-            for (int c = a + wave; c < b; c += nwave) {
-                const uint32_t mc = s_moff[c + 1] - s_moff[c];
-                const E* src = P + s_src[c];
-                E* dst = s_ent + (s_moff[c] - base);
-                for (uint32_t e = lane; e < mc; e += 64) {
-                    E v = src[e];
-                    if (WIDE) {
-                        int* vi = reinterpret_cast<int*>(&v);
-                        vi[3] = (vi[3] - lo0) * nb;
-                    } else {
-                        uint32_t* vu = reinterpret_cast<uint32_t*>(&v);
-                        vu[1] = (vu[1] & 0xffffu) | ((((vu[1] >> 16) - (uint32_t)lo0) * (uint32_t)nb) << 16);
-                    }
-                    dst[e] = v;
-                }
+            const GEnt<WIDE> ent = pool.at(s_src[cl]);
+            const int mm = (int)s_m[cl];
+            const int rr = (int)(s_roff[cl + 1] - s_roff[cl]);
+            const int lw = (int)(w - s_roff[cl] * (uint32_t)Pp);
+            const int p = lw / rr;
+            const int j = lw - p * rr;
+            const E vj = ent[j];
+            const int bj = Ent<WIDE>::col(vj) / nb;
+            const int Aj = (bj - lo0) * RL - lo0 * nb;
+            uint32_t jx, jy = 0, jz;
+            if constexpr (WIDE) {
+                jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
+            } else {
+                jx = vj.x; jz = vj.y & 0xffffu;
             }
-            __syncthreads();
-            const uint32_t r0 = s_roff[a], r1 = s_roff[b];
-            for (uint32_t row = r0 + tid; row < r1; row += kTripletThreads) {
-                int cl = a, ch = b - 1;
-                while (cl < ch) {
-                    const int mid = (cl + ch + 1) >> 1;
-                    if (s_roff[mid] <= row) cl = mid; else ch = mid - 1;
+            auto d2 = [&](const E& vk) -> uint32_t {
+                if constexpr (WIDE)
+                    return Ent<true>::dist2(vk, (int)jx, (int)jy, (int)jz, cm1);
+                else
+                    return Ent<false>::dist2(vk, jx, jz, 0);
+            };
+            // four candidates at a time: distances, table, threshold, then the
+            // (predicated) LDS increments
+            auto eval4 = [&](const E (&v)[4]) {
+                uint32_t s[4], sc[4];
+                int c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) { s[u] = d2(v[u]); sc[u] = min(s[u], R2m1); }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c[u] = lds_bin<ONE_STEP>(s[u], sc[u], s_tab, s_thr, sh);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (s[u] < R2) atomicAdd(&s_hist[Aj + Ent<WIDE>::col(v[u]) + c[u]], 1u);
+            };
+            auto eval1 = [&](const E& v) {
+                const uint32_t s = d2(v);
+                if (s < R2) {
+                    const int c = lds_bin<ONE_STEP>(s, s, s_tab, s_thr, sh);
+                    atomicAdd(&s_hist[Aj + Ent<WIDE>::col(v) + c], 1u);
                 }
-                const E* ent = s_ent + (s_moff[cl] - base);
-                const int mm = (int)(s_moff[cl + 1] - s_moff[cl]);
-                const int rr = (int)(s_roff[cl + 1] - s_roff[cl]);
-                const int j = (int)(row - s_roff[cl]);
-                const E vj = ent[j];
-                const int Aj = Ent<WIDE>::col(vj) * colmul;
-                uint32_t jx, jy = 0, jz;
-                if (WIDE) {
-                    const int* vji = reinterpret_cast<const int*>(&vj);
-                    jx = (uint32_t)vji[0]; jy = (uint32_t)vji[1]; jz = (uint32_t)vji[2];
-                } else {
-                    const uint2 vu = *reinterpret_cast<const uint2*>(&vj);
-                    jx = vu.x; jz = vu.y & 0xffffu;
-                }
-                auto d2 = [&](const E& vk) -> uint32_t {
-                    if constexpr (WIDE)
-                        return Ent<true>::dist2(vk, (int)jx, (int)jy, (int)jz, cm1);
-                    else
-                        return Ent<false>::dist2(vk, jx, jz, 0);
-                };
-                // four candidates at a time: loads, distances, table, threshold,
-                // then the (predicated) LDS increments
-                auto eval4 = [&](const E (&v)[4]) {
-                    uint32_t s[4], sc[4];
-                    int c[4];
+            };
+            // this unit's share [u0, u1) of the row's sequence: u < H is the
+            // circular triangle (k = j + u + 1 mod rr), u >= H the rectangle
+            // (k = rr + u - H)
+            const int H = (rr - 1) / 2 + (((rr & 1) == 0 && j < rr / 2) ? 1 : 0);
+            const int L = H + (mm - rr);
+            const int u0 = (p * L) / Pp, u1 = ((p + 1) * L) / Pp;
+            const int tend = min(u1, H);
+            int t = u0 + 1;
+            for (; t + 3 <= tend; t += 4) {
+                E v[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) { s[u] = d2(v[u]); sc[u] = min(s[u], R2m1); }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) c[u] = lds_bin<ONE_STEP>(s[u], sc[u], s_tab, s_thr, sh);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (s[u] < R2) atomicAdd(&s_hist[Aj + Ent<WIDE>::col(v[u]) + c[u]], 1u);
-                };
-                auto eval1 = [&](const E& v) {
-                    const uint32_t s = d2(v);
-                    if (s < R2) {
-                        const int c = lds_bin<ONE_STEP>(s, s, s_tab, s_thr, sh);
-                        atomicAdd(&s_hist[Aj + Ent<WIDE>::col(v) + c], 1u);
-                    }
-                };
-                // triangle (circular within the slab rows)
-                const int H = (rr - 1) / 2 + (((rr & 1) == 0 && j < rr / 2) ? 1 : 0);
-                int t = 1;
-                for (; t + 4 <= H + 1; t += 4) {
-                    E v[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        int k = j + t + u;
-                        k -= (k >= rr) ? rr : 0;
-                        v[u] = ent[k];
-                    }
-                    eval4(v);
-                }
-                for (; t <= H; ++t) {
-                    int k = j + t;
+                for (int u = 0; u < 4; ++u) {
+                    int k = j + t + u;
                     k -= (k >= rr) ? rr : 0;
-                    eval1(ent[k]);
+                    v[u] = ent[k];
                 }
-                // rectangle
-                int k = rr;
-                for (; k + 4 <= mm; k += 4) {
-                    E v[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = ent[k + u];
-                    eval4(v);
-                }
-                for (; k < mm; ++k) eval1(ent[k]);
+                eval4(v);
             }
-            __syncthreads();
-            a = b;
+            for (; t <= tend; ++t) {
+                int k = j + t;
+                k -= (k >= rr) ? rr : 0;
+                eval1(ent[k]);
+            }
+            // rectangle, next group's loads issued before this group's work
+            int k = rr + max(u0, H) - H;
+            const int kend = rr + u1 - H;
+            if (k + 4 <= kend) {
+                E cur[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) cur[u] = ent[k + u];
+                for (; k + 4 <= kend; k += 4) {
+                    E nxt[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) nxt[u] = ent[min(k + 4 + u, mm - 1)];
+                    eval4(cur);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+                }
+            }
+            for (; k < kend; ++k) eval1(ent[k]);
         }
+        __syncthreads();
     }
     if (cur_seg >= 0) flush(cur_seg);
     if (tid == 0 && evaluated) atomicAdd(A.cand, (unsigned long long)evaluated);

@@ -206,8 +206,8 @@ class Plan:
                                    float(rmax), int(nbins), int(layout),
                                    _dev_ptr(hist, "uint64", "hist")), "g3_accumulate")
 
-    # -- g3_accumulate_batch: one graph launch for many systems
-    def accumulate_batch(self, systems: Sequence[dict]):
+    @staticmethod
+    def _systems(systems: Sequence[dict]):
         arr = (System * len(systems))()
         for i, s in enumerate(systems):
             fr, h = s["frames"], s["hist"]
@@ -224,7 +224,19 @@ class Plan:
             arr[i].nbins = int(s["nbins"])
             arr[i].layout = int(s["layout"])
             arr[i].hist = _dev_ptr(h, "uint64", "hist")
+        return arr
+
+    # -- g3_accumulate_batch: one graph launch for many systems
+    def accumulate_batch(self, systems: Sequence[dict]):
+        arr = self._systems(systems)
         _check(lib().g3_accumulate_batch(self._h, arr, len(systems)), "g3_accumulate_batch")
+
+    # -- g3_autotune: pick (and keep) the fastest tuning for these systems
+    def autotune(self, systems: Sequence[dict]) -> dict:
+        arr = self._systems(systems)
+        t = Tuning()
+        _check(lib().g3_autotune(self._h, arr, len(systems), C.byref(t)), "g3_autotune")
+        return t.as_dict()
 
     def sync(self):
         _check(lib().g3_sync(self._h), "g3_sync")
