@@ -13,6 +13,7 @@ constexpr int kMaxSlabs = 24;          // r12 slabs per system
 constexpr int kTripletThreads = 1024;  // threads of the triplet workgroup
 constexpr int kTabBytes = 8192;        // LDS bytes of the bin lookup table
 constexpr int kWave = 64;
+constexpr int kPoolPad = 8;          // entries after each frame's pool slot that unrolled reads may touch
 constexpr int kCursorStride = 32;   // uint32 words between per-frame pool cursors (one 128 B line each)
 
 // Per-frame status bits (one uint32 per frame and system).
@@ -53,7 +54,7 @@ struct Sys {
     uint16_t* slab_j;        // [N][n_slabs + 1]  J_q = #entries with bin < slab_lo[q];
                              // a list is partitioned by slab: slab q holds [J_q, J_q+1)
     void* pool;              // entries, 8 or 16 bytes each
-    int64_t pool_cap;        // entries per frame slot
+    int64_t pool_cap;        // entries per frame slot (the slot stride is pool_cap + kPoolPad)
     int32_t per_frame;       // 1: every frame has its own scratch; 0: reused
     uint32_t* flags;         // [F] (always per frame)
 };

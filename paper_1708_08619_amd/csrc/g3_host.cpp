@@ -240,6 +240,7 @@ struct g3_plan_s {
     struct Rec {            // what a range of the flag log belongs to
         g3_system sys;
         int log_off;
+        bool worst_case;    // already the recomputation with the largest pool
     };
     std::vector<Rec> recs;
 
@@ -381,7 +382,10 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
             P.pool_cap = (int64_t)N * std::min<int64_t>(kListCap, std::max<int64_t>(N, 1)) + slack;
         }
         P.off_pool = o;
-        o = align_up(o + F * (size_t)P.pool_cap * (g.wide ? 16 : 8), 256);
+        // byte offsets inside a slot must fit 32 bits
+        const int64_t max_cap = ((int64_t)1 << 32) / (g.wide ? 16 : 8) - kPoolPad - 1;
+        P.pool_cap = std::min<int64_t>(P.pool_cap, max_cap);
+        o = align_up(o + F * (size_t)(P.pool_cap + kPoolPad) * (g.wide ? 16 : 8), 256);
     }
     return o;
 }
@@ -604,7 +608,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     int foff;
     st = reserve_flags(p, s.n_frames, &flags, &foff);
     if (st) return st;
-    p->recs.push_back({s, foff});
+    p->recs.push_back({s, foff, worst_case});
 
     const Prepared& P = ps[0];
     const int F = s.n_frames;
@@ -711,7 +715,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         std::vector<Seg> segs;
         int items = 0, fo = foff, max_n = 0, max_hb = 0;
         for (size_t k = 0; k < ps.size(); ++k) {
-            p->recs.push_back({ps[k].in, fo});
+            p->recs.push_back({ps[k].in, fo, false});
             sys.push_back(make_sys(ps[k], (char*)p->arena, p->flag_log + fo));
             fo += ps[k].in.n_frames;
             for (int f = 0; f < ps[k].in.n_frames; ++f) jobs.push_back({(int)k, f});
@@ -839,6 +843,7 @@ g3_status drain(g3_plan p)
                 const uint32_t v = fl[r.log_off + f];
                 if (v & kFlagDomain) { if (result == G3_OK) result = G3_EDOMAIN; }
                 else if (v & kFlagList) { if (result == G3_OK) result = G3_ENOMEM; }
+                else if ((v & kFlagPool) && r.worst_case) { if (result == G3_OK) result = G3_ENOMEM; }
                 else if (v & kFlagPool) {
                     g3_system one = r.sys;
                     one.frames = r.sys.frames + (size_t)f * 3 * r.sys.n_atoms;

@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     uint32_t* nbr_off = S.nbr_off + fr_off(S, f, N);
     uint32_t* nbr_cnt = S.nbr_cnt + fr_off(S, f, N);
     uint16_t* slab_j = S.slab_j + fr_off(S, f, (size_t)N * (n_slabs + 1));
-    const size_t pbase = S.per_frame ? (size_t)f * (size_t)pool_cap : 0;
+    const size_t pbase = S.per_frame ? (size_t)f * (size_t)(pool_cap + kPoolPad) : 0;
     E* pool = reinterpret_cast<E*>(S.pool) + pbase;
 
     // bin tables and the bin -> slab map, once per workgroup
@@ -488,32 +488,55 @@ struct Ent<true> {
 };
 
 // Entries read straight from the neighbour pool with global (not flat)
-// loads.
+// loads: a wave-uniform base plus a 32-bit byte offset per lane, so the
+// loads take the scalar-base form and unrolled neighbours differ only in the
+// immediate offset.
 template <bool WIDE>
 struct GEnt;
 
 template <>
 struct GEnt<false> {
+    static constexpr uint32_t kSize = 8;
     typedef const __attribute__((address_space(1))) unsigned long long* P;
-    const char* base;
-    __device__ __forceinline__ GEnt at(uint32_t k) const { return GEnt{base + (size_t)k * 8}; }
-    __device__ __forceinline__ uint2 operator[](int k) const
+    typedef const __attribute__((address_space(1))) char* B;
+    const char* base;   // uniform
+    __device__ __forceinline__ uint2 load(uint32_t byte_off) const
     {
-        const unsigned long long v = ((P)base)[k];
+        const unsigned long long v = *(P)((B)base + byte_off);
         return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    }
+    // group of four consecutive entries from one 64-bit address
+    __device__ __forceinline__ void load4(uint32_t byte_off, uint2 (&v)[4]) const
+    {
+        const P q = (P)((B)base + byte_off);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned long long x = q[u];
+            v[u] = make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+        }
     }
 };
 
 template <>
 struct GEnt<true> {
+    static constexpr uint32_t kSize = 16;
     typedef int int4v __attribute__((ext_vector_type(4)));
     typedef const __attribute__((address_space(1))) int4v* P;
-    const char* base;
-    __device__ __forceinline__ GEnt at(uint32_t k) const { return GEnt{base + (size_t)k * 16}; }
-    __device__ __forceinline__ int4 operator[](int k) const
+    typedef const __attribute__((address_space(1))) char* B;
+    const char* base;   // uniform
+    __device__ __forceinline__ int4 load(uint32_t byte_off) const
     {
-        const int4v v = ((P)base)[k];
+        const int4v v = *(P)((B)base + byte_off);
         return make_int4(v.x, v.y, v.z, v.w);
+    }
+    __device__ __forceinline__ void load4(uint32_t byte_off, int4 (&v)[4]) const
+    {
+        const P q = (P)((B)base + byte_off);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int4v x = q[u];
+            v[u] = make_int4(x.x, x.y, x.z, x.w);
+        }
     }
 };
 
@@ -631,8 +654,9 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const uint32_t* off = S.nbr_off + (S.per_frame ? (size_t)f * N : 0);
         const uint32_t* cnt = S.nbr_cnt + (S.per_frame ? (size_t)f * N : 0);
         const uint16_t* J = S.slab_j + (S.per_frame ? (size_t)f * N * (S.n_slabs + 1) : 0);
-        const size_t pbase = S.per_frame ? (size_t)f * (size_t)S.pool_cap : 0;
+        const size_t pbase = S.per_frame ? (size_t)f * (size_t)(S.pool_cap + kPoolPad) : 0;
         const GEnt<WIDE> pool{reinterpret_cast<const char*>(S.pool) + pbase * sizeof(E)};
+        constexpr uint32_t ES = GEnt<WIDE>::kSize;
 
         // per centre: its entries from J_q on (m) and its slab rows (r)
         uint32_t m = 0, r = 0;
@@ -683,13 +707,13 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 const int mid = (cl + ch + 1) >> 1;
                 if (s_roff[mid] * (uint32_t)Pp <= w) cl = mid; else ch = mid - 1;
             }
-            const GEnt<WIDE> ent = pool.at(s_src[cl]);
+            const uint32_t eoff = s_src[cl] * ES;        // byte offset of the centre's entry J_q
             const int mm = (int)s_m[cl];
             const int rr = (int)(s_roff[cl + 1] - s_roff[cl]);
             const int lw = (int)(w - s_roff[cl] * (uint32_t)Pp);
             const int p = lw / rr;
             const int j = lw - p * rr;
-            const E vj = ent[j];
+            const E vj = pool.load(eoff + (uint32_t)j * ES);
             const int bj = Ent<WIDE>::col(vj) / nb;
             const int Aj = (bj - lo0) * RL - lo0 * nb;
             uint32_t jx, jy = 0, jz;
@@ -738,32 +762,37 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 for (int u = 0; u < 4; ++u) {
                     int k = j + t + u;
                     k -= (k >= rr) ? rr : 0;
-                    v[u] = ent[k];
+                    v[u] = pool.load(eoff + (uint32_t)k * ES);
                 }
                 eval4(v);
             }
             for (; t <= tend; ++t) {
                 int k = j + t;
                 k -= (k >= rr) ? rr : 0;
-                eval1(ent[k]);
+                eval1(pool.load(eoff + (uint32_t)k * ES));
             }
-            // rectangle, next group's loads issued before this group's work
+            // rectangle: two register groups in ping-pong, each group's loads
+            // issued one group ahead (reads may run up to 7 entries past the
+            // list, into the pool slot's padding, and are never evaluated)
             int k = rr + max(u0, H) - H;
             const int kend = rr + u1 - H;
+            uint32_t ko = eoff + (uint32_t)k * ES;
             if (k + 4 <= kend) {
-                E cur[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) cur[u] = ent[k + u];
-                for (; k + 4 <= kend; k += 4) {
-                    E nxt[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) nxt[u] = ent[min(k + 4 + u, mm - 1)];
-                    eval4(cur);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+                E ga[4], gb[4];
+                pool.load4(ko, ga);
+                for (; k + 8 <= kend; k += 8, ko += 8 * ES) {
+                    pool.load4(ko + 4 * ES, gb);
+                    eval4(ga);
+                    pool.load4(ko + 8 * ES, ga);
+                    eval4(gb);
+                }
+                if (k + 4 <= kend) {
+                    eval4(ga);
+                    k += 4;
+                    ko += 4 * ES;
                 }
             }
-            for (; k < kend; ++k) eval1(ent[k]);
+            for (; k < kend; ++k, ko += ES) eval1(pool.load(ko));
         }
         __syncthreads();
     }
