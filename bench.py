@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--frames", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-centres", type=int, default=16384)
+    ap.add_argument("--cpu-frames", type=int, default=8,
+                    help="frames of the workload the CPU oracle processes (all centres)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
@@ -122,12 +123,13 @@ def main():
     achieved = ops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": INT32_VALU_PEAK_TOPS,
                 "unit": "Tops/s (int32)", "frac": achieved / INT32_VALU_PEAK_TOPS if achieved else None,
-                "traffic": None, "kernel": "k_triplet", "kernel_ms": kern_ms,
+                "traffic": traffic_per_launch(), "traffic_unit": "bytes per launch",
+                "kernel": "k_triplet", "kernel_ms": kern_ms,
                 "candidates_per_launch": cand, "binned_per_launch": binned}
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, args.cpu_centres)
+        cpu = cpu_baseline(w, args.cpu_frames)
 
     line = {
         "metric": "G triplets binned/s at N=65536 (plain vs batched); p50/p99 served latency",
@@ -150,21 +152,36 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(w, n_centres: int):
-    """The oracle (plain C, OpenMP over centres) on a bounded sample: the
-    contribution of the first ``n_centres`` centres of frame 0."""
+def cpu_baseline(w, n_frames: int):
+    """The oracle (plain C, OpenMP over centres, untuned) on a bounded
+    sample of the same workload: its first ``n_frames`` frames, all centres."""
     import oracle
     oracle.lib()
     nt = oracle.max_threads()
-    centres = np.arange(min(n_centres, w.n_atoms), dtype=np.int32)
+    n_frames = max(1, min(n_frames, w.n_frames))
     t0 = time.perf_counter()
-    H = oracle.hist_full(w.frames[:1], w.box, w.rmax, w.nbins, n_threads=nt, centres=centres)
+    H = oracle.hist_full(w.frames[:n_frames], w.box, w.rmax, w.nbins, n_threads=nt)
     dt = time.perf_counter() - t0
     binned = int(H.sum()) // 2                  # unordered pairs = half-layout total
     return {"value": binned / dt / 1e9, "unit": "G triplets binned/s", "cores": nt,
             "kind": "oracle", "seconds": dt,
-            "sample": f"frame 0, centres 0..{len(centres) - 1} of {w.n_atoms} "
+            "sample": f"frames 0..{n_frames - 1} of {w.n_frames}, all {w.n_atoms} centres "
                       f"({binned} triplets binned)"}
+
+
+def traffic_per_launch():
+    """HBM bytes per triplet-kernel launch from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None if the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_triplet_lj65536_batched_traffic.json")
+    src = os.path.join(ROOT, "paper_1708_08619_amd", "csrc", "g3_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return rec["bytes_per_launch"] if rec.get("kernel_source_sha256") == h else None
 
 
 if __name__ == "__main__":
