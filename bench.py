@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=8,
                     help="frames of the workload the CPU oracle processes (all centres)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests in the served (continuous batching) run; 0 skips it")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
@@ -127,6 +130,10 @@ def main():
                 "kernel": "k_triplet", "kernel_ms": kern_ms,
                 "candidates_per_launch": cand, "binned_per_launch": binned}
 
+    served = None
+    if args.serve_requests > 0:
+        served = serve_bench(args.serve_requests, args.serve_rate)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, args.cpu_frames)
@@ -145,6 +152,7 @@ def main():
                    "form": "batched (one hipGraph launch per step)"},
         "triplets_binned_per_step": binned,
         "plain": plain,
+        "served": served,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -167,6 +175,27 @@ def cpu_baseline(w, n_frames: int):
             "kind": "oracle", "seconds": dt,
             "sample": f"frames 0..{n_frames - 1} of {w.n_frames}, all {w.n_atoms} centres "
                       f"({binned} triplets binned)"}
+
+
+def serve_bench(n_requests: int, rate_hz: float):
+    """Open-loop Poisson request stream served by continuous batching; p50/p99
+    latency (arrival -> histogram in host memory) at two HBM budgets."""
+    from paper_1708_08619_amd import serve
+    store = serve.TrajectoryStore(n_systems=16, max_frames=20, n_min=1024, n_max=65536)
+    out = {"rate_hz": rate_hz, "workload": "frames U{1..20}, N log-uniform 1024..65536, "
+           "rmax in {2.0, 2.5, 3.0} sigma, dr 0.05 sigma, jittered FCC rho U(0.7,0.9)"}
+    for name, budget, fpi in (("budget_8GiB", 8 << 30, 2), ("budget_256MiB", 256 << 20, 2)):
+        reqs = serve.poisson_requests(store, n_requests, rate_hz)
+        warm = serve.poisson_requests(store, 8, 1e6, seed=(1, 2))
+        srv = serve.Server(hbm_budget_bytes=budget, frames_per_iter=fpi)
+        srv.run_open_loop(warm)                 # library scratch and allocator warm-up
+        srv.iterations, srv.peak_used = 0, 0
+        st = srv.run_open_loop(reqs)
+        out[name] = {k: st[k] for k in ("requests", "p50_ms", "p99_ms", "mean_ms", "max_ms",
+                                        "throughput_G_per_s", "requests_per_s", "iterations",
+                                        "peak_hbm_bytes")}
+        out[name]["frames_per_iter"] = fpi
+    return out
 
 
 def traffic_per_launch():

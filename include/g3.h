@@ -17,7 +17,7 @@
  *   frames   device pointer, int32, layout [n_frames][3][n_atoms] (x row, y row,
  *            z row per frame); every coordinate must satisfy 0 <= x_d < box[d].
  *   box      host array of 3 positive int32 edges of the orthorhombic periodic
- *            box, in the same unit as the coordinates, each <= 2^30.
+ *            box, in the same unit as the coordinates, each <= 2^29.
  *   rmax     cutoff in coordinate units (binary64, used exactly); requires
  *            1 <= rmax <= 46340 and 2*rmax < box[d] on every axis.
  *   nbins    bins per axis, 1..G3_MAX_NBINS; bin width dr = rmax / nbins,
@@ -58,7 +58,7 @@ typedef enum {
     G3_ENOMEM = 3,   /* device memory exhausted, or one centre has more
                         neighbours than the plan's per-centre capacity */
     G3_EDEVICE = 4,  /* HIP runtime error */
-    G3_EBUSY = 5     /* reserved */
+    G3_EBUSY = 5     /* queued work still running (g3_query) */
 } g3_status;
 
 typedef enum { G3_HALF = 0, G3_FULL = 1 } g3_layout;
@@ -81,7 +81,6 @@ typedef struct {
 typedef struct {
     int32_t lds_hist_bins;   /* uint32 histogram bins held in LDS per workgroup
                                 (the r12 slab size); slabs are whole rows lo */
-    int32_t lds_entries;     /* neighbour entries staged in LDS per sub-batch */
     int32_t centres_per_item;/* centres in one work item of the persistent kernel */
     int32_t wg_per_cu;       /* resident workgroups per compute unit (1 or 2) */
 } g3_tuning;
@@ -101,10 +100,12 @@ g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames,
                         int32_t n_atoms, const int32_t box[3], double rmax,
                         int32_t nbins, int32_t layout, uint64_t* hist);
 
-/* Batched form: every frame of every system in ONE hipGraph launch (batched
+/* Batched form: every frame of every system in ONE launch sequence (batched
  * cell and neighbour builds, one persistent triplet kernel pulling work items
- * from a device counter, one flush at the end).  Systems may differ in size,
- * box, rmax, nbins and layout.  Several systems may not share one hist. */
+ * from a device counter, one flush at the end), replayed as a hipGraph once
+ * the same launch signature (shapes and tuning) repeats.  Systems may differ
+ * in size, box, rmax, nbins and layout.  Several systems may not share one
+ * hist. */
 g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_systems);
 
 /* Wait for the plan's queued work and report asynchronous errors:
@@ -114,6 +115,10 @@ g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_sys
  * neighbour lists overflowed the batched scratch estimate are recomputed here
  * through the plain path before returning, so they are never lost. */
 g3_status g3_sync(g3_plan p);
+
+/* Non-blocking: G3_OK if all work queued on the plan's stream has finished
+ * (g3_sync will then not wait), G3_EBUSY if some is still running. */
+g3_status g3_query(g3_plan p);
 
 /* Histogram length for (nbins, layout); 0 if invalid. */
 size_t g3_hist_len(int32_t nbins, int32_t layout);

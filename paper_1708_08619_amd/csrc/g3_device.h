@@ -94,17 +94,14 @@ struct TripletArgs {
     int32_t* slot_seg;       // [max_slots]
     int32_t max_slots;
     int32_t hb_max;          // LDS histogram bins
-    int32_t ec;              // LDS entries
     int32_t cb;              // centres per item
     int32_t tb_max;          // bytes reserved for the bin table
     unsigned long long* cand;  // running count of candidate (centre, {j,k}) pairs evaluated
 };
 
 // LDS bytes used by the triplet kernel for a configuration.
-inline size_t triplet_lds_bytes(int hb_max, int ec, int cb, int tb_max, bool wide)
+inline size_t triplet_lds_bytes(int hb_max, int cb, int tb_max)
 {
-    (void)ec;
-    (void)wide;
     return 256 * 4 + (size_t)tb_max + (size_t)hb_max * 4 + (size_t)(3 * cb + 1) * 4;
 }
 

@@ -900,7 +900,7 @@ hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
 
 void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s)
 {
-    const size_t lds = triplet_lds_bytes(a.hb_max, a.ec, a.cb, a.tb_max, wide);
+    const size_t lds = triplet_lds_bytes(a.hb_max, a.cb, a.tb_max);
     if (wide) {
         if (one_step)
             hipLaunchKernelGGL((k_triplet<true, true>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);

@@ -37,7 +37,7 @@ class System(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("lds_hist_bins", C.c_int32), ("lds_entries", C.c_int32),
+    _fields_ = [("lds_hist_bins", C.c_int32),
                 ("centres_per_item", C.c_int32), ("wg_per_cu", C.c_int32)]
 
     def as_dict(self) -> dict:
@@ -71,6 +71,7 @@ def lib():
         "g3_accumulate": ([P, P, I32, I32, P, D, I32, I32, P], I32),
         "g3_accumulate_batch": ([P, P, I32], I32),
         "g3_sync": ([P], I32),
+        "g3_query": ([P], I32),
         "g3_hist_len": ([I32, I32], C.c_size_t),
         "g3_check_args": ([I32, P, D, I32, I32], I32),
         "g3_thresholds": ([D, I32, P], I32),
@@ -240,6 +241,14 @@ class Plan:
 
     def sync(self):
         _check(lib().g3_sync(self._h), "g3_sync")
+
+    def query(self) -> bool:
+        """True if all queued work has finished (non-blocking)."""
+        st = int(lib().g3_query(self._h))
+        if st == EBUSY:
+            return False
+        _check(st, "g3_query")
+        return True
 
     def sync_status(self) -> int:
         return int(lib().g3_sync(self._h))

@@ -1,0 +1,332 @@
+"""Serving loop for g3 analyses: continuous batching under an HBM budget.
+
+Requests (one system's frames plus rmax, nbins and layout) arrive while
+others are on the GPU.  The scheduler works in iterations: every iteration is
+one batched accumulate (``g3_accumulate_batch``) over the next
+``frames_per_iter`` frames of every active request, so a request that arrives
+while the GPU is busy joins the next iteration and leaves as soon as its own
+frames are done (iteration-level continuous batching).  Admission is
+first-come first-served while the request's device footprint -- its frames,
+its histogram and its share of the neighbour pool -- fits the HBM budget; a
+request that does not fit waits until finished requests free their memory.
+A request's frames and histogram stay resident on the device from admission
+to completion; completion is the moment its histogram is visible in host
+memory, and latency runs from its arrival to that moment.
+
+The scheduler talks to an executor: :class:`GpuExecutor` drives libg3
+through ``g3.Plan`` (all arithmetic runs in the HIP library); tests substitute
+a CPU executor to check the scheduling logic.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import g3
+
+
+@dataclass
+class Request:
+    """One g3 analysis: host int32 frames [F, 3, N] and its parameters."""
+    rid: int
+    frames: np.ndarray
+    box: list
+    rmax: float
+    nbins: int
+    layout: int = g3.HALF
+    arrival: float = 0.0            # seconds on the server's clock
+    # filled by the server
+    admitted: float = math.nan
+    done: float = math.nan
+    result: np.ndarray | None = None
+    status: int = g3.OK
+    dev_frames: object = None
+    dev_hist: object = None
+    next_frame: int = 0
+    nbytes: int = 0
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.frames.shape[0])
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.frames.shape[2])
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def footprint_bytes(req: Request, frames_per_iter: int) -> int:
+    """Device bytes a request holds while active: frames, histogram, and the
+    neighbour-pool share of one iteration (uniform-density estimate with the
+    library's headroom) plus per-frame cell scratch."""
+    F, N = req.n_frames, req.n_atoms
+    V = float(req.box[0]) * req.box[1] * req.box[2]
+    nexp = N / V * 4.0 / 3.0 * math.pi * req.rmax ** 3
+    entry = 16 if math.ceil(req.rmax) > 32767 else 8
+    k = min(F, frames_per_iter)
+    pool = k * N * (1.35 * min(nexp, N) + 16) * entry
+    scratch = k * N * 48
+    return int(F * 3 * N * 4 + g3.hist_len(req.nbins, req.layout) * 8 + pool + scratch)
+
+
+class GpuExecutor:
+    """Device side of the server: torch buffers on one HIP stream and a
+    libg3 plan on that stream."""
+
+    def __init__(self, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda:0")
+        torch.cuda.set_device(self.device)
+        self.plan = g3.Plan()
+        self._host = {}
+
+    def upload(self, frames: np.ndarray):
+        t = self.torch
+        host = t.from_numpy(np.ascontiguousarray(frames, dtype=np.int32)).pin_memory()
+        dev = host.to(self.device, non_blocking=True)
+        self._host[id(dev)] = host           # keep the pinned source alive until synced
+        return dev
+
+    def new_hist(self, n: int):
+        t = self.torch
+        return t.zeros(n, dtype=t.uint64, device=self.device)
+
+    def accumulate_batch(self, systems: list[dict]):
+        self.plan.accumulate_batch(systems)
+
+    def start_fetch(self, hist):
+        t = self.torch
+        host = t.empty(hist.shape, dtype=t.uint64, pin_memory=True)
+        host.copy_(hist, non_blocking=True)
+        return host
+
+    def finish_fetch(self, token) -> np.ndarray:
+        return token.numpy().copy()
+
+    def release(self, frames, hist):
+        self._host.pop(id(frames), None)
+
+    def sync(self) -> int:
+        return self.plan.sync_status()
+
+    def record(self):
+        ev = self.torch.cuda.Event()
+        ev.record()
+        return ev
+
+
+class Server:
+    """Iteration-level continuous batching."""
+
+    def __init__(self, hbm_budget_bytes: int = 8 << 30, frames_per_iter: int = 4,
+                 max_in_flight: int = 2, executor=None):
+        self.ex = executor if executor is not None else GpuExecutor()
+        self.budget = int(hbm_budget_bytes)
+        self.frames_per_iter = int(frames_per_iter)
+        self.max_in_flight = int(max_in_flight)
+        self.queue: collections.deque[Request] = collections.deque()
+        self.active: list[Request] = []
+        self.in_flight: collections.deque = collections.deque()
+        self.used = 0
+        self.peak_used = 0
+        self.iterations = 0
+        self.completed: list[Request] = []
+        self._next_rid = 0
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    # -- admission -----------------------------------------------------------
+    def submit(self, req: Request):
+        fr = req.frames
+        if fr.ndim != 3 or fr.shape[1] != 3:
+            raise ValueError("frames must be [F, 3, N]")
+        st = g3.check_args(req.n_atoms, req.box, req.rmax, req.nbins, req.layout)
+        if st != g3.OK:
+            raise g3.G3Error(st, f"request {req.rid}")
+        if req.n_frames == 0:
+            raise ValueError("a request needs at least one frame")
+        lo = np.asarray(req.box, dtype=np.int64)[None, :, None]
+        if fr.min() < 0 or np.any(fr >= lo):
+            raise g3.G3Error(g3.EDOMAIN, f"request {req.rid}")
+        req.nbytes = footprint_bytes(req, self.frames_per_iter)
+        if req.nbytes > self.budget:
+            raise g3.G3Error(g3.ENOMEM, f"request {req.rid} exceeds the HBM budget")
+        self.queue.append(req)
+
+    def request(self, frames: np.ndarray, box, rmax: float, nbins: int,
+                layout: int = g3.HALF) -> Request:
+        """Submit one analysis now and return its handle (a future): pass it
+        to :meth:`result`.  ``frames`` is host int32 [F, 3, N]."""
+        req = Request(self._next_rid, frames, list(box), float(rmax), int(nbins), int(layout),
+                      arrival=self.now())
+        self._next_rid += 1
+        self.submit(req)
+        return req
+
+    def result(self, req: Request) -> np.ndarray:
+        """Serve until ``req`` is complete and return its uint64 histogram
+        (other requests keep advancing meanwhile)."""
+        while math.isnan(req.done):
+            if not self.step():
+                raise RuntimeError(f"request {req.rid} is not queued on this server")
+        if req.status != g3.OK:
+            raise g3.G3Error(req.status, f"request {req.rid}")
+        return req.result
+
+    def _admit(self):
+        while self.queue and self.used + self.queue[0].nbytes <= self.budget:
+            req = self.queue.popleft()
+            req.dev_frames = self.ex.upload(req.frames)
+            req.dev_hist = self.ex.new_hist(g3.hist_len(req.nbins, req.layout))
+            req.admitted = self.now()
+            self.used += req.nbytes
+            self.peak_used = max(self.peak_used, self.used)
+            self.active.append(req)
+
+    def _release(self, req: Request):
+        self.used -= req.nbytes
+        self.ex.release(req.dev_frames, req.dev_hist)
+        req.dev_frames = req.dev_hist = None
+        self.active.remove(req)
+        self.completed.append(req)
+
+    # -- one iteration ---------------------------------------------------------
+    def _iterate(self):
+        k = self.frames_per_iter
+        systems, done_now = [], []
+        for req in self.active:
+            a, b = req.next_frame, min(req.next_frame + k, req.n_frames)
+            systems.append(dict(frames=req.dev_frames[a:b], box=req.box, rmax=req.rmax,
+                                nbins=req.nbins, layout=req.layout, hist=req.dev_hist))
+            req.next_frame = b
+            if b == req.n_frames:
+                done_now.append(req)
+        try:
+            self.ex.accumulate_batch(systems)
+        except Exception:
+            for req in list(self.active):     # nothing of this batch was queued
+                req.status = g3.EDEVICE
+                req.done = self.now()
+                self._release(req)
+            raise
+        self.iterations += 1
+        if not done_now:
+            self.in_flight.append(self.ex.record())
+            return
+        # A finished request's histogram is final only after g3_sync: a frame
+        # whose scratch overflowed is recomputed there from its device frames.
+        tokens = [self.ex.start_fetch(req.dev_hist) for req in done_now]
+        st = self.ex.sync()
+        self.in_flight.clear()
+        t = self.now()
+        for req, tok in zip(done_now, tokens):
+            req.status = st
+            req.done = t
+            req.result = self.ex.finish_fetch(tok)
+            self._release(req)
+        if st != g3.OK:
+            raise g3.G3Error(st, "serving batch")
+
+    def step(self) -> bool:
+        """Admit what fits and enqueue one iteration if there is work and room
+        in flight.  Returns True if it did anything."""
+        while self.in_flight and self.in_flight[0].query():
+            self.in_flight.popleft()
+        self._admit()
+        if self.active and len(self.in_flight) < self.max_in_flight:
+            self._iterate()
+            return True
+        if self.in_flight:
+            self.in_flight[0].synchronize()
+            return True
+        return False
+
+    def drain(self):
+        while self.queue or self.active or self.in_flight:
+            if not self.step():
+                break
+        st = self.ex.sync()
+        if st != g3.OK:
+            raise g3.G3Error(st, "serving batch")
+
+    # -- open-loop driver --------------------------------------------------------
+    def run_open_loop(self, requests: list[Request]) -> dict:
+        """Serve requests whose ``arrival`` times (seconds from start) form an
+        open-loop schedule.  Returns latency and throughput statistics."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        self.t0 = time.perf_counter()
+        i = 0
+        while i < len(pending) or self.queue or self.active or self.in_flight:
+            now = self.now()
+            while i < len(pending) and pending[i].arrival <= now:
+                self.submit(pending[i])
+                i += 1
+            if self.step():
+                continue
+            if i < len(pending):
+                time.sleep(max(0.0, min(pending[i].arrival - self.now(), 0.001)))
+        st = self.ex.sync()
+        if st != g3.OK:
+            raise g3.G3Error(st, "serving batch")
+        return summarize(requests, self.now(), self.iterations, self.peak_used)
+
+
+def summarize(requests: list[Request], wall: float, iterations: int, peak_used: int = 0) -> dict:
+    lat = np.array([r.latency for r in requests]) * 1e3
+    binned = sum(int(r.result.sum()) // (2 if r.layout == g3.FULL else 1) for r in requests)
+    first = min(r.arrival for r in requests)
+    last = max(r.done for r in requests)
+    span = max(last - first, 1e-9)
+    return {"requests": len(requests), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "max_ms": float(lat.max()), "triplets_binned": binned,
+            "throughput_G_per_s": binned / span / 1e9, "requests_per_s": len(requests) / span,
+            "iterations": iterations, "wall_s": wall, "peak_hbm_bytes": int(peak_used)}
+
+
+class TrajectoryStore:
+    """Seeded jittered-FCC trajectories that requests draw frames from, so a
+    long request stream needs only a few generated systems."""
+
+    def __init__(self, n_systems: int = 16, max_frames: int = 20, n_min: int = 1024,
+                 n_max: int = 65536, seed=(20170833, 7)):
+        from . import synth
+        g = np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(seed))))
+        self.max_frames = max_frames
+        self.systems = []
+        for s in range(n_systems):
+            N = int(round(math.exp(g.uniform(math.log(n_min), math.log(n_max)))))
+            rho = float(g.uniform(0.7, 0.9))
+            frames, box = synth.jittered_fcc(N, rho, 0.1, max_frames, list(seed) + [s])
+            self.systems.append((frames, box))
+
+    def request(self, rid: int, g: np.random.Generator, arrival: float) -> Request:
+        """frames ~ U{1..max_frames} of a random system, rmax in {2.0, 2.5,
+        3.0} sigma with dr = 0.05 sigma, half layout."""
+        s = int(g.integers(0, len(self.systems)))
+        frames, box = self.systems[s]
+        F = int(g.integers(1, frames.shape[0] + 1))
+        a = int(g.integers(0, frames.shape[0] - F + 1))
+        rm = float(g.choice([2.0, 2.5, 3.0]))
+        return Request(rid, frames[a:a + F], list(box), rm * 4096.0, int(round(rm / 0.05)),
+                       g3.HALF, arrival)
+
+
+def poisson_requests(store: TrajectoryStore, n: int, rate_hz: float, seed=(20170833, 9)):
+    """Open-loop Poisson arrivals at ``rate_hz``."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(seed))))
+    t, out = 0.0, []
+    for r in range(n):
+        t += float(g.exponential(1.0 / rate_hz))
+        out.append(store.request(r, g, t))
+    return out

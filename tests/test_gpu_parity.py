@@ -204,7 +204,7 @@ def test_accumulate_adds(g3mod, plan, torch_dev, oracle_mod):
 # ------------------------------------------------------------------ tuning invariance
 @pytest.mark.parametrize("tun", [
     dict(lds_hist_bins=4096),                          # many thin slabs
-    dict(lds_entries=1024, centres_per_item=64),
+    dict(centres_per_item=64),
     dict(centres_per_item=1024),
     dict(wg_per_cu=2),
 ])

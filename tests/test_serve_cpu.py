@@ -1,0 +1,138 @@
+"""Scheduler logic of the serving loop on the CPU: a fake executor backed by
+the oracle stands in for the GPU, so admission by HBM budget, FIFO order,
+frame chunking across iterations, rejection of bad requests and release of
+memory after a failure are checked without a device."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_1708_08619_amd import g3, serve, synth
+
+
+class _Done:
+    def query(self):
+        return True
+
+    def synchronize(self):
+        pass
+
+
+class OracleExecutor:
+    """Executes batches with the oracle; device buffers are numpy arrays."""
+
+    def __init__(self, oracle_mod, fail_on_call=None):
+        self.o = oracle_mod
+        self.calls = 0
+        self.fail_on_call = fail_on_call
+        self.live = 0
+
+    def upload(self, frames):
+        self.live += 1
+        return np.ascontiguousarray(frames, dtype=np.int32)
+
+    def new_hist(self, n):
+        return np.zeros(n, dtype=np.uint64)
+
+    def accumulate_batch(self, systems):
+        self.calls += 1
+        if self.fail_on_call == self.calls:
+            raise RuntimeError("injected executor failure")
+        for s in systems:
+            s["hist"] += self.o.hist(s["frames"], s["box"], s["rmax"], s["nbins"], s["layout"])
+
+    def start_fetch(self, hist):
+        return hist.copy()
+
+    def finish_fetch(self, tok):
+        return tok
+
+    def release(self, frames, hist):
+        self.live -= 1
+
+    def sync(self):
+        return g3.OK
+
+    def record(self):
+        return _Done()
+
+
+def _requests(n, seed=3):
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(n):
+        N = int(rng.integers(150, 260))
+        F = int(rng.integers(1, 7))
+        fr, box = synth.jittered_fcc(N, 0.8, 0.1, F, [seed, r])
+        rm = float(rng.choice([2.0, 2.5]))
+        out.append(serve.Request(r, fr, box, rm * 4096, int(round(rm / 0.05)),
+                                 int(rng.integers(0, 2)), arrival=0.0))
+    return out
+
+
+def test_results_and_budget(oracle_mod):
+    reqs = _requests(10)
+    fp = [serve.footprint_bytes(r, 2) for r in reqs]
+    budget = 2 * max(fp)                      # at most two requests fit at once
+    ex = OracleExecutor(oracle_mod)
+    srv = serve.Server(budget, frames_per_iter=2, executor=ex)
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    assert srv.peak_used <= budget
+    assert srv.used == 0 and ex.live == 0
+    for r in reqs:
+        want = oracle_mod.hist(r.frames, r.box, r.rmax, r.nbins, r.layout)
+        assert np.array_equal(r.result, want), r.rid
+    # FIFO admission, and queueing happened: someone was admitted after
+    # another finished
+    adm = [r.admitted for r in reqs]
+    assert adm == sorted(adm)
+    assert any(r.admitted >= min(q.done for q in reqs) for r in reqs)
+    assert srv.iterations >= max(r.n_frames for r in reqs) / 2
+
+
+def test_rejections(oracle_mod):
+    srv = serve.Server(1 << 20, frames_per_iter=2, executor=OracleExecutor(oracle_mod))
+    fr, box = synth.jittered_fcc(64, 0.8, 0.1, 2, [5, 0])
+    bad = fr.copy()
+    bad[0, 0, 0] = box[0]
+    with pytest.raises(g3.G3Error) as e:
+        srv.submit(serve.Request(0, bad, box, 2.0 * 4096, 40))
+    assert e.value.status == g3.EDOMAIN
+    with pytest.raises(g3.G3Error) as e:
+        srv.submit(serve.Request(1, fr, box, 0.5, 40))
+    assert e.value.status == g3.EINVAL
+    big = np.zeros((20, 3, 70000), dtype=np.int32)
+    with pytest.raises(g3.G3Error) as e:
+        srv.submit(serve.Request(2, big, [500000] * 3, 3.0 * 4096, 60))
+    assert e.value.status == g3.ENOMEM
+    assert not srv.queue
+
+
+def test_failure_releases_memory(oracle_mod):
+    reqs = _requests(4, seed=7)
+    ex = OracleExecutor(oracle_mod, fail_on_call=2)
+    srv = serve.Server(1 << 30, frames_per_iter=1, executor=ex)
+    for r in reqs:
+        srv.submit(r)
+    with pytest.raises(RuntimeError):
+        srv.drain()
+    assert srv.used == 0 and not srv.active and ex.live == 0
+    failed = [r for r in reqs if r.status == g3.EDEVICE]
+    assert failed
+
+
+def test_future_api(oracle_mod):
+    """submit -> handle, result(handle) -> histogram; a later request can be
+    collected first and an earlier one still completes."""
+    srv = serve.Server(1 << 30, frames_per_iter=1, executor=OracleExecutor(oracle_mod))
+    a_fr, a_box = synth.jittered_fcc(200, 0.8, 0.1, 3, [9, 0])
+    b_fr, b_box = synth.jittered_fcc(180, 0.8, 0.1, 1, [9, 1])
+    fa = srv.request(a_fr, a_box, 2.0 * 4096, 40)
+    fb = srv.request(b_fr, b_box, 2.5 * 4096, 50, g3.FULL)
+    hb = srv.result(fb)
+    assert np.array_equal(hb, oracle_mod.hist(b_fr, b_box, 2.5 * 4096, 50, g3.FULL))
+    ha = srv.result(fa)
+    assert np.array_equal(ha, oracle_mod.hist(a_fr, a_box, 2.0 * 4096, 40, g3.HALF))
+    assert fa.rid != fb.rid and srv.used == 0
