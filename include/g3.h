@@ -29,6 +29,13 @@
  *            nbins^3 bins (off-diagonal = half, diagonal lo == hi = 2 x half).
  *   hist     device pointer, uint64, g3_hist_len(nbins, layout) entries.  The
  *            library ADDS into it, so split or resumed runs sum exactly.
+ *   pair_hist  optional device pointer (NULL = not wanted), uint64, nbins
+ *            entries: the pair histogram behind g2(r) (the paper computes g2
+ *            beside g3 in the same pass, Sec. 3.3): for every frame and every
+ *            ordered pair (i, j), j != i, with |d_ij| < rmax, entry b(|d_ij|^2)
+ *            gains 1 -- the neighbour lists the triplet pass is built from,
+ *            counted.  ADDED into with device atomics, so several systems may
+ *            share one; it must not overlap any hist.
  *
  * Ownership and ordering: the caller owns frames, hist and all host arrays;
  * the plan owns its device scratch.  Work is queued on the plan's HIP stream
@@ -74,6 +81,7 @@ typedef struct {
     int32_t nbins;
     int32_t layout;
     uint64_t* hist;
+    uint64_t* pair_hist;     /* optional, may be NULL */
 } g3_system;
 
 /* Tuning knobs of the triplet kernel (chosen by g3_autotune or set by hand).
@@ -94,11 +102,13 @@ void g3_plan_destroy(g3_plan p);
 
 /* Plain form (the paper's per-frame pattern, Sec. 3.3, parallel g3 logic):
  * for each frame one sequence of kernel launches -- cell build, neighbour
- * lists, triplet binning, flush -- on the plan's stream, adding into hist.
+ * lists, triplet binning, flush -- on the plan's stream, adding into hist
+ * (and into pair_hist unless it is NULL).
  * Returns G3_EINVAL for invalid arguments without queuing any work. */
 g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames,
                         int32_t n_atoms, const int32_t box[3], double rmax,
-                        int32_t nbins, int32_t layout, uint64_t* hist);
+                        int32_t nbins, int32_t layout, uint64_t* hist,
+                        uint64_t* pair_hist);
 
 /* Batched form: every frame of every system in ONE launch sequence (batched
  * cell and neighbour builds, one persistent triplet kernel pulling work items
@@ -110,8 +120,9 @@ g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_sys
 
 /* Wait for the plan's queued work and report asynchronous errors:
  * G3_EDOMAIN if a frame held a coordinate outside the box (such frames add
- * nothing), G3_ENOMEM if a centre exceeded the per-centre neighbour capacity
- * (its frame adds nothing), G3_EDEVICE on a HIP error.  Frames whose
+ * nothing to hist or pair_hist), G3_ENOMEM if a centre exceeded the
+ * per-centre neighbour capacity (its frame adds nothing to hist; its pairs
+ * are still counted in pair_hist), G3_EDEVICE on a HIP error.  Frames whose
  * neighbour lists overflowed the batched scratch estimate are recomputed here
  * through the plain path before returning, so they are never lost. */
 g3_status g3_sync(g3_plan p);
@@ -141,6 +152,14 @@ g3_status g3_thresholds(double rmax, int32_t nbins, uint32_t* thr);
 g3_status g3_normalize(const uint64_t* hist, int32_t layout, int32_t nbins, double rmax,
                        int64_t n_frames, int32_t n_atoms, const int32_t box[3],
                        double* g3_out);
+
+/* Ideal-gas normalisation of the pair histogram (host, fp64):
+ *   g2[b] = H2[b] / E2[b],  E2[b] = n_frames * N (N-1) / V * 4 pi/3 (r_{b+1}^3 - r_b^3),
+ * r_b = b * rmax / nbins (ordered pairs, as pair_hist counts them).  Both
+ * arrays hold nbins entries. */
+g3_status g3_normalize_pairs(const uint64_t* pair_hist, int32_t nbins, double rmax,
+                             int64_t n_frames, int32_t n_atoms, const int32_t box[3],
+                             double* g2_out);
 
 /* W(a,b,c) for all bins (full layout, nbins^3 doubles, host). */
 g3_status g3_ideal_volume(int32_t nbins, double rmax, double* W_out);

@@ -47,7 +47,7 @@ def lib():
         L.g3o_hist_full.argtypes = [P, C.c_int, C.c_int, P, C.c_double, C.c_int, P, C.c_int,
                                     P, C.c_int]
         L.g3o_hist_full.restype = C.c_int
-        L.g3o_pair_hist.argtypes = [P, C.c_int, C.c_int, P, C.c_double, C.c_int, P]
+        L.g3o_pair_hist.argtypes = [P, C.c_int, C.c_int, P, C.c_double, C.c_int, P, C.c_int]
         L.g3o_pair_hist.restype = C.c_int
         L.g3o_fold_half.argtypes = [P, C.c_int, P]
         L.g3o_fold_half.restype = C.c_long
@@ -59,6 +59,8 @@ def lib():
         L.g3o_W_table.restype = None
         L.g3o_normalize.argtypes = [P, C.c_int, C.c_int, P, C.c_int64, C.c_int64, P, P]
         L.g3o_normalize.restype = None
+        L.g3o_normalize_pairs.argtypes = [P, C.c_int, C.c_double, C.c_int64, C.c_int64, P, P]
+        L.g3o_normalize_pairs.restype = None
         L.g3o_max_threads.argtypes = []
         L.g3o_max_threads.restype = C.c_int
         _lib = L
@@ -126,12 +128,12 @@ def hist(frames, box, rmax: float, nbins: int, layout: int, n_threads: int = 0,
     return half
 
 
-def pair_hist(frames, box, rmax: float, nbins: int) -> np.ndarray:
+def pair_hist(frames, box, rmax: float, nbins: int, n_threads: int = 0) -> np.ndarray:
     fr = _frames(frames)
     bx = np.ascontiguousarray(box, dtype=np.int32)
     H2 = np.zeros(nbins, dtype=np.uint64)
     if lib().g3o_pair_hist(_p(fr), fr.shape[0], fr.shape[2], _p(bx), float(rmax), int(nbins),
-                           _p(H2)):
+                           _p(H2), int(n_threads)):
         raise ValueError("oracle rejected the arguments")
     return H2
 
@@ -154,6 +156,16 @@ def normalize(H: np.ndarray, layout: int, nbins: int, rmax: float, n_frames: int
     bx = np.ascontiguousarray(box, dtype=np.int32)
     lib().g3o_normalize(_p(Hc), int(layout == 1), int(nbins), _p(W), int(n_frames),
                         int(n_atoms), _p(bx), _p(out))
+    return out
+
+
+def normalize_pairs(H2: np.ndarray, nbins: int, rmax: float, n_frames: int, n_atoms: int,
+                    box) -> np.ndarray:
+    h = np.ascontiguousarray(H2, dtype=np.uint64).reshape(-1)
+    out = np.zeros(int(nbins), dtype=np.float64)
+    bx = np.ascontiguousarray(box, dtype=np.int32)
+    lib().g3o_normalize_pairs(_p(h), int(nbins), float(rmax), int(n_frames), int(n_atoms),
+                              _p(bx), _p(out))
     return out
 
 

@@ -24,7 +24,9 @@
  *     squared lengths are below R2, H_full[b_ij][b_ik][b_jk] += 1;
  *   * the half layout counts unordered pairs: H_half[lo][hi][c] with
  *     lo <= hi is H_full[lo][hi][c] off the diagonal and H_full[a][a][c] / 2 on
- *     it (folded here from H_full so that symmetry is tested, not assumed).
+ *     it (folded here from H_full so that symmetry is tested, not assumed);
+ *   * the pair histogram H2[b] counts ordered pairs (i, j), j != i, with
+ *     b_ij = b (the g2 histogram computed beside g3).
  *
  * Integers are int64 throughout (no overflow concerns, no pre-tests).  The
  * only parallelism is an OpenMP split of centres with private histograms
@@ -186,24 +188,54 @@ int g3o_hist_full(const int32_t *frames, int n_frames, int n_atoms, const int32_
 }
 
 /* Pair histogram of ORDERED pairs (i, j), i != j, |mi(x_j - x_i)| < rmax,
- * binned like the triplet sides.  Adds into H2[nbins]. */
+ * binned like the triplet sides.  Adds into H2[nbins].  Centres are split
+ * over n_threads OpenMP threads (<= 0: the default) with private counts. */
 int g3o_pair_hist(const int32_t *frames, int n_frames, int n_atoms, const int32_t *box,
-                  double rmax, int nbins, uint64_t *H2)
+                  double rmax, int nbins, uint64_t *H2, int n_threads)
 {
     if (check_args(box, rmax, nbins, n_atoms)) return -1;
     uint64_t thr[G3O_MAX_NBINS + 1];
     if (g3o_thresholds(rmax, nbins, thr)) return -1;
-    nbr_t *nb = malloc(sizeof(nbr_t) * (size_t)(n_atoms > 0 ? n_atoms : 1));
-    if (!nb) return -1;
-    for (int f = 0; f < n_frames; f++) {
-        const int32_t *fr = frames + (size_t)f * 3 * n_atoms;
-        for (int i = 0; i < n_atoms; i++) {
-            int n = neighbours(fr, n_atoms, box, i, thr, nbins, nb);
-            for (int p = 0; p < n; p++) H2[nb[p].b] += 1;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#endif
+    uint64_t *priv = calloc((size_t)nt * nbins, sizeof(uint64_t));
+    if (!priv) return -1;
+    int err = 0;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        uint64_t *Ht = priv + (size_t)t * nbins;
+        nbr_t *nb = malloc(sizeof(nbr_t) * (size_t)(n_atoms > 0 ? n_atoms : 1));
+        if (!nb) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            err = 1;
         }
+        for (int f = 0; f < n_frames && nb; f++) {
+            const int32_t *fr = frames + (size_t)f * 3 * n_atoms;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+            for (int i = 0; i < n_atoms; i++) {
+                int n = neighbours(fr, n_atoms, box, i, thr, nbins, nb);
+                for (int p = 0; p < n; p++) Ht[nb[p].b] += 1;
+            }
+        }
+        free(nb);
     }
-    free(nb);
-    return 0;
+    if (!err)
+        for (int t = 0; t < nt; t++)
+            for (int b = 0; b < nbins; b++) H2[b] += priv[(size_t)t * nbins + b];
+    free(priv);
+    return err ? -1 : 0;
 }
 
 /* Half-layout index of (lo, hi, c), lo <= hi: rows lo hold hi = lo..nbins-1. */
@@ -374,6 +406,24 @@ void g3o_normalize(const uint64_t *H, int layout_full, int nbins, const double *
                     size_t x = half_index(a, b, c, nbins);
                     g3[x] = E > 0 ? (double)H[x] / E : 0.0;
                 }
+    }
+}
+
+/* g2(r) from the ordered pair histogram (the paper computes g2 beside g3,
+ * Sec. 3.3): an ideal gas puts N(N-1)/V ordered pairs per unit volume, so
+ * shell b, between r_b = b*dr and r_{b+1}, expects
+ * F * N(N-1)/V * (4 pi / 3)(r_{b+1}^3 - r_b^3). */
+void g3o_normalize_pairs(const uint64_t *H2, int nbins, double rmax, int64_t n_frames,
+                         int64_t n_atoms, const int32_t *box, double *g2)
+{
+    double V = (double)box[0] * (double)box[1] * (double)box[2];
+    double Nd = (double)n_atoms;
+    double dr = rmax / nbins;
+    for (int b = 0; b < nbins; b++) {
+        double r0 = dr * b, r1 = dr * (b + 1);
+        double shell = 4.0 * M_PI / 3.0 * (r1 * r1 * r1 - r0 * r0 * r0);
+        double E = (double)n_frames * Nd * (Nd - 1.0) / V * shell;
+        g2[b] = E > 0 ? (double)H2[b] / E : 0.0;
     }
 }
 

@@ -28,6 +28,7 @@ struct Sys {
     // inputs
     const int32_t* frames;   // [F][3][N]
     uint64_t* hist;          // output (added into)
+    uint64_t* pair_hist;     // [nbins] ordered pairs per bin (added into), or null
     int32_t F, N;
     int32_t box[3];
     int32_t nc[3];           // cells per axis; 1 means "whole axis, explicit minimum image"

@@ -396,6 +396,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
     const Geometry& g = P.g;
     s.frames = P.in.frames;
     s.hist = P.in.hist;
+    s.pair_hist = P.in.pair_hist;
     s.F = P.in.n_frames;
     s.N = g.N;
     for (int d = 0; d < 3; ++d) { s.box[d] = g.box[d]; s.nc[d] = g.nc[d]; }
@@ -855,6 +856,7 @@ g3_status drain(g3_plan p)
                 else if (v & kFlagPool) {
                     g3_system one = r.sys;
                     one.frames = r.sys.frames + (size_t)f * 3 * r.sys.n_atoms;
+                    one.pair_hist = nullptr;   // its pairs were counted in full already
                     one.n_frames = 1;
                     redo.push_back(one);
                 }
@@ -915,9 +917,19 @@ void g3_plan_destroy(g3_plan p)
     delete p;
 }
 
+// pair_hist of a overlapping the histogram of b (atomics beside plain stores)
+static bool overlaps(const g3_system& a, const g3_system& b)
+{
+    if (!a.pair_hist) return false;
+    const uintptr_t p0 = (uintptr_t)a.pair_hist, p1 = p0 + sizeof(uint64_t) * (size_t)a.nbins;
+    const uintptr_t h0 = (uintptr_t)b.hist,
+                    h1 = h0 + sizeof(uint64_t) * g3_hist_len(b.nbins, b.layout);
+    return p0 < h1 && h0 < p1;
+}
+
 g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames, int32_t n_atoms,
                         const int32_t box[3], double rmax, int32_t nbins, int32_t layout,
-                        uint64_t* hist)
+                        uint64_t* hist, uint64_t* pair_hist)
 {
     if (!p) return G3_EINVAL;
     g3_status st = check(n_atoms, box, rmax, nbins, layout);
@@ -932,7 +944,9 @@ g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames, int3
     s.nbins = nbins;
     s.layout = layout;
     s.hist = hist;
-    if (n_frames == 0 || n_atoms < 3) return G3_OK;
+    s.pair_hist = pair_hist;
+    if (n_frames == 0 || n_atoms < (pair_hist ? 2 : 3)) return G3_OK;
+    if (pair_hist && overlaps(s, s)) return G3_EINVAL;
     return run_plain(p, s, false);
 }
 
@@ -945,10 +959,11 @@ g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_sys
         g3_status st = check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
         if (st) return st;
         if (s.n_frames < 0) return G3_EINVAL;
-        if (s.n_frames == 0 || s.n_atoms < 3) continue;
+        if (s.n_frames == 0 || s.n_atoms < (s.pair_hist ? 2 : 3)) continue;
         if (!s.frames || !s.hist) return G3_EINVAL;
         for (const auto& o : live)
-            if (o.hist == s.hist) return G3_EINVAL;
+            if (o.hist == s.hist || overlaps(o, s) || overlaps(s, o)) return G3_EINVAL;
+        if (overlaps(s, s)) return G3_EINVAL;
         live.push_back(s);
     }
     if (live.empty()) return G3_OK;
@@ -1028,6 +1043,25 @@ g3_status g3_normalize(const uint64_t* hist, int32_t layout, int32_t nbins, doub
                 if (layout == G3_HALF && a == b) E *= 0.5;
                 g3_out[x] = E > 0 ? (double)hist[x] / E : 0.0;
             }
+    return G3_OK;
+}
+
+g3_status g3_normalize_pairs(const uint64_t* pair_hist, int32_t nbins, double rmax,
+                             int64_t n_frames, int32_t n_atoms, const int32_t box[3], double* g2_out)
+{
+    if (!pair_hist || !g2_out || !box) return G3_EINVAL;
+    if (nbins < 1 || nbins > G3_MAX_NBINS || !(rmax > 0) || n_frames < 0 || n_atoms < 0) return G3_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (box[d] <= 0) return G3_EINVAL;
+    const double V = (double)box[0] * (double)box[1] * (double)box[2];
+    const double n = (double)n_atoms;
+    const double pref = (double)n_frames * n * (n - 1.0) / V * (4.0 * M_PI / 3.0);
+    const double dr = rmax / nbins;
+    for (int b = 0; b < nbins; ++b) {
+        const double r0 = b * dr, r1 = (b + 1) * dr;
+        const double E = pref * (r1 * r1 * r1 - r0 * r0 * r0);
+        g2_out[b] = E > 0 ? (double)pair_hist[b] / E : 0.0;
+    }
     return G3_OK;
 }
 
@@ -1129,7 +1163,11 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
     uint64_t* scratch = nullptr;
     G3_TRY_HIP(hipMalloc((void**)&scratch, total * sizeof(uint64_t)));
     size_t o = 0;
-    for (int i = 0; i < n_systems; ++i) { sys[i].hist = scratch + o; o += len[i]; }
+    for (int i = 0; i < n_systems; ++i) {
+        sys[i].hist = scratch + o;
+        sys[i].pair_hist = nullptr;
+        o += len[i];
+    }
     std::vector<uint64_t> ref(total), got(total);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipEventCreate(&e0);

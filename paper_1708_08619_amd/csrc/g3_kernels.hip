@@ -206,7 +206,8 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     uint8_t* s_slab = s_tab + 8192;                                          // [256] bin -> slab
     E* s_buf = reinterpret_cast<E*>(s_slab + 256);                           // [waves][kWaveBuf]
     uint32_t* s_scnt = reinterpret_cast<uint32_t*>(s_buf + kBuildWaves * kWaveBuf);  // [waves][32]
-    int32_t* s_x = reinterpret_cast<int32_t*>(s_scnt + kBuildWaves * 32);
+    uint32_t* s_g2 = s_scnt + kBuildWaves * 32;                              // [256] pair bins
+    int32_t* s_x = reinterpret_cast<int32_t*>(s_g2 + 256);
     int32_t* s_y = s_x + stg_cap;
     int32_t* s_z = s_y + stg_cap;
     __shared__ Stencil st;
@@ -249,7 +250,21 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
         int q = 0;
         while (q + 1 < n_slabs && S.slab_lo[q + 1] <= b) ++q;
         s_slab[b] = (uint8_t)q;
+        s_g2[b] = 0u;
     }
+    // pair histogram (g2): accepted (centre, neighbour) pairs per bin, counted
+    // in LDS and flushed with uint64 atomics before any counter could wrap
+    uint64_t* const pair_hist = S.pair_hist;
+    uint64_t g2_pending = 0;   // upper bound on the counts held in s_g2
+    auto flush_g2 = [&]() {
+        for (int b = tid; b < nb; b += kBuildThreads) {
+            const uint32_t v = s_g2[b];
+            if (v) {
+                atomicAdd(reinterpret_cast<unsigned long long*>(pair_hist + b), (unsigned long long)v);
+                s_g2[b] = 0u;
+            }
+        }
+    };
     const int rx = ncx >= 3 ? 1 : 0, ry = ncy >= 3 ? 1 : 0, rz = ncz >= 3 ? 1 : 0;
     const int nst = (2 * rx + 1) * (2 * ry + 1) * (2 * rz + 1);
     const int home = nst / 2;   // (0,0,0) sits in the middle of the odd stencil grid
@@ -358,6 +373,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                     if (pos < (uint32_t)kWaveBuf) buf[pos] = e;
                     atomicAdd(&scnt[s_slab[b]], 1u);
+                    if (pair_hist) atomicAdd(&s_g2[b], 1u);
                 }
                 n += (uint32_t)__popcll(mask);
             }
@@ -420,6 +436,17 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             wave_sync();
         }
         __syncthreads();   // the next cell restages s_x/s_y/s_z and st
+        if (pair_hist) {       // uniform: cs and st are the same for every thread
+            g2_pending += (uint64_t)(c1 - c0) * (uint64_t)T;
+            if (g2_pending > 0x7fffffffull) {
+                flush_g2();
+                g2_pending = 0;
+            }
+        }
+    }
+    if (pair_hist && g2_pending) {
+        __syncthreads();
+        flush_g2();
     }
 }
 
@@ -863,7 +890,7 @@ void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n,
 size_t nbr_build_lds_bytes(int stg_cap)
 {
     return 256 * 4 + 8192 + 256 + (size_t)kBuildWaves * kWaveBuf * 16 + kBuildWaves * 32 * 4 +
-           (size_t)3 * stg_cap * 4;
+           256 * 4 + (size_t)3 * stg_cap * 4;
 }
 
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int stg_cap, bool wide,

@@ -33,7 +33,8 @@ class G3Error(RuntimeError):
 class System(C.Structure):
     _fields_ = [("frames", C.c_void_p), ("n_frames", C.c_int32), ("n_atoms", C.c_int32),
                 ("box", C.c_int32 * 3), ("rmax", C.c_double), ("nbins", C.c_int32),
-                ("layout", C.c_int32), ("hist", C.c_void_p)]
+                ("layout", C.c_int32), ("hist", C.c_void_p),
+                ("pair_hist", C.c_void_p)]
 
 
 class Tuning(C.Structure):
@@ -68,7 +69,7 @@ def lib():
     sig = {
         "g3_plan_create": ([C.POINTER(P), P], I32),
         "g3_plan_destroy": ([P], None),
-        "g3_accumulate": ([P, P, I32, I32, P, D, I32, I32, P], I32),
+        "g3_accumulate": ([P, P, I32, I32, P, D, I32, I32, P, P], I32),
         "g3_accumulate_batch": ([P, P, I32], I32),
         "g3_sync": ([P], I32),
         "g3_query": ([P], I32),
@@ -77,6 +78,7 @@ def lib():
         "g3_thresholds": ([D, I32, P], I32),
         "g3_normalize": ([P, I32, I32, D, I64, I32, P, P], I32),
         "g3_ideal_volume": ([I32, D, P], I32),
+        "g3_normalize_pairs": ([P, I32, D, I64, I32, P, P], I32),
         "g3_set_tuning": ([P, P], I32),
         "g3_get_tuning": ([P, P], I32),
         "g3_autotune": ([P, P, I32, P], I32),
@@ -148,6 +150,18 @@ def normalize(hist: np.ndarray, layout: int, nbins: int, rmax: float, n_frames: 
     return out
 
 
+def normalize_pairs(pair_hist: np.ndarray, nbins: int, rmax: float, n_frames: int,
+                    n_atoms: int, box) -> np.ndarray:
+    """g2 from the pair histogram (ordered pairs), fp64 on the host."""
+    h = np.ascontiguousarray(pair_hist, dtype=np.uint64).reshape(-1)
+    if h.shape[0] != int(nbins):
+        raise ValueError("pair histogram length does not match nbins")
+    out = np.zeros(h.shape[0], dtype=np.float64)
+    _check(lib().g3_normalize_pairs(_np_ptr(h), int(nbins), float(rmax), int(n_frames),
+                                    int(n_atoms), _box(box), _np_ptr(out)), "g3_normalize_pairs")
+    return out
+
+
 def strerror(status: int) -> str:
     return _strerror(status)
 
@@ -197,7 +211,8 @@ class Plan:
         self.close()
 
     # -- g3_accumulate: the plain per-frame form
-    def accumulate(self, frames, box, rmax: float, nbins: int, layout: int, hist):
+    def accumulate(self, frames, box, rmax: float, nbins: int, layout: int, hist,
+                   pair_hist=None):
         F, three, N = (int(x) for x in frames.shape)
         if three != 3:
             raise ValueError("frames must be [n_frames, 3, n_atoms]")
@@ -205,7 +220,8 @@ class Plan:
             raise ValueError("hist has the wrong length")
         _check(lib().g3_accumulate(self._h, _dev_ptr(frames, "int32", "frames"), F, N, _box(box),
                                    float(rmax), int(nbins), int(layout),
-                                   _dev_ptr(hist, "uint64", "hist")), "g3_accumulate")
+                                   _dev_ptr(hist, "uint64", "hist"),
+                                   _pair_ptr(pair_hist, nbins)), "g3_accumulate")
 
     @staticmethod
     def _systems(systems: Sequence[dict]):
@@ -225,6 +241,7 @@ class Plan:
             arr[i].nbins = int(s["nbins"])
             arr[i].layout = int(s["layout"])
             arr[i].hist = _dev_ptr(h, "uint64", "hist")
+            arr[i].pair_hist = _pair_ptr(s.get("pair_hist"), s["nbins"])
         return arr
 
     # -- g3_accumulate_batch: one graph launch for many systems
@@ -274,6 +291,19 @@ class Plan:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().g3_kernel_time(self._h, C.byref(ms), C.byref(n)), "g3_kernel_time")
         return float(ms.value), int(n.value)
+
+
+def _pair_ptr(pair_hist, nbins: int):
+    if pair_hist is None:
+        return None
+    if pair_hist.numel() != int(nbins):
+        raise ValueError("pair_hist must hold nbins entries")
+    return _dev_ptr(pair_hist, "uint64", "pair_hist")
+
+
+def new_pair_hist(nbins: int, device="cuda"):
+    import torch
+    return torch.zeros(int(nbins), dtype=torch.uint64, device=device)
 
 
 def new_hist(nbins: int, layout: int, device="cuda"):

@@ -107,3 +107,14 @@ def test_normalize_vs_oracle(oracle_mod, layout):
 def test_normalize_rejects_bad_length():
     with pytest.raises(ValueError):
         g3.normalize(np.zeros(10, dtype=np.uint64), g3.HALF, 5, 100.0, 1, 10, [1000] * 3)
+
+
+def test_normalize_pairs_vs_oracle(oracle_mod):
+    nb, rmax, F, N, box = 60, 12288.0, 5, 65536, [174356] * 3
+    rng = np.random.default_rng(21)
+    H2 = rng.integers(0, 1 << 40, size=nb, dtype=np.uint64)
+    got = g3.normalize_pairs(H2, nb, rmax, F, N, box)
+    want = oracle_mod.normalize_pairs(H2, nb, rmax, F, N, box)
+    assert np.max(np.abs(got / want - 1.0)) < 1e-12
+    with pytest.raises(ValueError):
+        g3.normalize_pairs(H2[:10], nb, rmax, F, N, box)

@@ -238,3 +238,63 @@ def test_ideal_gas_g3_is_one(oracle_mod):
     zt = (tot.mean() - E1.sum()) / (tot.std(ddof=1) / math.sqrt(F))
     assert abs(zt) < 5.0
     assert abs(tot.mean() / E1.sum() - 1) < 0.02
+
+
+# ---------------------------------------------------------------- g2 (pair histogram)
+@pytest.mark.parametrize("seed", range(4))
+def test_pair_hist_brute_force(oracle_mod, seed):
+    """Ordered pairs per bin against a Fraction-exact minimum-image count."""
+    rng = np.random.default_rng(300 + seed)
+    box = [int(x) for x in rng.integers(300, 700, size=3)]
+    rmax = float(rng.uniform(min(box) / 5.0, min(box) / 2 - 1))
+    nbins = int(rng.integers(3, 9))
+    N = int(rng.integers(6, 30))
+    fr = _random_system(rng, N, box, F=2)
+    want = np.zeros(nbins, dtype=np.uint64)
+    for f in range(fr.shape[0]):
+        for i in range(N):
+            for j in range(N):
+                if i == j:
+                    continue
+                d = [refs.min_image(int(fr[f, a, j]) - int(fr[f, a, i]), box[a]) for a in range(3)]
+                b = refs.frac_bin(sum(x * x for x in d), rmax, nbins)
+                if b >= 0:
+                    want[b] += 1
+    assert np.array_equal(oracle_mod.pair_hist(fr, box, rmax, nbins), want)
+
+
+@pytest.mark.parametrize("kind", ["fcc", "diamond"])
+def test_pair_hist_perfect_lattices(oracle_mod, kind):
+    """Perfect crystals: every site sees the same shells, so H2 = N x the
+    lattice vectors per bin."""
+    if kind == "fcc":
+        n = 4
+        L = synth.cubic_lattice_box(256, 0.8, synth.LJ_UNIT_PER_SIGMA, n, 2 * n)
+        a = L // n
+        sites, vec = synth.fcc_sites(n, a), refs.fcc_vectors(a, 2.5 * 4096)
+        rmax, nbins = 2.5 * 4096, 50
+    else:
+        n = 8
+        L = synth.cubic_lattice_box(4096, 33.4, synth.WATER_UNIT_PER_NM, n, 4 * n)
+        a = L // n
+        rmax, nbins = 0.6 * 65536, 60
+        sites, vec = synth.diamond_sites(n, a), refs.diamond_vectors(a, rmax)
+    fr = synth.lattice_frames(sites, len(sites), [L] * 3, 0.0, 1, 0)
+    b = refs._bins_np((vec.astype(np.int64) ** 2).sum(-1), rmax, nbins)
+    want = np.bincount(b[b >= 0], minlength=nbins).astype(np.uint64) * np.uint64(len(sites))
+    got = oracle_mod.pair_hist(fr, [L] * 3, rmax, nbins)
+    assert np.array_equal(got, want) and got.sum() > 0
+
+
+def test_ideal_gas_g2_is_one(oracle_mod):
+    """Uniform positions: E[H2[b]] = F N(N-1)/V x shell volume, so g2 -> 1
+    (checked per bin against frame-to-frame standard errors)."""
+    N, F, nbins, L, rmax = 400, 40, 8, 12000, 5000.0
+    w = synth.ideal_gas(N, [L, L, L], F, rmax, nbins, layout=1, seed=(synth.SEED_BASE, 9))
+    per = np.stack([oracle_mod.pair_hist(w.frames[f:f + 1], w.box, rmax, nbins).astype(np.float64)
+                    for f in range(F)])
+    g = oracle_mod.normalize_pairs(per.sum(0).astype(np.uint64), nbins, rmax, F, N, w.box)
+    sem_rel = per.std(0, ddof=1) / math.sqrt(F) / np.maximum(per.mean(0), 1e-9)
+    live = per.mean(0) > 20
+    assert live.sum() >= nbins - 1
+    assert np.all(np.abs(g[live] - 1.0) < 5 * sem_rel[live] + 1e-3), g
