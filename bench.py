@@ -29,8 +29,11 @@ sys.path.insert(0, ROOT)
 # Algorithmic int32 operations of the method (see the design notes):
 #   per candidate pair (centre, unordered {j,k} within rmax of the centre):
 #     d_jk = d_ik - d_ij (3 sub), |d_jk|^2 (3 mul + 2 add), compare with R2 (1)
-#   per binned triplet: exact bin of |d_jk|^2 (table + compare: 2),
+#   per histogram increment: exact bin of |d_jk|^2 (table + compare: 2),
 #     histogram address (1), increment (1)
+# In the default enumeration a candidate pair is one of the centre's
+# neighbours ranked above it, and one increment stands for one triangle
+# (three triplets binned, added by the expansion).
 OPS_PER_CANDIDATE = 9
 OPS_PER_BINNED = 4
 # int32 VALU peak of MI355X: 256 CUs x 64 lanes/clk x 2.4 GHz
@@ -45,6 +48,8 @@ def parse():
     ap.add_argument("--frames", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-per-centre", action="store_true",
+                    help="skip timing the per-centre enumeration beside the default")
     ap.add_argument("--cpu-frames", type=int, default=8,
                     help="frames of the workload the CPU oracle processes (all centres)")
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -122,13 +127,30 @@ def main():
         plain = {"value": binned / plain_s / 1e9, "ms_per_step": plain_s * 1e3,
                  "triplet_kernel_ms_per_frame": pk_ms}
 
-    ops = OPS_PER_CANDIDATE * cand + OPS_PER_BINNED * binned
+    tri_once = plan.get_tuning()["per_centre"] != 1
+    increments = binned // 3 if tri_once else binned
+    ops = OPS_PER_CANDIDATE * cand + OPS_PER_BINNED * increments
     achieved = ops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": INT32_VALU_PEAK_TOPS,
                 "unit": "Tops/s (int32)", "frac": achieved / INT32_VALU_PEAK_TOPS if achieved else None,
                 "traffic": traffic_per_launch(), "traffic_unit": "bytes per launch",
                 "kernel": "k_triplet", "kernel_ms": kern_ms,
-                "candidates_per_launch": cand, "binned_per_launch": binned}
+                "candidates_per_launch": cand, "increments_per_launch": increments}
+
+    # the paper's enumeration (every centre's unordered pairs) for comparison
+    per_centre = None
+    if not args.no_per_centre:
+        plan.set_tuning(per_centre=1)
+        pc_s = timed(lambda: plan.accumulate_batch([system]), max(3, args.steps // 2), 1)
+        plan.kernel_time_reset(True)
+        c0 = plan.candidates()
+        timed(lambda: plan.accumulate_batch([system]), 2, 0)
+        pc_ms, pc_n = plan.kernel_time()
+        pc_cand = (plan.candidates() - c0) // max(pc_n, 1)
+        plan.kernel_time_reset(False)
+        plan.set_tuning()
+        per_centre = {"value": binned / pc_s / 1e9, "ms_per_step": pc_s * 1e3,
+                      "triplet_kernel_ms": pc_ms, "candidates_per_launch": pc_cand}
 
     served = None
     if args.serve_requests > 0:
@@ -149,9 +171,11 @@ def main():
         "config": {"workload": "lj65536_jittered_fcc", "n_atoms": w.n_atoms,
                    "n_frames": w.n_frames, "rho_sigma3": 0.85, "jitter_sigma": 0.15,
                    "rmax_sigma": 3.0, "nbins": w.nbins, "layout": "half",
-                   "form": "batched (one hipGraph launch per step)"},
+                   "form": "batched (one hipGraph launch per step)",
+                   "enumeration": "triangle-once" if tri_once else "per-centre"},
         "triplets_binned_per_step": binned,
         "plain": plain,
+        "per_centre_enumeration": per_centre,
         "served": served,
         "roofline": roofline,
         "cpu_baseline": cpu,

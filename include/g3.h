@@ -91,6 +91,11 @@ typedef struct {
                                 (the r12 slab size); slabs are whole rows lo */
     int32_t centres_per_item;/* centres in one work item of the persistent kernel */
     int32_t wg_per_cu;       /* resident workgroups per compute unit (1 or 2) */
+    int32_t per_centre;      /* 1: evaluate every centre's unordered neighbour pairs
+                                (the paper's loop, each triangle met at all three
+                                atoms); default: meet each triangle once, at its
+                                lowest-ranked atom, and expand it exactly into the
+                                three histogram entries it owes */
 } g3_tuning;
 
 /* Create a plan bound to a HIP stream (hipStream_t passed as void*, NULL =

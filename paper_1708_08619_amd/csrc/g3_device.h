@@ -29,6 +29,9 @@ struct Sys {
     const int32_t* frames;   // [F][3][N]
     uint64_t* hist;          // output (added into)
     uint64_t* pair_hist;     // [nbins] ordered pairs per bin (added into), or null
+    uint64_t* tri;           // triangle-once mode: [half bins] triangles counted from their
+                             // lowest-ranked atom, expanded into hist at the end; null:
+                             // every centre's pairs are counted into hist directly
     int32_t F, N;
     int32_t box[3];
     int32_t nc[3];           // cells per axis; 1 means "whole axis, explicit minimum image"
@@ -128,6 +131,7 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
                       bool one_step, hipStream_t s);
 void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
+void launch_expand(const Sys* sys, int n_sys, int max_nbins, hipStream_t s);
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes);
 
 }  // namespace g3

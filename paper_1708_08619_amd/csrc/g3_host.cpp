@@ -294,6 +294,7 @@ hipError_t grow(void** ptr, size_t* have, size_t need)
 
 struct Tun {
     int hb_max, cb, wg_per_cu;
+    bool tri_once;
 };
 
 Tun effective(const g3_plan p)
@@ -301,6 +302,7 @@ Tun effective(const g3_plan p)
     Tun t;
     t.cb = p->tun.centres_per_item > 0 ? std::min(p->tun.centres_per_item, kTripletThreads) : 512;
     t.wg_per_cu = p->tun.wg_per_cu == 2 ? 2 : 1;
+    t.tri_once = p->tun.per_centre != 1;
     const size_t budget = kLdsPerCU / t.wg_per_cu - 256;   // static shared memory headroom
     const size_t fixed = triplet_lds_bytes(0, t.cb, kTabMax);
     int hb = budget > fixed ? (int)((budget - fixed) / 4) : 0;
@@ -316,6 +318,8 @@ struct Prepared {
     g3_system in;
     size_t off_cell_count, off_cell_start, off_atom_cell, off_atom_rank, off_sorted, off_nbr_off,
         off_nbr_cnt, off_cursor, off_slab_j, off_pool, off_thr, off_tab;
+    size_t off_tri;          // triangle-once counts (half layout, uint64), if tri_once
+    bool tri_once;
     int64_t pool_cap;
     int per_frame;
 };
@@ -342,7 +346,10 @@ g3_status prepare(const g3_system& s, int hb_max, Prepared& P)
 }
 
 // Lay out scratch for a list of prepared systems; returns total bytes.
-size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case, size_t base)
+// Triangle-once buffers of all systems are laid out last, back to back, so one
+// fill clears them.
+size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case, size_t base,
+                      bool tri_once)
 {
     size_t o = base;
     // unused tails of the per-wave pool chunks of the neighbour build
@@ -386,7 +393,20 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         P.pool_cap = std::min<int64_t>(P.pool_cap, max_cap);
         o = align_up(o + F * (size_t)(P.pool_cap + kPoolPad) * (g.wide ? 16 : 8), 256);
     }
+    for (auto& P : ps) {
+        P.tri_once = tri_once;
+        P.off_tri = o;
+        if (tri_once) o = align_up(o + g3_hist_len(P.g.nbins, G3_HALF) * sizeof(uint64_t), 256);
+    }
     return o;
+}
+
+// Byte range [begin, end) of the triangle-once buffers of a laid-out group.
+std::pair<size_t, size_t> tri_range(const std::vector<Prepared>& ps)
+{
+    if (ps.empty() || !ps[0].tri_once) return {0, 0};
+    const Prepared& L = ps.back();
+    return {ps[0].off_tri, L.off_tri + g3_hist_len(L.g.nbins, G3_HALF) * sizeof(uint64_t)};
 }
 
 Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
@@ -397,6 +417,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
     s.frames = P.in.frames;
     s.hist = P.in.hist;
     s.pair_hist = P.in.pair_hist;
+    s.tri = P.tri_once ? reinterpret_cast<uint64_t*>(arena + P.off_tri) : nullptr;
     s.F = P.in.n_frames;
     s.N = g.N;
     for (int d = 0; d < 3; ++d) { s.box[d] = g.box[d]; s.nc[d] = g.nc[d]; }
@@ -599,7 +620,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     st = prepare(s, tn.hb_max, ps[0]);
     if (st) return st;
     const size_t tables_base = 0;
-    const size_t need = layout_scratch(ps, false, worst_case, 0);
+    const size_t need = layout_scratch(ps, false, worst_case, 0, tn.tri_once);
     G3_TRY_HIP(grow(&p->arena, &p->arena_n, need));
     st = set_lds_limits(p);
     if (st) return st;
@@ -655,6 +676,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     a.n_segs = S;
     a.total_items = items_per_frame;
     const int N = P.g.N;
+    const auto tri = tri_range(ps);
     launch_zero_u32((uint32_t*)((char*)p->arena + P.off_cursor), (size_t)F * kCursorStride, p->stream);
     for (int f = 0; f < F; ++f) {
         const Job* j = djobs + f;
@@ -664,12 +686,15 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
         launch_cell_scatter(dsys, j, 1, N, p->stream);
         launch_nbr_build(dsys, j, 1, P.g.ncell, kStageCap, P.g.wide != 0, P.g.one_step != 0, p->stream);
         launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
+        if (tri.second > tri.first)
+            launch_zero_u32((uint32_t*)((char*)p->arena + tri.first), (tri.second - tri.first) / 4, p->stream);
         a.segs = dsegs + (size_t)f * S;
         hipEvent_t e0;
         timing_begin(p, &e0);
         launch_triplet(a, P.g.wide != 0, P.g.one_step != 0, n_wg, p->stream);
         timing_end(p, e0);
         launch_reduce(a, tn.hb_max, S, p->stream);
+        if (tn.tri_once) launch_expand(dsys, 1, P.g.nbins, p->stream);
     }
     G3_TRY_HIP(hipGetLastError());
     return G3_OK;
@@ -697,7 +722,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             ps.push_back(std::move(P));
         }
         if (ps.empty()) continue;
-        const size_t need = layout_scratch(ps, true, false, 0);
+        const size_t need = layout_scratch(ps, true, false, 0, tn.tri_once);
         // flags for every frame of the group
         int total_f = 0;
         for (auto& P : ps) total_f += P.in.n_frames;
@@ -779,6 +804,12 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
                             (size_t)P.g.ncell * (size_t)P.in.n_frames});
             zero.push_back({(uint32_t*)((char*)p->arena + P.off_cursor), (size_t)P.in.n_frames * kCursorStride});
         }
+        const auto tri = tri_range(ps);
+        if (tri.second > tri.first)
+            zero.push_back({(uint32_t*)((char*)p->arena + tri.first), (tri.second - tri.first) / 4});
+        int max_nb = 0;
+        for (auto& P : ps) max_nb = std::max(max_nb, P.g.nbins);
+        const int n_sys = (int)ps.size();
 
         auto enqueue = [&](hipStream_t sm) {
             for (auto& z : zero) launch_zero_u32(z.first, z.second, sm);
@@ -789,6 +820,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_nbr_build(dsys, djobs, nj, max_cells, kStageCap, wide, one_step, sm);
             launch_triplet(a, wide, one_step, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
+            if (tn.tri_once) launch_expand(dsys, n_sys, max_nb, sm);
         };
         if (p->timing) {
             // timed runs launch directly so that events bracket the kernel
@@ -803,6 +835,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_triplet(a, wide, one_step, n_wg, p->stream);
             timing_end(p, e0);
             launch_reduce(a, max_hb, ns, p->stream);
+            if (tn.tri_once) launch_expand(dsys, n_sys, max_nb, p->stream);
             G3_TRY_HIP(hipGetLastError());
             continue;
         }
@@ -1068,7 +1101,7 @@ g3_status g3_normalize_pairs(const uint64_t* pair_hist, int32_t nbins, double rm
 g3_status g3_set_tuning(g3_plan p, const g3_tuning* t)
 {
     if (!p || !t) return G3_EINVAL;
-    if (t->wg_per_cu > 2 || t->centres_per_item > kTripletThreads) return G3_EINVAL;
+    if (t->wg_per_cu > 2 || t->centres_per_item > kTripletThreads || t->per_centre > 1) return G3_EINVAL;
     p->tun = *t;
     return G3_OK;
 }
@@ -1080,6 +1113,7 @@ g3_status g3_get_tuning(g3_plan p, g3_tuning* t)
     t->lds_hist_bins = tn.hb_max;
     t->centres_per_item = tn.cb;
     t->wg_per_cu = tn.wg_per_cu;
+    t->per_centre = tn.tri_once ? 0 : 1;
     return G3_OK;
 }
 
@@ -1116,11 +1150,12 @@ g3_status g3_kernel_time_reset(g3_plan p, int32_t enable)
     return G3_OK;
 }
 
-// Workload signature for the autotuner cache: per system the entry format,
-// nbins, layout, log2 of N and of the expected neighbour count, and frames.
-static std::string tune_key(const g3_system* sys, int n)
+// Workload signature for the autotuner cache: the enumeration mode, then per
+// system the entry format, nbins, layout, log2 of N and of the expected
+// neighbour count, and frames.
+static std::string tune_key(const g3_system* sys, int n, int per_centre)
 {
-    std::string k;
+    std::string k = per_centre == 1 ? "pc;" : "to;";
     for (int i = 0; i < n; ++i) {
         const g3_system& s = sys[i];
         const double V = (double)s.box[0] * s.box[1] * s.box[2];
@@ -1143,7 +1178,7 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
         if (st) return st;
         if (s.n_frames < 0 || (s.n_frames > 0 && !s.frames)) return G3_EINVAL;
     }
-    const std::string key = tune_key(systems, n_systems);
+    const std::string key = tune_key(systems, n_systems, p->tun.per_centre);
     auto hit = p->tuned.find(key);
     if (hit != p->tuned.end()) {
         p->tun = hit->second;
@@ -1184,6 +1219,7 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
         for (int ci = 0; ci < 3 && st == G3_OK; ++ci)
             for (int fi = 0; fi < 2 && st == G3_OK; ++fi) {
                 g3_tuning t{};
+                t.per_centre = saved.per_centre;
                 t.wg_per_cu = wgs[wi];
                 t.centres_per_item = cbs[ci];
                 p->tun = t;

@@ -161,9 +161,13 @@ __global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sy
 // C <= 46340, products on the 24-bit multiplier (|d| < 2^16).
 namespace {
 
+// The stencil of a cell, its cells ordered by cell index: atoms are stored
+// cell by cell, so stencil positions t = 0..T-1 run in increasing sorted
+// index, and "atom j ranks above the centre" is simply t > tself.
 struct Stencil {
     int n;                 // stencil cells
-    int start[27], pre[28];
+    int home;              // position of the centre's own cell
+    int start[27], pre[28], cnt[27];
     int shx[27], shy[27], shz[27];
 };
 
@@ -255,6 +259,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     // pair histogram (g2): accepted (centre, neighbour) pairs per bin, counted
     // in LDS and flushed with uint64 atomics before any counter could wrap
     uint64_t* const pair_hist = S.pair_hist;
+    const bool tri_once = S.tri != nullptr;
+    // triangle-once lists hold each unordered pair once (at its lower-ranked
+    // atom): it stands for two ordered pairs
+    const uint32_t pair_inc = tri_once ? 2u : 1u;
     uint64_t g2_pending = 0;   // upper bound on the counts held in s_g2
     auto flush_g2 = [&]() {
         for (int b = tid; b < nb; b += kBuildThreads) {
@@ -272,31 +280,41 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     for (int cell = blockIdx.x; cell < ncell; cell += gridDim.x) {
         const int c0 = cs[cell], c1 = cs[cell + 1];
         if (c0 == c1) continue;   // uniform over the workgroup
-        // stencil table: lane e of wave 0 fills entry e, then a prefix sum
+        // stencil table: lane e of wave 0 takes stencil offset e and stores it
+        // at the rank of its cell index (the cells are distinct), then a
+        // prefix sum of the counts in that order
         if (wave == 0) {
-            int cnt_e = 0;
+            int c = 0x7fffffff, a = 0, cnt_e = 0, shx = 0, shy = 0, shz = 0;
             if (lane < nst) {
                 const int kx = cell % ncx, ky = (cell / ncx) % ncy, kz = cell / (ncx * ncy);
                 const int ox = lane % (2 * rx + 1) - rx;
                 const int oy = (lane / (2 * rx + 1)) % (2 * ry + 1) - ry;
                 const int oz = lane / ((2 * rx + 1) * (2 * ry + 1)) - rz;
-                int x = kx + ox, y = ky + oy, z = kz + oz, shx = 0, shy = 0, shz = 0;
+                int x = kx + ox, y = ky + oy, z = kz + oz;
                 if (x < 0) { x += ncx; shx = -Lx; } else if (x >= ncx) { x -= ncx; shx = Lx; }
                 if (y < 0) { y += ncy; shy = -Ly; } else if (y >= ncy) { y -= ncy; shy = Ly; }
                 if (z < 0) { z += ncz; shz = -Lz; } else if (z >= ncz) { z -= ncz; shz = Lz; }
-                const int c = (z * ncy + y) * ncx + x;
-                const int a = cs[c];
+                c = (z * ncy + y) * ncx + x;
+                a = cs[c];
                 cnt_e = cs[c + 1] - a;
-                st.start[lane] = a;
-                st.shx[lane] = shx; st.shy[lane] = shy; st.shz[lane] = shz;
             }
-            int incl = cnt_e;
+            int rank = 0;
+            for (int l = 0; l < nst; ++l) rank += (__shfl(c, l, 64) < c) ? 1 : 0;
+            if (lane < nst) {
+                st.start[rank] = a;
+                st.cnt[rank] = cnt_e;
+                st.shx[rank] = shx; st.shy[rank] = shy; st.shz[rank] = shz;
+                if (lane == home) st.home = rank;
+            }
+            wave_sync();
+            const int v = lane < nst ? st.cnt[lane] : 0;
+            int incl = v;
 #pragma unroll
             for (int d = 1; d < 32; d <<= 1) {
                 const int y = __shfl_up(incl, d, 64);
                 if (lane >= d) incl += y;
             }
-            if (lane < nst) st.pre[lane] = incl - cnt_e;
+            if (lane < nst) st.pre[lane] = incl - v;
             if (lane == nst - 1) { st.pre[nst] = incl; st.n = nst; }
         }
         __syncthreads();
@@ -320,7 +338,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
 
         for (int ci = c0 + wave; ci < c1; ci += kBuildWaves) {
             // the centre is part of its own stencil (home cell, no shift)
-            const int tself = st.pre[home] + (ci - st.start[home]);
+            const int hr = st.home;
+            const int tself = st.pre[hr] + (ci - st.start[hr]);
+            // triangle-once mode keeps only the atoms ranked above the centre
+            const int t_first = tri_once ? tself + 1 : 0;
             const int xi = staged ? s_x[tself] : X[ci];
             const int yi = staged ? s_y[tself] : Y[ci];
             const int zi = staged ? s_z[tself] : Z[ci];
@@ -363,7 +384,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             wave_sync();
             // the one evaluation pass: count per slab, compact into the buffer
             uint32_t n = 0;
-            for (int t0 = 0; t0 < T; t0 += 64) {
+            for (int t0 = t_first; t0 < T; t0 += 64) {
                 E e;
                 int b = 0;
                 const bool acc = test(t0 + lane, e, b);
@@ -373,7 +394,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                     if (pos < (uint32_t)kWaveBuf) buf[pos] = e;
                     atomicAdd(&scnt[s_slab[b]], 1u);
-                    if (pair_hist) atomicAdd(&s_g2[b], 1u);
+                    if (pair_hist) atomicAdd(&s_g2[b], pair_inc);
                 }
                 n += (uint32_t)__popcll(mask);
             }
@@ -423,7 +444,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     P[atomicAdd(&scnt[s_slab[bin_of_entry(v)]], 1u)] = v;
                 }
             } else {
-                for (int t0 = 0; t0 < T; t0 += 64) {
+                for (int t0 = t_first; t0 < T; t0 += 64) {
                     E e;
                     int b = 0;
                     if (test(t0 + lane, e, b)) P[atomicAdd(&scnt[s_slab[b]], 1u)] = e;
@@ -437,7 +458,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
         }
         __syncthreads();   // the next cell restages s_x/s_y/s_z and st
         if (pair_hist) {       // uniform: cs and st are the same for every thread
-            g2_pending += (uint64_t)(c1 - c0) * (uint64_t)T;
+            g2_pending += (uint64_t)(c1 - c0) * (uint64_t)T * pair_inc;
             if (g2_pending > 0x7fffffffull) {
                 flush_g2();
                 g2_pending = 0;
@@ -621,6 +642,9 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             // bins with one ballot.
             const Sys& S = A.sys[G.sys];
             const int nb = S.nbins, RL = G.rl;
+            // triangle-once counts go to the half-layout triangle buffer
+            uint64_t* const out = S.tri ? S.tri : S.hist;
+            const int layout = S.tri ? 0 : S.layout;
             for (int x0 = wave * 64; x0 < G.hb; x0 += kTripletThreads) {
                 const int x = x0 + lane;
                 const uint32_t v = x < G.hb ? s_hist[x] : 0u;
@@ -629,15 +653,15 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 const int a = G.lo0 + x / RL, rem = x - (x / RL) * RL;
                 const int b = G.lo0 + rem / nb, c = rem - (rem / nb) * nb;
                 const int lo = min(a, b), hi = max(a, b);
-                if (S.layout == 0) {
+                if (layout == 0) {
                     const size_t h = ((size_t)lo * nb - (size_t)lo * (lo - 1) / 2 + (hi - lo)) * nb + c;
-                    atomicAdd((unsigned long long*)&S.hist[h], (unsigned long long)v);
+                    atomicAdd((unsigned long long*)&out[h], (unsigned long long)v);
                 } else if (lo == hi) {
-                    atomicAdd((unsigned long long*)&S.hist[((size_t)lo * nb + lo) * nb + c], 2ull * v);
+                    atomicAdd((unsigned long long*)&out[((size_t)lo * nb + lo) * nb + c], 2ull * v);
                 } else {
-                    atomicAdd((unsigned long long*)&S.hist[((size_t)lo * nb + hi) * nb + c],
+                    atomicAdd((unsigned long long*)&out[((size_t)lo * nb + hi) * nb + c],
                               (unsigned long long)v);
-                    atomicAdd((unsigned long long*)&S.hist[((size_t)hi * nb + lo) * nb + c],
+                    atomicAdd((unsigned long long*)&out[((size_t)hi * nb + lo) * nb + c],
                               (unsigned long long)v);
                 }
             }
@@ -853,13 +877,54 @@ __global__ void __launch_bounds__(256) k_reduce(TripletArgs A)
             if (mirror) sum += sl[xm];
         }
     if (sum == 0) return;
-    if (S.layout == 0) {
+    if (S.tri) {
+        S.tri[((size_t)a * nb - (size_t)a * (a - 1) / 2 + (b - a)) * nb + c] += sum;
+    } else if (S.layout == 0) {
         S.hist[((size_t)a * nb - (size_t)a * (a - 1) / 2 + (b - a)) * nb + c] += sum;
     } else if (a == b) {
         S.hist[((size_t)a * nb + a) * nb + c] += 2 * sum;
     } else {
         S.hist[((size_t)a * nb + b) * nb + c] += sum;
         S.hist[((size_t)b * nb + a) * nb + c] += sum;
+    }
+}
+
+// Triangle-once expansion.  A triangle whose sides fall in bins P, Q (at its
+// lowest-ranked atom) and R (opposite) was counted once, at T(lo, hi, R) with
+// lo = min(P, Q), hi = max(P, Q).  Seen from each of its three atoms it is
+// one unordered pair with the third side opposite, so it owes the half
+// histogram one count at each of
+//     (lo, hi, R),  (min(lo, R), max(lo, R), hi),  (min(hi, R), max(hi, R), lo).
+// Gathered per output bin (x <= y, z), the sources are
+//     T(x,y,z) + [x<=z] T(x,z,y) + [x!=y][y<=z] T(y,z,x)
+//              + [z<=x] T(z,x,y) + [x!=y][z<=y] T(z,y,x),
+// the [x!=y] terms dropping the second copy of a source that coincides with
+// the first.  One thread per output bin (full bins (a,b) and (b,a) each
+// recompute their half value), adding into the caller's histogram.
+__global__ void __launch_bounds__(256) k_expand(const Sys* __restrict__ sys)
+{
+    const Sys& S = sys[blockIdx.y];
+    if (!S.tri) return;
+    const int nb = S.nbins;
+    const size_t nb3 = (size_t)nb * nb * nb;
+    const uint64_t* __restrict__ T = S.tri;
+    auto half = [nb](int l, int h, int c) -> size_t {
+        return ((size_t)l * nb - (size_t)l * (l - 1) / 2 + (size_t)(h - l)) * nb + c;
+    };
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < nb3; e += (size_t)gridDim.x * 256) {
+        const int a = (int)(e / ((size_t)nb * nb));
+        const int b = (int)((e / nb) % nb);
+        const int z = (int)(e % nb);
+        if (S.layout == 0 && b < a) continue;
+        const int x = min(a, b), y = max(a, b);
+        uint64_t v = T[half(x, y, z)];
+        if (x <= z) v += T[half(x, z, y)];
+        if (x != y && y <= z) v += T[half(y, z, x)];
+        if (z <= x) v += T[half(z, x, y)];
+        if (x != y && z <= y) v += T[half(z, y, x)];
+        if (v == 0) continue;
+        if (S.layout == 0) S.hist[half(x, y, z)] += v;
+        else S.hist[e] += (a == b) ? 2 * v : v;
     }
 }
 
@@ -945,6 +1010,15 @@ void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s)
 {
     if (n_segs <= 0) return;
     hipLaunchKernelGGL(k_reduce, dim3((max_hb + 255) / 256, n_segs), dim3(256), 0, s, a);
+}
+
+void launch_expand(const Sys* sys, int n_sys, int max_nbins, hipStream_t s)
+{
+    if (n_sys <= 0) return;
+    const size_t nb3 = (size_t)max_nbins * max_nbins * max_nbins;
+    size_t blocks = (nb3 + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)blocks, n_sys), dim3(256), 0, s, sys);
 }
 
 }  // namespace g3

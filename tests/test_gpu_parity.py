@@ -207,6 +207,8 @@ def test_accumulate_adds(g3mod, plan, torch_dev, oracle_mod):
     dict(centres_per_item=64),
     dict(centres_per_item=1024),
     dict(wg_per_cu=2),
+    dict(per_centre=1),
+    dict(per_centre=1, lds_hist_bins=4096, centres_per_item=64),
 ])
 def test_tuning_does_not_change_results(g3mod, plan, torch_dev, oracle_mod, tun):
     w = synth.lj_small("fcc", n_frames=4)
@@ -331,3 +333,46 @@ def test_large_system_sampled_frames(g3mod, plan, torch_dev, oracle_mod):
     for f in (0, 37):
         want = oracle_mod.hist(w.frames[f:f + 1], w.box, w.rmax, w.nbins, w.layout)
         assert_same(per[f], want, f"frame {f}")
+
+
+# ------------------------------------------------------------------ enumeration modes
+def _mode_workloads():
+    out = []
+    for kind in ("gas", "fcc"):
+        w = synth.lj_small(kind, n_frames=3)
+        for layout in (0, 1):
+            out.append((f"lj256_{kind}_L{layout}", w.frames, w.box, w.rmax, w.nbins, layout))
+    w = synth.water_like(n_frames=2)
+    out.append(("water4096_wide", w.frames, w.box, w.rmax, w.nbins, 1))
+    for seed in range(2):
+        rng = np.random.default_rng(60 + seed)
+        box = [int(x) for x in rng.integers(20000, 60000, size=3)]
+        N = int(rng.integers(200, 1200))
+        fr = np.stack([np.stack([rng.integers(0, L, size=N) for L in box]) for _ in range(2)])
+        rmax = float(rng.uniform(0.3, 0.49) * min(box))     # past L/4 and L/3
+        out.append((f"random{seed}", fr.astype(np.int32), box, rmax, int(rng.integers(5, 41)),
+                    seed % 2))
+    return out
+
+
+@pytest.mark.parametrize("wl", _mode_workloads(), ids=lambda w: w[0])
+@pytest.mark.parametrize("per_centre", [0, 1])
+def test_enumeration_modes_match_oracle(g3mod, plan, torch_dev, oracle_mod, wl, per_centre):
+    """Both enumerations (each triangle once and expanded, or every centre's
+    pairs) give the oracle's histogram, in both forms."""
+    _, fr, box, rmax, nbins, layout = wl
+    plan.set_tuning(per_centre=per_centre)
+    want = oracle_mod.hist(fr, box, rmax, nbins, layout)
+    a, b = both(g3mod, plan, torch_dev, fr, box, rmax, nbins, layout)
+    assert_same(a, want, "plain")
+    assert_same(b, want, "batched")
+
+
+def test_large_system_per_centre_mode(g3mod, plan, torch_dev, oracle_mod):
+    """The N = 65536 workload with every centre's pairs evaluated (the
+    paper's loop), two frames batched, equals the oracle."""
+    w = synth.lj_large(n_frames=50)
+    fr = w.frames[[3, 44]]
+    plan.set_tuning(per_centre=1)
+    (b,) = run_batch(g3mod, plan, torch_dev, [(fr, w.box, w.rmax, w.nbins, w.layout)])
+    assert_same(b, oracle_mod.hist(fr, w.box, w.rmax, w.nbins, w.layout), "per-centre batched")
