@@ -40,6 +40,7 @@ struct Sys {
     uint32_t R2;             // thr[nbins]: s accepted iff s < R2
     int32_t nbins, layout, wide;
     int32_t sh, tab_len;     // bin table: tab[s >> sh] is b(s) or b(s)-1 or lower
+    int32_t tab_bits;        // tab_len = 2^tab_bits
     int32_t one_step;        // 1: tab[s >> sh] is b(s) or b(s)-1
     const uint32_t* thr;     // device [nbins + 1]
     const uint8_t* tab;      // device [tab_len]
@@ -103,10 +104,14 @@ struct TripletArgs {
     unsigned long long* cand;  // running count of candidate (centre, {j,k}) pairs evaluated
 };
 
-// LDS bytes used by the triplet kernel for a configuration.
-inline size_t triplet_lds_bytes(int hb_max, int cb, int tb_max)
+// Triplet kernel LDS: thr (1 KB), bin table, 64 trash words, 32 words of
+// scalars, then the histogram slab and per-item centre arrays and the
+// work-unit chunk table (uint16, one per 64 units).
+constexpr int kChunkCap = 2048;
+constexpr uint32_t kTripletLdsFixed = 1024 + kTabBytes + 256 + 128;
+inline size_t triplet_lds_bytes(int hb_max, int cb)
 {
-    return 256 * 4 + (size_t)tb_max + (size_t)hb_max * 4 + (size_t)(3 * cb + 1) * 4;
+    return kTripletLdsFixed + (size_t)hb_max * 4 + (size_t)(3 * cb + 1) * 4 + 2 * kChunkCap;
 }
 
 // Neighbour build launch shape: workgroups per frame (each loops over cells),

@@ -24,7 +24,7 @@ using namespace g3;
 
 constexpr int kListCap = 1024;       // neighbours per centre held by the triplet kernel
 constexpr int kStageCap = 1024;      // stencil atoms staged in LDS by the neighbour build
-constexpr int kTabMax = 8192;        // bytes of the bin lookup table in LDS
+constexpr int kTabMax = kTabBytes;   // bytes of the bin lookup table in LDS
 constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
 constexpr size_t kLdsPerCU = 160 * 1024;
 
@@ -85,7 +85,7 @@ struct Geometry {
     int box[3] = {0, 0, 0}, nc[3] = {1, 1, 1}, ncell = 1;
     int C = 0;
     uint32_t R2 = 0;
-    int sh = 0, tab_len = 0, one_step = 0;
+    int sh = 0, tab_len = 0, tab_bits = 0, one_step = 0;
     std::vector<uint32_t> thr;
     std::vector<uint8_t> tab;
     std::vector<int> slab_lo;  // n_slabs + 1 boundaries
@@ -141,7 +141,11 @@ void plan_bins(Geometry& g, double rmax)
     while (sh < 31 && std::ldexp(1.0, sh + 1) <= dr2) ++sh;
     while (((uint64_t)g.R2 + ((1ull << sh) - 1)) >> sh > (uint64_t)kTabMax) ++sh;
     g.sh = sh;
-    g.tab_len = (int)(((uint64_t)g.R2 + ((1ull << sh) - 1)) >> sh);
+    // a power-of-two table, so that a bit-field extract of s indexes it
+    const int need = (int)(((uint64_t)g.R2 + ((1ull << sh) - 1)) >> sh);
+    g.tab_bits = 0;
+    while ((1 << g.tab_bits) < need) ++g.tab_bits;
+    g.tab_len = 1 << g.tab_bits;
     g.tab.resize(g.tab_len);
     int b = 0;
     for (int q = 0; q < g.tab_len; ++q) {
@@ -304,7 +308,7 @@ Tun effective(const g3_plan p)
     t.wg_per_cu = p->tun.wg_per_cu == 2 ? 2 : 1;
     t.tri_once = p->tun.per_centre != 1;
     const size_t budget = kLdsPerCU / t.wg_per_cu - 256;   // static shared memory headroom
-    const size_t fixed = triplet_lds_bytes(0, t.cb, kTabMax);
+    const size_t fixed = triplet_lds_bytes(0, t.cb);
     int hb = budget > fixed ? (int)((budget - fixed) / 4) : 0;
     hb &= ~63;
     if (p->tun.lds_hist_bins > 0) hb = std::min(hb, p->tun.lds_hist_bins & ~63);
@@ -429,6 +433,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
     s.wide = g.wide;
     s.sh = g.sh;
     s.tab_len = g.tab_len;
+    s.tab_bits = g.tab_bits;
     s.one_step = g.one_step;
     s.thr = reinterpret_cast<const uint32_t*>(arena + P.off_thr);
     s.tab = reinterpret_cast<const uint8_t*>(arena + P.off_tab);

@@ -588,18 +588,66 @@ struct GEnt<true> {
     }
 };
 
-// Bin of an accepted squared distance s (< R2) from the LDS tables.
-template <bool ONE_STEP>
-__device__ __forceinline__ int lds_bin(uint32_t s, uint32_t sclamp, const uint8_t* tab,
-                                       const uint32_t* thr, int sh)
+// LDS of the triplet kernel at fixed byte addresses.  The kernel declares no
+// static LDS, so its dynamic LDS starts at address 0 (the host checks this
+// before the first launch) and table bases fold into instruction offsets.
+constexpr uint32_t kTlThr = 0;                        // uint32 thr[256]
+constexpr uint32_t kTlTab = 1024;                     // uint8 tab[kTabBytes]
+constexpr uint32_t kTlTrash = kTlTab + kTabBytes;     // uint32 [64]: rejected candidates land here
+constexpr uint32_t kTlMisc = kTlTrash + 256;          // uint32 scan[17], item, slot
+constexpr uint32_t kTlItem = kTlMisc + 4 * 17;
+constexpr uint32_t kTlSlot = kTlItem + 4;
+constexpr uint32_t kTlHist = kTlMisc + 128;           // uint32 hist[hb_max], then per item:
+                                                      // src[cb], m[cb], roff[cb+1], chunk[kChunkCap]
+static_assert(kTlHist == kTripletLdsFixed, "triplet LDS map");
+
+// (LDS pointers are 32-bit on the device; the host pass sees 64-bit ones)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wint-to-pointer-cast"
+typedef __attribute__((address_space(3))) uint32_t lds32_t;
+typedef __attribute__((address_space(3))) uint16_t lds16_t;
+typedef __attribute__((address_space(3))) uint8_t lds8_t;
+__device__ __forceinline__ uint32_t ld32(uint32_t a) { return *(lds32_t*)a; }
+__device__ __forceinline__ uint32_t ld16(uint32_t a) { return *(lds16_t*)a; }
+__device__ __forceinline__ uint32_t ld8(uint32_t a) { return *(lds8_t*)a; }
+__device__ __forceinline__ void st32(uint32_t a, uint32_t v) { *(lds32_t*)a = v; }
+__device__ __forceinline__ void st16(uint32_t a, uint32_t v) { *(lds16_t*)a = (uint16_t)v; }
+__device__ __forceinline__ void st8(uint32_t a, uint32_t v) { *(lds8_t*)a = (uint8_t)v; }
+__device__ __forceinline__ void inc32(uint32_t a)
 {
-    int c = tab[sclamp >> sh];
-    if (ONE_STEP) {
-        c += (s >= thr[c + 1]) ? 1 : 0;
-    } else {
-        while (sclamp >= thr[c + 1]) ++c;
+    __hip_atomic_fetch_add((lds32_t*)a, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+#pragma clang diagnostic pop
+
+// Exclusive scan over the 1024-thread block with its 17 scratch words at LDS
+// address tmp.  Only LDS-address accessors are used: a generic pointer made
+// from a fixed LDS address is not a valid LDS reference.
+__device__ uint32_t block_excl_scan_at(uint32_t v, uint32_t tmp, uint32_t* total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
     }
-    return c;
+    if (lane == 63) st32(tmp + 4u * w, x);
+    __syncthreads();
+    if (w == 0) {
+        uint32_t y = lane < nw ? ld32(tmp + 4u * lane) : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t t = __shfl_up(y, o, 64);
+            if (lane >= o) y += t;
+        }
+        if (lane < nw) st32(tmp + 4u * lane, y);
+    }
+    __syncthreads();
+    uint32_t pre = (w > 0 ? ld32(tmp + 4u * (w - 1)) : 0u) + x - v;
+    *total = ld32(tmp + 4u * (nw - 1));
+    __syncthreads();
+    return pre;
 }
 
 }  // namespace
@@ -608,18 +656,10 @@ template <bool WIDE, bool ONE_STEP>
 __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
 {
     using E = typename Ent<WIDE>::T;
-    extern __shared__ __align__(16) unsigned char smem[];
-    // tables first, at fixed offsets, so their addresses fold into the
-    // instructions' immediate offsets
-    uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                      // 256
-    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + 256);                 // kTabBytes
-    uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_tab + kTabBytes);        // hb_max
-    uint32_t* s_src = s_hist + A.hb_max;                                      // cb: list start
-    uint32_t* s_m = s_src + A.cb;                                             // cb: entries from J_q
-    uint32_t* s_roff = s_m + A.cb;                                            // cb + 1: row prefix
-    __shared__ uint32_t s_tmp[17];
-    __shared__ int s_item;
-    __shared__ uint32_t s_slot;
+    const uint32_t kSrc = kTlHist + 4u * (uint32_t)A.hb_max;
+    const uint32_t kM = kSrc + 4u * (uint32_t)A.cb;
+    const uint32_t kRoff = kM + 4u * (uint32_t)A.cb;
+    const uint32_t kChunkT = kRoff + 4u * (uint32_t)(A.cb + 1);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -630,12 +670,12 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
     auto flush = [&](int seg) {
         const Seg& G = A.segs[seg];
         __syncthreads();
-        if (tid == 0) s_slot = atomicAdd(&A.ctl->slots_used, 1u);
+        if (tid == 0) st32(kTlSlot, atomicAdd(&A.ctl->slots_used, 1u));
         __syncthreads();
-        const uint32_t slot = s_slot;
+        const uint32_t slot = ld32(kTlSlot);
         if (slot < (uint32_t)A.max_slots) {
             uint32_t* dst = A.slots + (size_t)slot * A.hb_max;
-            for (int x = tid; x < G.hb; x += kTripletThreads) dst[x] = s_hist[x];
+            for (int x = tid; x < G.hb; x += kTripletThreads) dst[x] = ld32(kTlHist + 4u * x);
             if (tid == 0) A.slot_seg[slot] = seg;
         } else {
             // Fallback: add the non-zero bins directly; a wave skips 64 empty
@@ -647,7 +687,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             const int layout = S.tri ? 0 : S.layout;
             for (int x0 = wave * 64; x0 < G.hb; x0 += kTripletThreads) {
                 const int x = x0 + lane;
-                const uint32_t v = x < G.hb ? s_hist[x] : 0u;
+                const uint32_t v = x < G.hb ? ld32(kTlHist + 4u * x) : 0u;
                 if (__ballot(v != 0u) == 0ull) continue;
                 if (v == 0u) continue;
                 const int a = G.lo0 + x / RL, rem = x - (x / RL) * RL;
@@ -670,13 +710,13 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
     };
 
     auto zero_hist = [&](int hb) {
-        for (int x = tid; x < hb; x += kTripletThreads) s_hist[x] = 0u;
+        for (int x = tid; x < hb; x += kTripletThreads) st32(kTlHist + 4u * x, 0u);
     };
 
     for (;;) {
-        if (tid == 0) s_item = (int)atomicAdd(&A.ctl->next_item, 1u);
+        if (tid == 0) st32(kTlItem, atomicAdd(&A.ctl->next_item, 1u));
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane((int)ld32(kTlItem));
         __syncthreads();
         if (item >= A.total_items) break;
         int seg = 0;
@@ -686,8 +726,8 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         if (seg != cur_seg) {
             if (cur_seg >= 0) flush(cur_seg);
             if (G.sys != cur_sys) {
-                for (int x = tid; x <= S.nbins; x += kTripletThreads) s_thr[x] = S.thr[x];
-                for (int x = tid; x < S.tab_len; x += kTripletThreads) s_tab[x] = S.tab[x];
+                for (int x = tid; x <= S.nbins; x += kTripletThreads) st32(kTlThr + 4u * x, S.thr[x]);
+                for (int x = tid; x < S.tab_len; x += kTripletThreads) st8(kTlTab + x, S.tab[x]);
                 cur_sys = G.sys;
             }
             zero_hist(G.hb);
@@ -709,8 +749,10 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const GEnt<WIDE> pool{reinterpret_cast<const char*>(S.pool) + pbase * sizeof(E)};
         constexpr uint32_t ES = GEnt<WIDE>::kSize;
 
-        // per centre: its entries from J_q on (m) and its slab rows (r)
-        uint32_t m = 0, r = 0;
+        // per centre: its entries from J_q on (m) and its slab rows (r);
+        // centres with rows are compacted (index kc < nne), so that unit
+        // boundaries between consecutive centres strictly increase
+        uint32_t m = 0, r = 0, src = 0;
         if (tid < nctr) {
             const int i = c_begin + tid;
             const uint32_t o = off[i], n = cnt[i];
@@ -718,55 +760,92 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             const uint32_t j1 = J[(size_t)i * (S.n_slabs + 1) + q + 1];
             r = j1 - j0;
             m = r ? n - j0 : 0u;
-            s_src[tid] = o + j0;
-            s_m[tid] = m;
+            src = o + j0;
         }
         // candidate pairs of this item: r(r-1)/2 + r(m-r) per centre
         const uint32_t inc = r ? r * (r - 1) / 2 + r * (m - r) : 0u;
-        uint32_t rtot, itot;
-        const uint32_t rpre = block_excl_scan(r, s_tmp, &rtot);
-        (void)block_excl_scan(inc, s_tmp, &itot);
-        if (tid < nctr) s_roff[tid] = rpre;
-        if (tid == 0) s_roff[nctr] = rtot;
-        __syncthreads();
-        if (rtot == 0) continue;
+        uint32_t rtot, itot, nne;
+        const uint32_t rpre = block_excl_scan_at(r, kTlMisc, &rtot);
+        (void)block_excl_scan_at(inc, kTlMisc, &itot);
+        const uint32_t kc = block_excl_scan_at(r ? 1u : 0u, kTlMisc, &nne);
+        rtot = __builtin_amdgcn_readfirstlane(rtot);
+        const int nne_u = __builtin_amdgcn_readfirstlane((int)nne);
+        if (r) {
+            st32(kSrc + 4u * kc, src);
+            st32(kM + 4u * kc, m);
+            st32(kRoff + 4u * kc, rpre);
+        }
+        if (tid == 0) st32(kRoff + 4u * (uint32_t)nne_u, rtot);
+        if (rtot == 0) {
+            __syncthreads();
+            continue;
+        }
         if (pending + itot > 0xFFFFFFFFull) {  // keep every uint32 LDS counter exact
             flush(seg);
             zero_hist(G.hb);
             pending = 0;
-            __syncthreads();
         }
         pending += itot;
         evaluated += itot;
 
+        // Work units: every row is cut into Pp = 2^pp parts of its candidate
+        // sequence (circular triangle part, then the rectangle), about two
+        // units per thread; unit w of centre cl is row (w - roff[cl] Pp) >> pp,
+        // part (w - roff[cl] Pp) & (Pp - 1).
+        int pp = 0;
+        while (pp < 4 && (rtot << (pp + 1)) <= 2u * kTripletThreads) ++pp;
+        const uint32_t U = rtot << pp;
+        // chunk table: the centre holding unit 64c, for the waves' first lanes
+        const bool chunked = U <= 64u * (uint32_t)kChunkCap;
+        __syncthreads();                       // roff complete
+        if (chunked && tid < nne_u) {
+            const uint32_t a = ld32(kRoff + 4u * tid) << pp, b = ld32(kRoff + 4u * tid + 4u) << pp;
+            for (uint32_t c = (a + 63u) >> 6; (c << 6) < b; ++c) st16(kChunkT + 2u * c, (uint32_t)tid);
+        }
+        __syncthreads();
+
         const uint32_t R2 = S.R2, R2m1 = S.R2 - 1u;
-        const int sh = S.sh;
+        const uint32_t sh = (uint32_t)S.sh, tbits = (uint32_t)S.tab_bits;
         const int cm1 = S.C - 1;
-        // slab index of (b_j, b_k, c) = (b_j - lo0) RL + (b_k - lo0) nb + c; the
-        // entries carry b_k * nb, so the row constant absorbs -lo0 * nb
         const int RL = G.rl;
-        // Work units: every row is cut into Pp parts of its candidate sequence
-        // (circular triangle part, then the rectangle), Pp chosen so that the
-        // item has about two units per thread.  Units of a centre are
-        // part-major, so neighbouring lanes take neighbouring rows of one part
-        // and read the same rectangle entries.
-        const int Pp = (int)min(16u, max(1u, (2u * kTripletThreads + rtot - 1) / rtot));
-        const uint32_t U = rtot * (uint32_t)Pp;
-        for (uint32_t w = tid; w < U; w += kTripletThreads) {
-            int cl = 0, ch = nctr - 1;
-            while (cl < ch) {
-                const int mid = (cl + ch + 1) >> 1;
-                if (s_roff[mid] * (uint32_t)Pp <= w) cl = mid; else ch = mid - 1;
+        const uint32_t trash = kTlTrash + 4u * (uint32_t)lane;
+        for (uint32_t w0 = (uint32_t)wave * 64u; w0 < U; w0 += kTripletThreads) {
+            const uint32_t w = w0 + (uint32_t)lane;
+            // (compacted) centre of unit w: the wave's first centre from the
+            // chunk table, then one step per centre boundary inside the wave's
+            // 64 units -- at most 63, since every centre has at least one unit
+            int cl;
+            if (chunked) {
+                const int c0 = (int)ld16(kChunkT + 2u * (w0 >> 6));
+                const int ci = c0 + 1 + lane;
+                const uint32_t bnd = ci <= nne_u ? ld32(kRoff + 4u * (uint32_t)ci) << pp : 0xffffffffu;
+                uint64_t M = __ballot(bnd <= w0 + 63u);
+                cl = c0;
+                while (M) {
+                    const int l = __builtin_ctzll(M);
+                    M &= M - 1ull;
+                    cl += (w >= (uint32_t)__builtin_amdgcn_readlane((int)bnd, l)) ? 1 : 0;
+                }
+            } else {
+                int lo = 0, hi = nne_u - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((ld32(kRoff + 4u * (uint32_t)mid) << pp) <= w) lo = mid; else hi = mid - 1;
+                }
+                cl = lo;
             }
-            const uint32_t eoff = s_src[cl] * ES;        // byte offset of the centre's entry J_q
-            const int mm = (int)s_m[cl];
-            const int rr = (int)(s_roff[cl + 1] - s_roff[cl]);
-            const int lw = (int)(w - s_roff[cl] * (uint32_t)Pp);
-            const int p = lw / rr;
-            const int j = lw - p * rr;
+            if (w >= U) continue;
+            const uint32_t r0 = ld32(kRoff + 4u * (uint32_t)cl);
+            const int rr = (int)(ld32(kRoff + 4u * (uint32_t)cl + 4u) - r0);
+            const uint32_t lw = w - (r0 << pp);
+            const int j = (int)(lw >> pp), p = (int)(lw & ((1u << pp) - 1u));
+            const uint32_t eoff = ld32(kSrc + 4u * (uint32_t)cl) * ES;   // byte offset of entry J_q
+            const int mm = (int)ld32(kM + 4u * (uint32_t)cl);
             const E vj = pool.load(eoff + (uint32_t)j * ES);
-            const int bj = Ent<WIDE>::col(vj) / nb;
-            const int Aj = (bj - lo0) * RL - lo0 * nb;
+            // slab index of (b_j, b_k, c) is (b_j - lo0) RL + (b_k - lo0) nb + c;
+            // entries carry b nb, and (b_j - lo0) RL = (b_j nb)(nb - lo0) - lo0 RL
+            const int colj = Ent<WIDE>::col(vj);
+            const uint32_t rowbase = kTlHist + 4u * (uint32_t)(colj * (nb - lo0) - lo0 * RL - lo0 * nb);
             uint32_t jx, jy = 0, jz;
             if constexpr (WIDE) {
                 jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
@@ -779,32 +858,46 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 else
                     return Ent<false>::dist2(vk, jx, jz, 0);
             };
-            // four candidates at a time: distances, table, threshold, then the
-            // (predicated) LDS increments
+            // bin of s from the table plus the threshold step(s); any value
+            // for a rejected candidate, whose increment goes to the trash
+            auto bin = [&](uint32_t s) -> uint32_t {
+                uint32_t c;
+                if constexpr (ONE_STEP) {
+                    c = ld8(kTlTab + __builtin_amdgcn_ubfe(s, sh, tbits));
+                    c += (s >= ld32(kTlThr + 4u + 4u * c)) ? 1u : 0u;
+                } else {
+                    const uint32_t sc = min(s, R2m1);
+                    c = ld8(kTlTab + (sc >> sh));
+                    while (sc >= ld32(kTlThr + 4u + 4u * c)) ++c;
+                }
+                return c;
+            };
+            // four candidates at a time: distances, bins, addresses, then the
+            // four increments (rejected ones to this lane's trash word)
             auto eval4 = [&](const E (&v)[4]) {
-                uint32_t s[4], sc[4];
-                int c[4];
+                uint32_t s[4], a[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) { s[u] = d2(v[u]); sc[u] = min(s[u], R2m1); }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) c[u] = lds_bin<ONE_STEP>(s[u], sc[u], s_tab, s_thr, sh);
+                for (int u = 0; u < 4; ++u) s[u] = d2(v[u]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (s[u] < R2) atomicAdd(&s_hist[Aj + Ent<WIDE>::col(v[u]) + c[u]], 1u);
+                    a[u] = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v[u]) + bin(s[u]));
+                // keep the address arithmetic unconditional (a select, not a branch)
+                asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) inc32(s[u] < R2 ? a[u] : trash);
             };
             auto eval1 = [&](const E& v) {
                 const uint32_t s = d2(v);
-                if (s < R2) {
-                    const int c = lds_bin<ONE_STEP>(s, s, s_tab, s_thr, sh);
-                    atomicAdd(&s_hist[Aj + Ent<WIDE>::col(v) + c], 1u);
-                }
+                uint32_t a = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v) + bin(s));
+                asm volatile("" : "+v"(a));
+                inc32(s < R2 ? a : trash);
             };
             // this unit's share [u0, u1) of the row's sequence: u < H is the
             // circular triangle (k = j + u + 1 mod rr), u >= H the rectangle
             // (k = rr + u - H)
             const int H = (rr - 1) / 2 + (((rr & 1) == 0 && j < rr / 2) ? 1 : 0);
             const int L = H + (mm - rr);
-            const int u0 = (p * L) / Pp, u1 = ((p + 1) * L) / Pp;
+            const int u0 = (p * L) >> pp, u1 = ((p + 1) * L) >> pp;
             const int tend = min(u1, H);
             int t = u0 + 1;
             for (; t + 3 <= tend; t += 4) {
@@ -979,9 +1072,14 @@ hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
     const void* trip[4] = {(const void*)k_triplet<false, false>, (const void*)k_triplet<false, true>,
                            (const void*)k_triplet<true, false>, (const void*)k_triplet<true, true>};
     hipError_t e;
-    for (const void* k : trip)
+    for (const void* k : trip) {
+        // the triplet kernel addresses LDS from 0: it must have no static LDS
+        hipFuncAttributes fa;
+        if ((e = hipFuncGetAttributes(&fa, k))) return e;
+        if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
         if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)triplet_bytes)))
             return e;
+    }
     const void* build[4] = {(const void*)k_nbr_build<false, false>, (const void*)k_nbr_build<false, true>,
                             (const void*)k_nbr_build<true, false>, (const void*)k_nbr_build<true, true>};
     for (const void* k : build)
@@ -992,7 +1090,7 @@ hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
 
 void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s)
 {
-    const size_t lds = triplet_lds_bytes(a.hb_max, a.cb, a.tb_max);
+    const size_t lds = triplet_lds_bytes(a.hb_max, a.cb);
     if (wide) {
         if (one_step)
             hipLaunchKernelGGL((k_triplet<true, true>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
