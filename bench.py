@@ -60,6 +60,11 @@ def parse():
     return ap.parse_args()
 
 
+def mark(msg: str):
+    """Progress marker on stderr, flushed before the GPU work it names."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -89,6 +94,7 @@ def main():
         del src, dst
 
     # triplets binned per step = total of the half histogram of one pass
+    mark(f"first batched pass: N={w.n_atoms} frames={w.n_frames}")
     plan.accumulate_batch([system])
     plan.sync()
     binned = int(hist.sum().item())
@@ -106,7 +112,9 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    mark(f"batched: {args.warmup} warm-up + {args.steps} timed steps (graph replays)")
     batched_s = timed(lambda: plan.accumulate_batch([system]), args.steps, args.warmup)
+    mark("batched: triplet-kernel timing (direct launches)")
 
     # triplet-kernel duration: HIP events around the kernel on the plan's stream
     # (direct launches of the same kernels with the same arguments)
@@ -118,6 +126,7 @@ def main():
 
     plain = None
     if not args.no_plain:
+        mark("plain per-frame form")
         plain_s = timed(lambda: plan.accumulate(frames, w.box, w.rmax, w.nbins, w.layout, hist),
                         max(2, args.steps // 2), 1)
         plan.kernel_time_reset(True)
@@ -140,6 +149,7 @@ def main():
     # the paper's enumeration (every centre's unordered pairs) for comparison
     per_centre = None
     if not args.no_per_centre:
+        mark("per-centre enumeration, batched")
         plan.set_tuning(per_centre=1)
         pc_s = timed(lambda: plan.accumulate_batch([system]), max(3, args.steps // 2), 1)
         plan.kernel_time_reset(True)
@@ -154,10 +164,12 @@ def main():
 
     served = None
     if args.serve_requests > 0:
+        mark(f"served: {args.serve_requests} requests at {args.serve_rate}/s, two budgets")
         served = serve_bench(args.serve_requests, args.serve_rate)
 
     cpu = None
     if not args.no_cpu:
+        mark("cpu baseline (oracle)")
         cpu = cpu_baseline(w, args.cpu_frames)
 
     line = {

@@ -778,7 +778,9 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         auto put = [&](const void* d, size_t n) { key.append((const char*)d, n); };
         put(&wide, sizeof(wide));
         put(&one_step, sizeof(one_step));
-        put(&tn, sizeof(tn));
+        // tuning fields one by one (the struct's padding bytes are undefined)
+        const int32_t tk[4] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0};
+        put(tk, sizeof(tk));
         int nj = (int)jobs.size(), ns = (int)segs.size();
         put(&nj, 4); put(&ns, 4); put(&items, 4); put(&max_n, 4); put(&max_hb, 4); put(&max_cells, 4);
         put(&p->arena, sizeof(void*)); put(&p->tables, sizeof(void*)); put(&p->slots, sizeof(void*));
@@ -858,7 +860,12 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             continue;
         }
         if (!have) {
-            if (gexec) { hipGraphExecDestroy(gexec); gexec = nullptr; }
+            if (gexec) {
+                // an earlier launch of this graph may still run on the stream
+                G3_TRY_HIP(hipStreamSynchronize(p->stream));
+                hipGraphExecDestroy(gexec);
+                gexec = nullptr;
+            }
             hipGraph_t graph;
             if (!p->cap_stream) G3_TRY_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
             G3_TRY_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
