@@ -773,7 +773,9 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         if ((st = upload_geometry(p, ps))) return st;
         if ((st = end_upload(p))) return st;
 
-        // graph key: everything baked into launch parameters
+        // graph key: everything baked into the launches (grids and arguments);
+        // completed below with the fill ranges, which depend on the order and
+        // sizes of the systems and not only on their totals
         std::string key;
         auto put = [&](const void* d, size_t n) { key.append((const char*)d, n); };
         put(&wide, sizeof(wide));
@@ -817,6 +819,12 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         int max_nb = 0;
         for (auto& P : ps) max_nb = std::max(max_nb, P.g.nbins);
         const int n_sys = (int)ps.size();
+        for (auto& z : zero) {
+            put(&z.first, sizeof(z.first));
+            put(&z.second, sizeof(z.second));
+        }
+        put(&n_sys, sizeof(n_sys));
+        put(&max_nb, sizeof(max_nb));
 
         auto enqueue = [&](hipStream_t sm) {
             for (auto& z : zero) launch_zero_u32(z.first, z.second, sm);
