@@ -28,12 +28,12 @@ __device__ __forceinline__ int cell_of(int x, int nc, int L)
     return (int)(((int64_t)x * nc) / L);
 }
 
-// Minimum image of one component (only used on axes with a single cell).
+// Minimum image of one component (only used on axes with a single cell);
+// |d| < L <= 2^29, so 2d fits int32.
 __device__ __forceinline__ int min_image(int d, int L)
 {
-    if (2 * (int64_t)d > L) return d - L;
-    if (2 * (int64_t)d < -(int64_t)L) return d + L;
-    return d;
+    const int d2 = 2 * d;
+    return d2 > L ? d - L : (d2 < -L ? d + L : d);
 }
 
 // Exclusive scan over a 1024-thread block.  tmp needs 17 words.
@@ -161,13 +161,13 @@ __global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sy
 // C <= 46340, products on the 24-bit multiplier (|d| < 2^16).
 namespace {
 
-// The stencil of a cell, its cells ordered by cell index: atoms are stored
-// cell by cell, so stencil positions t = 0..T-1 run in increasing sorted
-// index, and "atom j ranks above the centre" is simply t > tself.
+// The stencil of a cell: the home cell first, then the other cells.  Atoms
+// are ranked by their cell-sorted index, so in triangle-once mode the other
+// cells kept are those of higher cell index (all their atoms rank above the
+// home cell's), and "atom j ranks above the centre" is simply t > tself.
 struct Stencil {
-    int n;                 // stencil cells
-    int home;              // position of the centre's own cell
-    int start[27], pre[28], cnt[27];
+    int n;                 // stencil cells kept
+    int start[27], pre[28];
     int shx[27], shy[27], shz[27];
 };
 
@@ -179,24 +179,19 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-template <bool ONE_STEP>
-__device__ __forceinline__ int bin_of(uint32_t s, const uint8_t* tab, const uint32_t* thr, int sh)
-{
-    int b = tab[s >> sh];
-    if (ONE_STEP) {
-        b += (s >= thr[b + 1]) ? 1 : 0;
-    } else {
-        while (s >= thr[b + 1]) ++b;
-    }
-    return b;
-}
 
 }  // namespace
 
 constexpr int kBuildThreads = 256;
 constexpr int kBuildWaves = kBuildWavesPerWG;
 static_assert(kBuildThreads == 64 * kBuildWavesPerWG, "build workgroup shape");
-constexpr int kWaveBuf = 256;      // neighbours buffered per wave before the write
+// Neighbours buffered per wave before the write: 2 KB of entries per wave
+// either way (a longer list re-evaluates its candidates for the write).
+// Keeping the workgroup under 40 KB of LDS lets 4 of them share a CU.
+constexpr int kBufBytes = 2048;
+template <bool WIDE>
+constexpr int wave_buf() { return kBufBytes / (WIDE ? 16 : 8); }
+constexpr int kWaveBufMax = kBufBytes / 8;
 constexpr uint32_t kChunk = kBuildChunk;
 
 template <bool WIDE, bool ONE_STEP>
@@ -208,10 +203,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                    // [256]
     uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + 256);               // [8192]
     uint8_t* s_slab = s_tab + 8192;                                          // [256] bin -> slab
+    constexpr int kWaveBuf = wave_buf<WIDE>();
     E* s_buf = reinterpret_cast<E*>(s_slab + 256);                           // [waves][kWaveBuf]
     uint32_t* s_scnt = reinterpret_cast<uint32_t*>(s_buf + kBuildWaves * kWaveBuf);  // [waves][32]
     uint32_t* s_g2 = s_scnt + kBuildWaves * 32;                              // [256] pair bins
-    int32_t* s_x = reinterpret_cast<int32_t*>(s_g2 + 256);
+    uint8_t* s_sb = reinterpret_cast<uint8_t*>(s_g2 + 256);                  // [waves][kWaveBuf] slab
+    int32_t* s_x = reinterpret_cast<int32_t*>(s_sb + kBuildWaves * kWaveBufMax);
     int32_t* s_y = s_x + stg_cap;
     int32_t* s_z = s_y + stg_cap;
     __shared__ Stencil st;
@@ -231,9 +228,11 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     const uint32_t span = 2u * (uint32_t)cm1;
     const uint32_t R2 = S.R2;
     const int sh = S.sh, nb = S.nbins, n_slabs = S.n_slabs, list_cap = S.list_cap;
+    const int tbits = S.tab_bits;
     const int64_t pool_cap = S.pool_cap;
     uint32_t* scnt = s_scnt + wave * 32;
     E* buf = s_buf + wave * kWaveBuf;
+    uint8_t* sb = s_sb + wave * kWaveBuf;     // slab of each buffered entry
     uint32_t* flags = S.flags + f;
     uint32_t* cursor = S.cursor + (size_t)f * kCursorStride;
     uint32_t chunk_base = 0, chunk_left = 0;   // this wave's slice of the pool
@@ -280,9 +279,9 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     for (int cell = blockIdx.x; cell < ncell; cell += gridDim.x) {
         const int c0 = cs[cell], c1 = cs[cell + 1];
         if (c0 == c1) continue;   // uniform over the workgroup
-        // stencil table: lane e of wave 0 takes stencil offset e and stores it
-        // at the rank of its cell index (the cells are distinct), then a
-        // prefix sum of the counts in that order
+        // stencil table: lane e of wave 0 takes stencil offset e; the home
+        // cell goes to position 0, the kept others follow in lane order (the
+        // cells are distinct), then a prefix sum of the counts in that order
         if (wave == 0) {
             int c = 0x7fffffff, a = 0, cnt_e = 0, shx = 0, shy = 0, shz = 0;
             if (lane < nst) {
@@ -298,27 +297,35 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 a = cs[c];
                 cnt_e = cs[c + 1] - a;
             }
-            int rank = 0;
-            for (int l = 0; l < nst; ++l) rank += (__shfl(c, l, 64) < c) ? 1 : 0;
-            if (lane < nst) {
-                st.start[rank] = a;
-                st.cnt[rank] = cnt_e;
-                st.shx[rank] = shx; st.shy[rank] = shy; st.shz[rank] = shz;
-                if (lane == home) st.home = rank;
+            const int c_home = __shfl(c, home, 64);
+            const bool other = lane < nst && lane != home && (!tri_once || c > c_home);
+            const uint64_t om = __ballot(other);
+            const int n_keep = 1 + (int)__popcll(om);
+            int pos = -1;
+            if (lane == home) pos = 0;
+            if (other) pos = 1 + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
+            // counts in stencil order: lane p takes the count of the cell at p
+            int v = 0;
+            if (pos >= 0) {
+                st.start[pos] = a;
+                st.shx[pos] = shx; st.shy[pos] = shy; st.shz[pos] = shz;
+                st.pre[pos] = cnt_e;                  // count, replaced by the prefix below
             }
             wave_sync();
-            const int v = lane < nst ? st.cnt[lane] : 0;
+            if (lane < n_keep) v = st.pre[lane];
+            wave_sync();
             int incl = v;
 #pragma unroll
             for (int d = 1; d < 32; d <<= 1) {
                 const int y = __shfl_up(incl, d, 64);
                 if (lane >= d) incl += y;
             }
-            if (lane < nst) st.pre[lane] = incl - v;
-            if (lane == nst - 1) { st.pre[nst] = incl; st.n = nst; }
+            if (lane < n_keep) st.pre[lane] = incl - v;
+            if (lane == n_keep - 1) { st.pre[n_keep] = incl; st.n = n_keep; }
         }
         __syncthreads();
-        const int T = st.pre[nst];
+        const int T = st.pre[st.n];
         const bool staged = T <= stg_cap;
         auto cell_of_t = [&](int t) {
             int r = 0;
@@ -337,21 +344,28 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
         __syncthreads();
 
         for (int ci = c0 + wave; ci < c1; ci += kBuildWaves) {
-            // the centre is part of its own stencil (home cell, no shift)
-            const int hr = st.home;
-            const int tself = st.pre[hr] + (ci - st.start[hr]);
+            // the centre is part of its own stencil (home cell: position 0,
+            // no shift)
+            const int tself = ci - st.start[0];
             // triangle-once mode keeps only the atoms ranked above the centre
             const int t_first = tri_once ? tself + 1 : 0;
             const int xi = staged ? s_x[tself] : X[ci];
             const int yi = staged ? s_y[tself] : Y[ci];
             const int zi = staged ? s_z[tself] : Z[ci];
             // candidate t: accepted -> true with the entry and its bin
+            // Evaluated without branches: an invalid or rejected candidate
+            // still computes (garbage) values from in-range reads and returns
+            // false.  With every |d| <= C-1: narrow (C <= 32767) squares sum
+            // below 2^32; wide ones (C <= 46340) may wrap only when dz^2 is
+            // added, which the carry test catches.
             auto test = [&](int t, E& e, int& b) -> bool {
-                if (t >= T || t == tself) return false;
+                const bool valid = t < T && t != tself;
                 int x, y, z;
                 if (staged) {
-                    x = s_x[t]; y = s_y[t]; z = s_z[t];
+                    const int tc = valid ? t : tself;
+                    x = s_x[tc]; y = s_y[tc]; z = s_z[tc];
                 } else {
+                    if (!valid) return false;
                     const int r = cell_of_t(t);
                     const int j = st.start[r] + (t - st.pre[r]);
                     x = X[j] + st.shx[r]; y = Y[j] + st.shy[r]; z = Z[j] + st.shz[r];
@@ -360,25 +374,27 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 if (ncx == 1) dx = min_image(dx, Lx);
                 if (ncy == 1) dy = min_image(dy, Ly);
                 if (ncz == 1) dz = min_image(dz, Lz);
-                if ((uint32_t)(dx + cm1) > span || (uint32_t)(dy + cm1) > span ||
-                    (uint32_t)(dz + cm1) > span)
-                    return false;
+                const bool inr = max((uint32_t)(dx + cm1), max((uint32_t)(dy + cm1), (uint32_t)(dz + cm1))) <= span;
                 const uint32_t s2 = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy);
-                if (s2 >= R2) return false;
                 const uint32_t s = s2 + (uint32_t)__mul24(dz, dz);
-                if (s >= R2) return false;
-                b = bin_of<ONE_STEP>(s, s_tab, s_thr, sh);
+                bool ok = valid && inr && s < R2;
+                if constexpr (WIDE) ok = ok && s >= s2;
+                if constexpr (ONE_STEP) {
+                    b = s_tab[__builtin_amdgcn_ubfe(s, (uint32_t)sh, (uint32_t)tbits)];
+                    b += (s >= s_thr[b + 1]) ? 1 : 0;
+                } else {
+                    const uint32_t sc = min(s, R2 - 1u);
+                    b = s_tab[sc >> sh];
+                    while (sc >= s_thr[b + 1]) ++b;
+                }
+                const int bn = __mul24(b, nb);
                 if constexpr (WIDE) {
-                    e = make_int4(dx, dy, dz, b * nb);
+                    e = make_int4(dx, dy, dz, bn);
                 } else {
                     e = make_uint2(((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16),
-                                   ((uint32_t)dz & 0xffffu) | ((uint32_t)(b * nb) << 16));
+                                   ((uint32_t)dz & 0xffffu) | ((uint32_t)bn << 16));
                 }
-                return true;
-            };
-            auto bin_of_entry = [&](const E& e) -> int {
-                if constexpr (WIDE) return e.w / nb;
-                else return (int)(e.y >> 16) / nb;
+                return ok;
             };
             if (lane < 32) scnt[lane] = 0u;
             wave_sync();
@@ -392,8 +408,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 if (acc) {
                     const uint32_t pos = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                    if (pos < (uint32_t)kWaveBuf) buf[pos] = e;
-                    atomicAdd(&scnt[s_slab[b]], 1u);
+                    const uint32_t q = s_slab[b];
+                    if (pos < (uint32_t)kWaveBuf) {
+                        buf[pos] = e;
+                        sb[pos] = (uint8_t)q;
+                    }
+                    atomicAdd(&scnt[q], 1u);
                     if (pair_hist) atomicAdd(&s_g2[b], pair_inc);
                 }
                 n += (uint32_t)__popcll(mask);
@@ -440,8 +460,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             E* P = pool + base;
             if (n <= (uint32_t)kWaveBuf) {
                 for (uint32_t e = lane; e < n; e += 64) {
-                    const E v = buf[e];
-                    P[atomicAdd(&scnt[s_slab[bin_of_entry(v)]], 1u)] = v;
+                    P[atomicAdd(&scnt[sb[e]], 1u)] = buf[e];
                 }
             } else {
                 for (int t0 = t_first; t0 < T; t0 += 64) {
@@ -1047,8 +1066,8 @@ void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n,
 
 size_t nbr_build_lds_bytes(int stg_cap)
 {
-    return 256 * 4 + 8192 + 256 + (size_t)kBuildWaves * kWaveBuf * 16 + kBuildWaves * 32 * 4 +
-           256 * 4 + (size_t)3 * stg_cap * 4;
+    return 256 * 4 + 8192 + 256 + (size_t)kBuildWaves * kBufBytes + kBuildWaves * 32 * 4 +
+           256 * 4 + (size_t)kBuildWaves * kWaveBufMax + (size_t)3 * stg_cap * 4;
 }
 
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int stg_cap, bool wide,
