@@ -105,10 +105,10 @@ struct TripletArgs {
 };
 
 // Triplet kernel LDS: thr (1 KB), bin table, 64 trash words, 32 words of
-// scalars, then the histogram slab and per-item centre arrays and the
-// work-unit chunk table (uint16, one per 64 units).
+// scalars, 256 sort buckets, then the histogram slab and per-item centre
+// arrays and the work-unit chunk table (uint16, one per 64 units).
 constexpr int kChunkCap = 2048;
-constexpr uint32_t kTripletLdsFixed = 1024 + kTabBytes + 256 + 128;
+constexpr uint32_t kTripletLdsFixed = 1024 + kTabBytes + 256 + 128 + 1024;
 inline size_t triplet_lds_bytes(int hb_max, int cb)
 {
     return kTripletLdsFixed + (size_t)hb_max * 4 + (size_t)(3 * cb + 1) * 4 + 2 * kChunkCap;

@@ -613,10 +613,12 @@ struct GEnt<true> {
 constexpr uint32_t kTlThr = 0;                        // uint32 thr[256]
 constexpr uint32_t kTlTab = 1024;                     // uint8 tab[kTabBytes]
 constexpr uint32_t kTlTrash = kTlTab + kTabBytes;     // uint32 [64]: rejected candidates land here
-constexpr uint32_t kTlMisc = kTlTrash + 256;          // uint32 scan[17], item, slot
+constexpr uint32_t kTlMisc = kTlTrash + 256;          // uint32 scan[17], item, slot, chunk counter
 constexpr uint32_t kTlItem = kTlMisc + 4 * 17;
 constexpr uint32_t kTlSlot = kTlItem + 4;
-constexpr uint32_t kTlHist = kTlMisc + 128;           // uint32 hist[hb_max], then per item:
+constexpr uint32_t kTlNext = kTlSlot + 4;
+constexpr uint32_t kTlKeys = kTlMisc + 128;           // uint32 [256]: centres per row length
+constexpr uint32_t kTlHist = kTlKeys + 1024;          // uint32 hist[hb_max], then per item:
                                                       // src[cb], m[cb], roff[cb+1], chunk[kChunkCap]
 static_assert(kTlHist == kTripletLdsFixed, "triplet LDS map");
 
@@ -635,6 +637,10 @@ __device__ __forceinline__ void st8(uint32_t a, uint32_t v) { *(lds8_t*)a = (uin
 __device__ __forceinline__ void inc32(uint32_t a)
 {
     __hip_atomic_fetch_add((lds32_t*)a, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t fetch_inc32(uint32_t a)
+{
+    return __hip_atomic_fetch_add((lds32_t*)a, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 #pragma clang diagnostic pop
 
@@ -768,10 +774,11 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const GEnt<WIDE> pool{reinterpret_cast<const char*>(S.pool) + pbase * sizeof(E)};
         constexpr uint32_t ES = GEnt<WIDE>::kSize;
 
-        // per centre: its entries from J_q on (m) and its slab rows (r);
-        // centres with rows are compacted (index kc < nne), so that unit
-        // boundaries between consecutive centres strictly increase
-        uint32_t m = 0, r = 0, src = 0;
+        // per centre: its entries from J_q on (m) and its slab rows (r).
+        // Centres with rows are put in order of decreasing row length (a
+        // counting sort over 256 buckets), so that the 64 rows of a wave are
+        // about equally long, and unit boundaries strictly increase.
+        uint32_t m = 0, r = 0, src = 0, key = 0;
         if (tid < nctr) {
             const int i = c_begin + tid;
             const uint32_t o = off[i], n = cnt[i];
@@ -780,20 +787,32 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             r = j1 - j0;
             m = r ? n - j0 : 0u;
             src = o + j0;
+            key = 255u - min(r / 2u + (m - r), 255u);   // the centre's longest row
         }
+        if (tid < 256) st32(kTlKeys + 4u * tid, 0u);
+        if (tid == 0) st32(kTlNext, 0u);
+        __syncthreads();
+        const uint32_t rank = r ? fetch_inc32(kTlKeys + 4u * key) : 0u;
         // candidate pairs of this item: r(r-1)/2 + r(m-r) per centre
         const uint32_t inc = r ? r * (r - 1) / 2 + r * (m - r) : 0u;
         uint32_t rtot, itot, nne;
-        const uint32_t rpre = block_excl_scan_at(r, kTlMisc, &rtot);
-        (void)block_excl_scan_at(inc, kTlMisc, &itot);
-        const uint32_t kc = block_excl_scan_at(r ? 1u : 0u, kTlMisc, &nne);
-        rtot = __builtin_amdgcn_readfirstlane(rtot);
-        const int nne_u = __builtin_amdgcn_readfirstlane((int)nne);
+        (void)block_excl_scan_at(inc, kTlMisc, &itot);   // its barriers also order the ranks
+        const uint32_t bc = tid < 256 ? ld32(kTlKeys + 4u * tid) : 0u;
+        const uint32_t bstart = block_excl_scan_at(bc, kTlMisc, &nne);
+        if (tid < 256) st32(kTlKeys + 4u * tid, bstart);
+        __syncthreads();
         if (r) {
-            st32(kSrc + 4u * kc, src);
-            st32(kM + 4u * kc, m);
-            st32(kRoff + 4u * kc, rpre);
+            const uint32_t pos = ld32(kTlKeys + 4u * key) + rank;
+            st32(kSrc + 4u * pos, src);
+            st32(kM + 4u * pos, m);
+            st32(kRoff + 4u * pos, r);
         }
+        const int nne_u = __builtin_amdgcn_readfirstlane((int)nne);
+        __syncthreads();
+        const uint32_t rs = tid < nne_u ? ld32(kRoff + 4u * tid) : 0u;
+        const uint32_t rpre = block_excl_scan_at(rs, kTlMisc, &rtot);
+        rtot = __builtin_amdgcn_readfirstlane(rtot);
+        if (tid < nne_u) st32(kRoff + 4u * tid, rpre);
         if (tid == 0) st32(kRoff + 4u * (uint32_t)nne_u, rtot);
         if (rtot == 0) {
             __syncthreads();
@@ -828,7 +847,12 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const int cm1 = S.C - 1;
         const int RL = G.rl;
         const uint32_t trash = kTlTrash + 4u * (uint32_t)lane;
-        for (uint32_t w0 = (uint32_t)wave * 64u; w0 < U; w0 += kTripletThreads) {
+        // waves take chunks of 64 units from a counter, longest rows first
+        for (;;) {
+            uint32_t cix = 0;
+            if (lane == 0) cix = fetch_inc32(kTlNext);
+            const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(cix, 0, 64)) * 64u;
+            if (w0 >= U) break;
             const uint32_t w = w0 + (uint32_t)lane;
             // (compacted) centre of unit w: the wave's first centre from the
             // chunk table, then one step per centre boundary inside the wave's
