@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--frames", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library defaults instead of the autotuned configuration")
+    ap.add_argument("--tuning", default="",
+                    help="fixed tuning, e.g. centres_per_item=1024,lds_hist_bins=25536 (no autotuner run)")
     ap.add_argument("--no-per-centre", action="store_true",
                     help="skip timing the per-centre enumeration beside the default")
     ap.add_argument("--cpu-frames", type=int, default=8,
@@ -92,6 +96,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    # the autotuner picks the triplet kernel's tiling for this workload (on
+    # scratch histograms, outside the timed region) and the plan keeps it
+    if args.tuning:
+        plan.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+    elif not args.no_autotune:
+        mark("autotune")
+        plan.autotune([system])
+    tuning = plan.get_tuning()
 
     # triplets binned per step = total of the half histogram of one pass
     mark(f"first batched pass: N={w.n_atoms} frames={w.n_frames}")
@@ -150,7 +163,7 @@ def main():
     per_centre = None
     if not args.no_per_centre:
         mark("per-centre enumeration, batched")
-        plan.set_tuning(per_centre=1)
+        plan.set_tuning(**dict(tuning, per_centre=1))
         pc_s = timed(lambda: plan.accumulate_batch([system]), max(3, args.steps // 2), 1)
         plan.kernel_time_reset(True)
         c0 = plan.candidates()
@@ -158,7 +171,7 @@ def main():
         pc_ms, pc_n = plan.kernel_time()
         pc_cand = (plan.candidates() - c0) // max(pc_n, 1)
         plan.kernel_time_reset(False)
-        plan.set_tuning()
+        plan.set_tuning(**tuning)
         per_centre = {"value": binned / pc_s / 1e9, "ms_per_step": pc_s * 1e3,
                       "triplet_kernel_ms": pc_ms, "candidates_per_launch": pc_cand}
 
@@ -186,6 +199,7 @@ def main():
                    "form": "batched (one hipGraph launch per step)",
                    "enumeration": "triangle-once" if tri_once else "per-centre"},
         "triplets_binned_per_step": binned,
+        "tuning": tuning,
         "plain": plain,
         "per_centre_enumeration": per_centre,
         "served": served,
