@@ -166,6 +166,23 @@ g3_status g3_normalize_pairs(const uint64_t* pair_hist, int32_t nbins, double rm
                              int64_t n_frames, int32_t n_atoms, const int32_t box[3],
                              double* g2_out);
 
+/* Superposition ratio (Kirkwood's approximation g3 ~ g2 g2 g2 tested bin by
+ * bin; the angle-resolved motivation of Sec. 3.3): out[x] = g3[x] /
+ * (g2[a] g2[b] g2[c]) for the bin (a, b, c) at index x of the layout, 0 where
+ * the product is 0.  g3 and out: host, g3_hist_len(nbins, layout) doubles
+ * (e.g. from g3_normalize); g2: host, nbins doubles (g3_normalize_pairs). */
+g3_status g3_superposition(const double* g3, int32_t layout, int32_t nbins, const double* g2,
+                           double* out);
+
+/* Isosceles slice g3(r, r, theta): both sides at the apex in bin a, third
+ * side in bin c = 0..nbins-1.  value[c] = g3(a, a, c) (either layout);
+ * theta[c] = the apex angle, in radians, of the triangle with both sides at
+ * the centre of bin a and the third side at the centre of bin c,
+ * 2 asin((c + 1/2) / (2 (a + 1/2))), or -1 where that third side exceeds
+ * twice the other two (no triangle).  Host arrays of nbins doubles. */
+g3_status g3_isosceles(const double* g3, int32_t layout, int32_t nbins, int32_t a,
+                       double* theta, double* value);
+
 /* W(a,b,c) for all bins (full layout, nbins^3 doubles, host). */
 g3_status g3_ideal_volume(int32_t nbins, double rmax, double* W_out);
 

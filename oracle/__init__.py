@@ -169,5 +169,31 @@ def normalize_pairs(H2: np.ndarray, nbins: int, rmax: float, n_frames: int, n_at
     return out
 
 
+def superposition_full(g3_full: np.ndarray, g2: np.ndarray) -> np.ndarray:
+    """Kirkwood superposition test: g3(a,b,c) / (g2(a) g2(b) g2(c)) on the
+    full nbins^3 array, 0 where the product is 0 (angle-resolved motivation
+    of Sec. 3.3).  Plain loops over bins."""
+    G = np.asarray(g3_full, dtype=np.float64)
+    nb = G.shape[0]
+    out = np.zeros_like(G)
+    for a in range(nb):
+        for b in range(nb):
+            for c in range(nb):
+                d = g2[a] * g2[b] * g2[c]
+                out[a, b, c] = G[a, b, c] / d if d > 0 else 0.0
+    return out
+
+
+def isosceles_angle(a: int, c: int) -> float:
+    """Apex angle of the isosceles triangle with both sides at the centre of
+    bin a and the third side at the centre of bin c (law of cosines), or -1
+    if no such triangle exists."""
+    import math
+    r, t = a + 0.5, c + 0.5
+    if t > 2 * r:
+        return -1.0
+    return math.acos(1.0 - t * t / (2.0 * r * r))
+
+
 def max_threads() -> int:
     return int(lib().g3o_max_threads())

@@ -1118,6 +1118,43 @@ g3_status g3_normalize_pairs(const uint64_t* pair_hist, int32_t nbins, double rm
     return G3_OK;
 }
 
+static size_t layout_index(int32_t layout, int32_t nb, int a, int b, int c)
+{
+    if (layout == G3_FULL) return ((size_t)a * nb + b) * nb + c;
+    const int lo = std::min(a, b), hi = std::max(a, b);
+    return ((size_t)lo * nb - (size_t)lo * (lo - 1) / 2 + (size_t)(hi - lo)) * nb + c;
+}
+
+g3_status g3_superposition(const double* g3, int32_t layout, int32_t nbins, const double* g2,
+                           double* out)
+{
+    if (!g3 || !g2 || !out || nbins < 1 || nbins > G3_MAX_NBINS) return G3_EINVAL;
+    if (layout != G3_HALF && layout != G3_FULL) return G3_EINVAL;
+    for (int a = 0; a < nbins; ++a)
+        for (int b = (layout == G3_HALF ? a : 0); b < nbins; ++b)
+            for (int c = 0; c < nbins; ++c) {
+                const size_t x = layout_index(layout, nbins, a, b, c);
+                const double d = g2[a] * g2[b] * g2[c];
+                out[x] = d > 0 ? g3[x] / d : 0.0;
+            }
+    return G3_OK;
+}
+
+g3_status g3_isosceles(const double* g3, int32_t layout, int32_t nbins, int32_t a, double* theta,
+                       double* value)
+{
+    if (!g3 || !theta || !value || nbins < 1 || nbins > G3_MAX_NBINS || a < 0 || a >= nbins)
+        return G3_EINVAL;
+    if (layout != G3_HALF && layout != G3_FULL) return G3_EINVAL;
+    const double r = a + 0.5;
+    for (int c = 0; c < nbins; ++c) {
+        const double t = c + 0.5;
+        theta[c] = t <= 2.0 * r ? 2.0 * std::asin(t / (2.0 * r)) : -1.0;
+        value[c] = g3[layout_index(layout, nbins, a, a, c)];
+    }
+    return G3_OK;
+}
+
 g3_status g3_set_tuning(g3_plan p, const g3_tuning* t)
 {
     if (!p || !t) return G3_EINVAL;

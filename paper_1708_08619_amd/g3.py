@@ -80,6 +80,8 @@ def lib():
         "g3_normalize": ([P, I32, I32, D, I64, I32, P, P], I32),
         "g3_ideal_volume": ([I32, D, P], I32),
         "g3_normalize_pairs": ([P, I32, D, I64, I32, P, P], I32),
+        "g3_superposition": ([P, I32, I32, P, P], I32),
+        "g3_isosceles": ([P, I32, I32, I32, P, P], I32),
         "g3_set_tuning": ([P, P], I32),
         "g3_get_tuning": ([P, P], I32),
         "g3_autotune": ([P, P, I32, P], I32),
@@ -161,6 +163,30 @@ def normalize_pairs(pair_hist: np.ndarray, nbins: int, rmax: float, n_frames: in
     _check(lib().g3_normalize_pairs(_np_ptr(h), int(nbins), float(rmax), int(n_frames),
                                     int(n_atoms), _box(box), _np_ptr(out)), "g3_normalize_pairs")
     return out
+
+
+def superposition(g3: np.ndarray, layout: int, nbins: int, g2: np.ndarray) -> np.ndarray:
+    """g3 / (g2 g2 g2) bin by bin (0 where the product is 0), host fp64."""
+    x = np.ascontiguousarray(g3, dtype=np.float64).reshape(-1)
+    y = np.ascontiguousarray(g2, dtype=np.float64).reshape(-1)
+    if x.shape[0] != hist_len(nbins, layout) or y.shape[0] != int(nbins):
+        raise ValueError("array lengths do not match nbins/layout")
+    out = np.zeros_like(x)
+    _check(lib().g3_superposition(_np_ptr(x), int(layout), int(nbins), _np_ptr(y), _np_ptr(out)),
+           "g3_superposition")
+    return out
+
+
+def isosceles(g3: np.ndarray, layout: int, nbins: int, a: int):
+    """(theta, g3(a, a, c)) for c = 0..nbins-1; theta -1 where no triangle."""
+    x = np.ascontiguousarray(g3, dtype=np.float64).reshape(-1)
+    if x.shape[0] != hist_len(nbins, layout):
+        raise ValueError("array length does not match nbins/layout")
+    th = np.zeros(int(nbins))
+    val = np.zeros(int(nbins))
+    _check(lib().g3_isosceles(_np_ptr(x), int(layout), int(nbins), int(a), _np_ptr(th),
+                              _np_ptr(val)), "g3_isosceles")
+    return th, val
 
 
 def strerror(status: int) -> str:

@@ -118,3 +118,38 @@ def test_normalize_pairs_vs_oracle(oracle_mod):
     assert np.max(np.abs(got / want - 1.0)) < 1e-12
     with pytest.raises(ValueError):
         g3.normalize_pairs(H2[:10], nb, rmax, F, N, box)
+
+
+@pytest.mark.parametrize("layout", [g3.HALF, g3.FULL])
+def test_superposition_vs_oracle(oracle_mod, layout):
+    nb = 9
+    rng = np.random.default_rng(30 + layout)
+    full = rng.uniform(0.0, 3.0, (nb, nb, nb))
+    full = (full + full.transpose(1, 0, 2)) / 2           # symmetric in the two centre sides
+    g2 = rng.uniform(0.2, 2.0, nb)
+    g2[4] = 0.0
+    want = oracle_mod.superposition_full(full, g2)
+    if layout == g3.FULL:
+        src, want_l = full.reshape(-1), want.reshape(-1)
+    else:
+        idx = [(a, b, c) for a in range(nb) for b in range(a, nb) for c in range(nb)]
+        src = np.array([full[i] for i in idx])
+        want_l = np.array([want[i] for i in idx])
+    got = g3.superposition(src, layout, nb, g2)
+    assert np.allclose(got, want_l, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("layout", [g3.HALF, g3.FULL])
+def test_isosceles_vs_oracle(oracle_mod, layout):
+    nb = 12
+    full = np.arange(nb ** 3, dtype=np.float64).reshape(nb, nb, nb)
+    full = np.minimum(full, full.transpose(1, 0, 2))       # symmetric, distinct per (lo, hi, c)
+    src = full.reshape(-1) if layout == g3.FULL else np.array(
+        [full[a, b, c] for a in range(nb) for b in range(a, nb) for c in range(nb)])
+    for a in (0, 3, 11):
+        th, val = g3.isosceles(src, layout, nb, a)
+        assert np.array_equal(val, full[a, a, :])
+        want = np.array([oracle_mod.isosceles_angle(a, c) for c in range(nb)])
+        assert np.allclose(th, want, rtol=1e-12, atol=1e-12)
+    with pytest.raises(g3.G3Error):
+        g3.isosceles(src, layout, nb, nb)

@@ -175,3 +175,25 @@ def test_large_system_pairs(g3mod, plan, torch_dev, oracle_mod):
     ((h, p),) = batch_pairs(g3mod, plan, torch_dev, [(fr, w.box, w.rmax, w.nbins, w.layout)])
     assert np.array_equal(p, oracle_mod.pair_hist(fr, w.box, w.rmax, w.nbins))
     assert np.array_equal(h, oracle_mod.hist(fr, w.box, w.rmax, w.nbins, w.layout))
+
+
+def test_superposition_chain_matches_oracle(g3mod, plan, torch_dev, oracle_mod):
+    """Histograms from the GPU, normalised and turned into the superposition
+    ratio and an isosceles slice by the library, equal the same chain run on
+    the oracle's histograms with the oracle's definitions."""
+    w = synth.lj_small("fcc", n_frames=4)
+    h, p = plain_pairs(g3mod, plan, torch_dev, w.frames, w.box, w.rmax, w.nbins, 1)
+    F, N, nb = w.frames.shape[0], w.frames.shape[2], w.nbins
+    g3v = g3mod.normalize(h, 1, nb, w.rmax, F, N, w.box)
+    g2v = g3mod.normalize_pairs(p, nb, w.rmax, F, N, w.box)
+    got = g3mod.superposition(g3v, 1, nb, g2v).reshape(nb, nb, nb)
+    Ho = oracle_mod.hist(w.frames, w.box, w.rmax, nb, 1)
+    Po = oracle_mod.pair_hist(w.frames, w.box, w.rmax, nb)
+    g3o = oracle_mod.normalize(Ho, 1, nb, w.rmax, F, N, w.box).reshape(nb, nb, nb)
+    g2o = oracle_mod.normalize_pairs(Po, nb, w.rmax, F, N, w.box)
+    want = oracle_mod.superposition_full(g3o, g2o)
+    assert np.allclose(got, want, rtol=1e-10, atol=0)
+    a = 20
+    th, val = g3mod.isosceles(g3v, 1, nb, a)
+    assert np.allclose(val, g3o[a, a, :], rtol=1e-10, atol=0)
+    assert np.allclose(th, [oracle_mod.isosceles_angle(a, c) for c in range(nb)], rtol=1e-12)

@@ -298,3 +298,29 @@ def test_ideal_gas_g2_is_one(oracle_mod):
     live = per.mean(0) > 20
     assert live.sum() >= nbins - 1
     assert np.all(np.abs(g[live] - 1.0) < 5 * sem_rel[live] + 1e-3), g
+
+
+# ---------------------------------------------------------------- post-processing
+def test_superposition_exact_product(oracle_mod):
+    """g3 equal to the product of pair factors gives ratio 1 wherever the
+    product is non-zero, and 0 where a factor vanishes."""
+    rng = np.random.default_rng(2)
+    nb = 7
+    g2 = rng.uniform(0.5, 2.0, nb)
+    g2[3] = 0.0
+    G = np.einsum("a,b,c->abc", g2, g2, g2) * 1.0
+    out = oracle_mod.superposition_full(G, g2)
+    live = np.einsum("a,b,c->abc", g2, g2, g2) > 0
+    assert np.allclose(out[live], 1.0, rtol=1e-14) and np.all(out[~live] == 0)
+
+
+def test_isosceles_angles(oracle_mod):
+    """Equilateral bins give 60 degrees, c = 2a + 1 would be degenerate, and
+    the angle grows with the third side."""
+    import math
+    for a in range(0, 30):
+        assert math.isclose(oracle_mod.isosceles_angle(a, a), math.pi / 3, rel_tol=1e-14)
+        angs = [oracle_mod.isosceles_angle(a, c) for c in range(2 * a + 1)]
+        assert all(x < y for x, y in zip(angs, angs[1:]))
+        assert oracle_mod.isosceles_angle(a, 2 * a + 1) == -1.0
+    assert math.isclose(oracle_mod.isosceles_angle(0, 0), math.pi / 3)
