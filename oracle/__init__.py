@@ -47,6 +47,19 @@ def lib():
         L.g3o_hist_full.argtypes = [P, C.c_int, C.c_int, P, C.c_double, C.c_int, P, C.c_int,
                                     P, C.c_int]
         L.g3o_hist_full.restype = C.c_int
+        L.g3o_hist_full3.argtypes = [P, C.c_int, C.c_int, P, C.c_double, C.c_int, C.c_int, P,
+                                     C.c_int, P, C.c_int]
+        L.g3o_hist_full3.restype = C.c_int
+        L.g3o_thresholds_n.argtypes = [C.c_double, C.c_int, C.c_int, P]
+        L.g3o_thresholds_n.restype = C.c_int
+        L.g3o_half_len3.argtypes = [C.c_int, C.c_int]
+        L.g3o_half_len3.restype = C.c_size_t
+        L.g3o_fold_half3.argtypes = [P, C.c_int, C.c_int, P]
+        L.g3o_fold_half3.restype = C.c_long
+        L.g3o_W_table3.argtypes = [C.c_int, C.c_int, C.c_double, P]
+        L.g3o_W_table3.restype = None
+        L.g3o_normalize3.argtypes = [P, C.c_int, C.c_int, C.c_int, P, C.c_int64, C.c_int64, P, P]
+        L.g3o_normalize3.restype = None
         L.g3o_pair_hist.argtypes = [P, C.c_int, C.c_int, P, C.c_double, C.c_int, P, C.c_int]
         L.g3o_pair_hist.restype = C.c_int
         L.g3o_fold_half.argtypes = [P, C.c_int, P]
@@ -71,6 +84,14 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def thresholds_n(rmax: float, nbins: int, count: int) -> np.ndarray:
+    """thr[b] = ceil((b rmax / nbins)^2) for b = 0..count."""
+    thr = np.zeros(count + 1, dtype=np.uint64)
+    if lib().g3o_thresholds_n(float(rmax), int(nbins), int(count), _p(thr)):
+        raise ValueError("oracle rejected the arguments")
+    return thr
+
+
 def thresholds(rmax: float, nbins: int) -> np.ndarray:
     thr = np.zeros(nbins + 1, dtype=np.uint64)
     if lib().g3o_thresholds(float(rmax), int(nbins), _p(thr)):
@@ -90,36 +111,38 @@ def _frames(frames) -> np.ndarray:
 
 
 def hist_full(frames, box, rmax: float, nbins: int, n_threads: int = 0,
-              centres=None) -> np.ndarray:
-    """H_full[b_ij][b_ik][b_jk] over ordered (j, k); shape (nbins,)*3 uint64."""
+              centres=None, nbins_third: int | None = None) -> np.ndarray:
+    """H_full[b_ij][b_ik][b_jk] over ordered (j, k); shape (nbins, nbins,
+    nbins_third) uint64 (third side in nbins_third bins of width rmax/nbins)."""
+    nc = int(nbins_third or nbins)
     fr = _frames(frames)
     bx = np.ascontiguousarray(box, dtype=np.int32)
-    H = np.zeros(nbins ** 3, dtype=np.uint64)
+    H = np.zeros(nbins * nbins * nc, dtype=np.uint64)
     if centres is not None:
         ct = np.ascontiguousarray(centres, dtype=np.int32)
-        cp, nc = _p(ct), len(ct)
+        cp, ncen = _p(ct), len(ct)
     else:
-        ct, cp, nc = None, None, 0
-    rc = lib().g3o_hist_full(_p(fr), fr.shape[0], fr.shape[2], _p(bx), float(rmax), int(nbins),
-                             _p(H), int(n_threads), cp, nc)
+        ct, cp, ncen = None, None, 0
+    rc = lib().g3o_hist_full3(_p(fr), fr.shape[0], fr.shape[2], _p(bx), float(rmax), int(nbins),
+                              nc, _p(H), int(n_threads), cp, ncen)
     if rc:
         raise ValueError("oracle rejected the arguments")
-    return H.reshape(nbins, nbins, nbins)
+    return H.reshape(nbins, nbins, nc)
 
 
 def fold_half(full: np.ndarray) -> tuple[np.ndarray, int]:
     """(H_half flat, number of symmetry violations)."""
-    nbins = full.shape[0]
+    nbins, nc = full.shape[0], full.shape[2]
     f = np.ascontiguousarray(full, dtype=np.uint64).reshape(-1)
-    half = np.zeros(lib().g3o_half_len(nbins), dtype=np.uint64)
-    bad = lib().g3o_fold_half(_p(f), nbins, _p(half))
+    half = np.zeros(lib().g3o_half_len3(nbins, nc), dtype=np.uint64)
+    bad = lib().g3o_fold_half3(_p(f), nbins, nc, _p(half))
     return half, int(bad)
 
 
 def hist(frames, box, rmax: float, nbins: int, layout: int, n_threads: int = 0,
-         centres=None) -> np.ndarray:
+         centres=None, nbins_third: int | None = None) -> np.ndarray:
     """Flat histogram in the library's layout (0 = half, 1 = full)."""
-    full = hist_full(frames, box, rmax, nbins, n_threads, centres)
+    full = hist_full(frames, box, rmax, nbins, n_threads, centres, nbins_third)
     if layout == 1:
         return full.reshape(-1)
     half, bad = fold_half(full)
@@ -142,20 +165,22 @@ def W_box(a0, a1, b0, b1, c0, c1) -> float:
     return float(lib().g3o_W_box(a0, a1, b0, b1, c0, c1))
 
 
-def W_table(nbins: int, dr: float) -> np.ndarray:
-    W = np.zeros(nbins ** 3, dtype=np.float64)
-    lib().g3o_W_table(int(nbins), float(dr), _p(W))
-    return W.reshape(nbins, nbins, nbins)
+def W_table(nbins: int, dr: float, nbins_third: int | None = None) -> np.ndarray:
+    nc = int(nbins_third or nbins)
+    W = np.zeros(nbins * nbins * nc, dtype=np.float64)
+    lib().g3o_W_table3(int(nbins), nc, float(dr), _p(W))
+    return W.reshape(nbins, nbins, nc)
 
 
 def normalize(H: np.ndarray, layout: int, nbins: int, rmax: float, n_frames: int,
-              n_atoms: int, box) -> np.ndarray:
-    W = np.ascontiguousarray(W_table(nbins, rmax / nbins).reshape(-1))
+              n_atoms: int, box, nbins_third: int | None = None) -> np.ndarray:
+    nc = int(nbins_third or nbins)
+    W = np.ascontiguousarray(W_table(nbins, rmax / nbins, nc).reshape(-1))
     Hc = np.ascontiguousarray(H, dtype=np.uint64).reshape(-1)
     out = np.zeros(Hc.shape[0], dtype=np.float64)
     bx = np.ascontiguousarray(box, dtype=np.int32)
-    lib().g3o_normalize(_p(Hc), int(layout == 1), int(nbins), _p(W), int(n_frames),
-                        int(n_atoms), _p(bx), _p(out))
+    lib().g3o_normalize3(_p(Hc), int(layout == 1), int(nbins), nc, _p(W), int(n_frames),
+                         int(n_atoms), _p(bx), _p(out))
     return out
 
 

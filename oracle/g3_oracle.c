@@ -42,22 +42,24 @@
 
 typedef unsigned __int128 u128;
 
-#define G3O_MAX_NBINS 255
+#define G3O_MAX_NBINS 512
 
-/* Exact thresholds thr[b] = ceil((b * rmax / nbins)^2), b = 0..nbins.
+/* Exact thresholds thr[b] = ceil((b * rmax / nbins)^2) for b = 0..count
+ * (bins of width rmax / nbins; count >= nbins extends them past rmax).
  * rmax is decomposed as m * 2^e with m odd (or e >= 0), which makes the
  * square an exact rational b^2 m^2 2^(2e) / nbins^2.  Returns 0, or -1 for
- * arguments outside 1 <= rmax < 2^31, 1 <= nbins <= 255. */
-int g3o_thresholds(double rmax, int nbins, uint64_t *thr)
+ * arguments outside 1 <= rmax < 2^31, 1 <= nbins <= count <= 512. */
+int g3o_thresholds_n(double rmax, int nbins, int count, uint64_t *thr)
 {
-    if (!(rmax >= 1.0) || !(rmax < 2147483648.0) || nbins < 1 || nbins > G3O_MAX_NBINS)
+    if (!(rmax >= 1.0) || !(rmax < 2147483648.0) || nbins < 1 || count < nbins ||
+        count > G3O_MAX_NBINS)
         return -1;
     int E;
     double f = frexp(rmax, &E);                 /* rmax = f * 2^E, f in [0.5, 1) */
     int64_t m = (int64_t)ldexp(f, 53);          /* exact 53-bit integer */
     int e = E - 53;
     while ((m & 1) == 0 && e < 0) { m >>= 1; e++; }
-    for (int b = 0; b <= nbins; b++) {
+    for (int b = 0; b <= count; b++) {
         u128 q;
         u128 den = (u128)nbins * (u128)nbins;
         if (e >= 0) {
@@ -72,6 +74,11 @@ int g3o_thresholds(double rmax, int nbins, uint64_t *thr)
         thr[b] = (uint64_t)q;
     }
     return 0;
+}
+
+int g3o_thresholds(double rmax, int nbins, uint64_t *thr)
+{
+    return g3o_thresholds_n(rmax, nbins, nbins, thr);
 }
 
 /* b(s) = max{b : thr[b] <= s}; -1 if s >= thr[nbins]. */
@@ -121,18 +128,26 @@ static int neighbours(const int32_t *fr, int N, const int32_t *box, int i,
     return n;
 }
 
-/* H_full (nbins^3, row-major [b_ij][b_ik][b_jk]) over all frames.
+/* H_full ([b_ij][b_ik][b_jk], nbins x nbins x nbins_third, row-major) over
+ * all frames.  The two sides at the centre are below rmax (nbins bins of
+ * width rmax / nbins); the third side, from the updated positions, is binned
+ * in nbins_third bins of the same width, i.e. kept below
+ * nbins_third * rmax / nbins.  nbins_third = nbins is the one-cutoff reading;
+ * nbins_third = 2 nbins with rmax = L/4 is the paper's geometry (two sides
+ * below L/4, the third below L/2, Sec. 3.3).
  * frames: [n_frames][3][n_atoms] int32.  Adds into H (caller zeroes it).
  * n_threads <= 0 uses the OpenMP default.  If centres != NULL only the
  * listed centre indices (n_centres of them) contribute.  Returns 0 or -1. */
-int g3o_hist_full(const int32_t *frames, int n_frames, int n_atoms, const int32_t *box,
-                  double rmax, int nbins, uint64_t *H, int n_threads,
-                  const int32_t *centres, int n_centres)
+int g3o_hist_full3(const int32_t *frames, int n_frames, int n_atoms, const int32_t *box,
+                   double rmax, int nbins, int nbins_third, uint64_t *H, int n_threads,
+                   const int32_t *centres, int n_centres)
 {
     if (check_args(box, rmax, nbins, n_atoms)) return -1;
+    if (nbins_third < nbins || nbins_third > 2 * nbins) return -1;
     uint64_t thr[G3O_MAX_NBINS + 1];
-    if (g3o_thresholds(rmax, nbins, thr)) return -1;
-    const size_t nb3 = (size_t)nbins * nbins * nbins;
+    if (g3o_thresholds_n(rmax, nbins, nbins_third, thr)) return -1;
+    const int nc = nbins_third;
+    const size_t nb3 = (size_t)nbins * nbins * nc;
     const int n_ctr = centres ? n_centres : n_atoms;
     int nt = 1;
 #ifdef _OPENMP
@@ -171,9 +186,9 @@ int g3o_hist_full(const int32_t *frames, int n_frames, int n_atoms, const int32_
                         int64_t ex = nb[q].d[0] - nb[p].d[0];
                         int64_t ey = nb[q].d[1] - nb[p].d[1];
                         int64_t ez = nb[q].d[2] - nb[p].d[2];
-                        int c = g3o_bin((uint64_t)(ex * ex + ey * ey + ez * ez), thr, nbins);
+                        int c = g3o_bin((uint64_t)(ex * ex + ey * ey + ez * ez), thr, nc);
                         if (c < 0) continue;
-                        Ht[((size_t)nb[p].b * nbins + nb[q].b) * nbins + c] += 1;
+                        Ht[((size_t)nb[p].b * nbins + nb[q].b) * nc + c] += 1;
                     }
                 }
             }
@@ -185,6 +200,14 @@ int g3o_hist_full(const int32_t *frames, int n_frames, int n_atoms, const int32_
             for (size_t x = 0; x < nb3; x++) H[x] += priv[(size_t)t * nb3 + x];
     free(priv);
     return err ? -1 : 0;
+}
+
+int g3o_hist_full(const int32_t *frames, int n_frames, int n_atoms, const int32_t *box,
+                  double rmax, int nbins, uint64_t *H, int n_threads,
+                  const int32_t *centres, int n_centres)
+{
+    return g3o_hist_full3(frames, n_frames, n_atoms, box, rmax, nbins, nbins, H, n_threads,
+                          centres, n_centres);
 }
 
 /* Pair histogram of ORDERED pairs (i, j), i != j, |mi(x_j - x_i)| < rmax,
@@ -239,37 +262,51 @@ int g3o_pair_hist(const int32_t *frames, int n_frames, int n_atoms, const int32_
 }
 
 /* Half-layout index of (lo, hi, c), lo <= hi: rows lo hold hi = lo..nbins-1. */
-static size_t half_index(int lo, int hi, int c, int nbins)
+/* Half-layout index of (lo, hi, c), lo <= hi: rows lo hold hi = lo..nbins-1,
+ * each with nc third-side bins. */
+static size_t half_index3(int lo, int hi, int c, int nbins, int nc)
 {
     size_t rowoff = (size_t)lo * nbins - (size_t)lo * (lo - 1) / 2;
-    return (rowoff + (size_t)(hi - lo)) * nbins + c;
+    return (rowoff + (size_t)(hi - lo)) * nc + c;
+}
+
+
+size_t g3o_half_len3(int nbins, int nc)
+{
+    return (size_t)nbins * (nbins + 1) / 2 * nc;
 }
 
 size_t g3o_half_len(int nbins)
 {
-    return (size_t)nbins * (nbins + 1) / 2 * nbins;
+    return g3o_half_len3(nbins, nbins);
 }
 
-/* Fold H_full into the half layout.  Returns the number of (a, b, c) where
- * the fold is inconsistent (H_full[a][b][c] != H_full[b][a][c], or an odd
- * diagonal count); 0 means H_full had the symmetry the definition implies. */
-long g3o_fold_half(const uint64_t *full, int nbins, uint64_t *half)
+/* Fold H_full (nbins x nbins x nc) into the half layout.  Returns the number
+ * of (a, b, c) where the fold is inconsistent (H_full[a][b][c] !=
+ * H_full[b][a][c], or an odd diagonal count); 0 means H_full had the
+ * symmetry the definition implies. */
+long g3o_fold_half3(const uint64_t *full, int nbins, int nc, uint64_t *half)
 {
     long bad = 0;
     for (int a = 0; a < nbins; a++)
         for (int b = a; b < nbins; b++)
-            for (int c = 0; c < nbins; c++) {
-                uint64_t v = full[((size_t)a * nbins + b) * nbins + c];
-                uint64_t w = full[((size_t)b * nbins + a) * nbins + c];
+            for (int c = 0; c < nc; c++) {
+                uint64_t v = full[((size_t)a * nbins + b) * nc + c];
+                uint64_t w = full[((size_t)b * nbins + a) * nc + c];
                 if (a == b) {
                     if (v & 1) bad++;
-                    half[half_index(a, b, c, nbins)] = v / 2;
+                    half[half_index3(a, b, c, nbins, nc)] = v / 2;
                 } else {
                     if (v != w) bad++;
-                    half[half_index(a, b, c, nbins)] = v;
+                    half[half_index3(a, b, c, nbins, nc)] = v;
                 }
             }
     return bad;
+}
+
+long g3o_fold_half(const uint64_t *full, int nbins, uint64_t *half)
+{
+    return g3o_fold_half3(full, nbins, nbins, half);
 }
 
 /* ---------------------------------------------------------------------------
@@ -372,41 +409,52 @@ double g3o_W_box(double a0, double a1, double b0, double b1, double c0, double c
     return 8.0 * M_PI * M_PI * acc;
 }
 
-/* W(a, b, c) for every bin of width dr, full layout [a][b][c]. */
-void g3o_W_table(int nbins, double dr, double *W)
+/* W(a, b, c) for every bin of width dr, full layout [a][b][c], c < nc. */
+void g3o_W_table3(int nbins, int nc, double dr, double *W)
 {
     for (int a = 0; a < nbins; a++)
         for (int b = 0; b < nbins; b++)
-            for (int c = 0; c < nbins; c++)
-                W[((size_t)a * nbins + b) * nbins + c] =
+            for (int c = 0; c < nc; c++)
+                W[((size_t)a * nbins + b) * nc + c] =
                     g3o_W_box(a * dr, (a + 1) * dr, b * dr, (b + 1) * dr, c * dr, (c + 1) * dr);
+}
+
+void g3o_W_table(int nbins, double dr, double *W)
+{
+    g3o_W_table3(nbins, nbins, dr, W);
 }
 
 /* g3 = H / E with E = F N (N-1)(N-2) / V^2 * W (ordered pairs, full layout);
  * in the half layout E is halved on the diagonal lo == hi.  g3 = 0 where W = 0.
  * H and g3 have the layout's length; W is the full table from g3o_W_table. */
-void g3o_normalize(const uint64_t *H, int layout_full, int nbins, const double *W,
-                   int64_t n_frames, int64_t n_atoms, const int32_t *box, double *g3)
+void g3o_normalize3(const uint64_t *H, int layout_full, int nbins, int nc, const double *W,
+                    int64_t n_frames, int64_t n_atoms, const int32_t *box, double *g3)
 {
     double V = (double)box[0] * (double)box[1] * (double)box[2];
     double Nd = (double)n_atoms;
     double pref = (double)n_frames * Nd * (Nd - 1.0) * (Nd - 2.0) / (V * V);
     if (layout_full) {
-        size_t nb3 = (size_t)nbins * nbins * nbins;
-        for (size_t x = 0; x < nb3; x++) {
+        size_t n = (size_t)nbins * nbins * nc;
+        for (size_t x = 0; x < n; x++) {
             double E = pref * W[x];
             g3[x] = E > 0 ? (double)H[x] / E : 0.0;
         }
     } else {
         for (int a = 0; a < nbins; a++)
             for (int b = a; b < nbins; b++)
-                for (int c = 0; c < nbins; c++) {
-                    double E = pref * W[((size_t)a * nbins + b) * nbins + c];
+                for (int c = 0; c < nc; c++) {
+                    double E = pref * W[((size_t)a * nbins + b) * nc + c];
                     if (a == b) E *= 0.5;
-                    size_t x = half_index(a, b, c, nbins);
+                    size_t x = half_index3(a, b, c, nbins, nc);
                     g3[x] = E > 0 ? (double)H[x] / E : 0.0;
                 }
     }
+}
+
+void g3o_normalize(const uint64_t *H, int layout_full, int nbins, const double *W,
+                   int64_t n_frames, int64_t n_atoms, const int32_t *box, double *g3)
+{
+    g3o_normalize3(H, layout_full, nbins, nbins, W, n_frames, n_atoms, box, g3);
 }
 
 /* g2(r) from the ordered pair histogram (the paper computes g2 beside g3,

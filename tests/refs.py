@@ -21,6 +21,19 @@ from fractions import Fraction
 import numpy as np
 
 
+def frac_bin_n(s: int, rmax: float, nbins: int, count: int) -> int:
+    """Bins of width rmax / nbins, count of them: max{b : s >= (b rmax /
+    nbins)^2} if s < (count rmax / nbins)^2, else -1 (exact)."""
+    R = Fraction(rmax)
+    lhs = Fraction(s) * nbins * nbins
+    if lhs >= Fraction(count * count) * R * R:
+        return -1
+    b = 0
+    while b + 1 < count and lhs >= Fraction((b + 1) ** 2) * R * R:
+        b += 1
+    return b
+
+
 def frac_bin(s: int, rmax: float, nbins: int) -> int:
     """max{b : s >= (b rmax / nbins)^2} if s < rmax^2, else -1 (exact)."""
     R = Fraction(rmax)
@@ -42,16 +55,23 @@ def min_image(d: int, L: int) -> int:
     return d
 
 
-def brute_full(frames, box, rmax: float, nbins: int) -> np.ndarray:
+def brute_full(frames, box, rmax: float, nbins: int, nbins_third: int | None = None) -> np.ndarray:
+    nc = nbins_third or nbins
     fr = np.asarray(frames, dtype=np.int64)
     F, _, N = fr.shape
-    H = np.zeros((nbins, nbins, nbins), dtype=np.uint64)
+    H = np.zeros((nbins, nbins, nc), dtype=np.uint64)
     cache: dict[int, int] = {}
+    cache3: dict[int, int] = {}
 
     def b(s):
         if s not in cache:
             cache[s] = frac_bin(s, rmax, nbins)
         return cache[s]
+
+    def b3(s):
+        if s not in cache3:
+            cache3[s] = frac_bin_n(s, rmax, nbins, nc)
+        return cache3[s]
 
     for f in range(F):
         P = [tuple(int(fr[f, d, a]) for d in range(3)) for a in range(N)]
@@ -71,20 +91,20 @@ def brute_full(frames, box, rmax: float, nbins: int) -> np.ndarray:
                     if bik < 0:
                         continue
                     djk = [dik[d] - dij[d] for d in range(3)]   # updated positions
-                    bjk = b(sum(x * x for x in djk))
+                    bjk = b3(sum(x * x for x in djk))
                     if bjk < 0:
                         continue
                     H[bij, bik, bjk] += 1
     return H
 
 
-def _bins_np(s: np.ndarray, rmax: float, nbins: int) -> np.ndarray:
+def _bins_np(s: np.ndarray, rmax: float, nbins: int, count: int | None = None) -> np.ndarray:
     """Exact bins for an int64 array via per-value Fraction decisions."""
     out = np.empty(s.shape, dtype=np.int64)
     flat = s.reshape(-1)
     o = out.reshape(-1)
     uniq, inv = np.unique(flat, return_inverse=True)
-    ub = np.array([frac_bin(int(v), rmax, nbins) for v in uniq], dtype=np.int64)
+    ub = np.array([frac_bin_n(int(v), rmax, nbins, count or nbins) for v in uniq], dtype=np.int64)
     o[:] = ub[inv]
     return out
 
@@ -146,17 +166,20 @@ def diamond_vectors(a_u: int, reach: float) -> np.ndarray:
     return v[(n2 > 0) & (n2 < reach * reach)]
 
 
-def lattice_full(vectors: np.ndarray, n_sites: int, rmax: float, nbins: int) -> np.ndarray:
-    """N x #{(u, v): u != v, |u|, |v|, |v - u| < rmax} binned (ordered)."""
+def lattice_full(vectors: np.ndarray, n_sites: int, rmax: float, nbins: int,
+                 nbins_third: int | None = None) -> np.ndarray:
+    """N x #{(u, v): u != v, |u|, |v| < rmax, |v - u| < nbins_third rmax /
+    nbins} binned (ordered)."""
+    nc = nbins_third or nbins
     v = np.asarray(vectors, dtype=np.int64)
     bv = _bins_np((v * v).sum(-1), rmax, nbins)
     keep = bv >= 0
     v, bv = v[keep], bv[keep]
     D = v[None, :, :] - v[:, None, :]                   # D[p, q] = v_q - v_p
-    bd = _bins_np((D * D).sum(-1), rmax, nbins)
+    bd = _bins_np((D * D).sum(-1), rmax, nbins, nc)
     P, Q = np.meshgrid(np.arange(len(v)), np.arange(len(v)), indexing="ij")
     m = (P != Q) & (bd >= 0)
-    H = np.zeros((nbins, nbins, nbins), dtype=np.uint64)
+    H = np.zeros((nbins, nbins, nc), dtype=np.uint64)
     np.add.at(H, (bv[P[m]], bv[Q[m]], bd[m]), 1)
     return H * np.uint64(n_sites)
 

@@ -324,3 +324,63 @@ def test_isosceles_angles(oracle_mod):
         assert all(x < y for x, y in zip(angs, angs[1:]))
         assert oracle_mod.isosceles_angle(a, 2 * a + 1) == -1.0
     assert math.isclose(oracle_mod.isosceles_angle(0, 0), math.pi / 3)
+
+
+# ---------------------------------------------------------------- paper geometry (third side to 2 rmax)
+@pytest.mark.parametrize("seed", range(4))
+def test_third_axis_brute_force(oracle_mod, seed):
+    """Third side binned over nbins_third bins of the same width (up to
+    2 nbins: the paper's L/4, L/2 geometry when rmax = L/4), Fraction exact."""
+    rng = np.random.default_rng(500 + seed)
+    box = [int(x) for x in rng.integers(300, 700, size=3)]
+    rmax = float(rng.uniform(min(box) / 6.0, min(box) / 4.0))
+    nbins = int(rng.integers(3, 7))
+    nc = nbins + int(rng.integers(1, nbins + 1))
+    fr = _random_system(rng, int(rng.integers(18, 26)), box)
+    want = refs.brute_full(fr, box, rmax, nbins, nc)
+    got = oracle_mod.hist_full(fr, box, rmax, nbins, n_threads=2, nbins_third=nc)
+    assert np.array_equal(got, want)
+    # the first nbins third-side bins are the one-cutoff histogram
+    assert np.array_equal(got[:, :, :nbins], oracle_mod.hist_full(fr, box, rmax, nbins))
+    assert got[:, :, nbins:].sum() > 0
+
+
+def test_third_axis_perfect_fcc(oracle_mod):
+    n = 4
+    L = synth.cubic_lattice_box(256, 0.8, synth.LJ_UNIT_PER_SIGMA, n, 2 * n)
+    a = L // n
+    sites = synth.fcc_sites(n, a)
+    fr = synth.lattice_frames(sites, len(sites), [L] * 3, 0.0, 1, 0)
+    rmax, nbins = L / 4.0, 20
+    got = oracle_mod.hist_full(fr, [L] * 3, rmax, nbins, nbins_third=2 * nbins)
+    want = refs.lattice_full(refs.fcc_vectors(a, rmax), len(sites), rmax, nbins, 2 * nbins)
+    assert np.array_equal(got, want) and got[:, :, nbins:].sum() > 0
+
+
+def test_third_axis_W_covers_every_triangle(oracle_mod):
+    """With 2 nbins third-side bins every t in [|r-s|, r+s] is inside, so the
+    third-side marginal of W is the product of the two shell volumes."""
+    import math
+    nb, dr = 8, 0.25
+    W = oracle_mod.W_table(nb, dr, 2 * nb)
+    for a in range(nb):
+        for b in range(nb):
+            want = (4 * math.pi / 3) ** 2 * ((a + 1) ** 3 - a ** 3) * ((b + 1) ** 3 - b ** 3) * dr ** 6
+            assert math.isclose(W[a, b].sum(), want, rel_tol=1e-12), (a, b)
+    assert np.allclose(W[:, :, :nb], oracle_mod.W_table(nb, dr), rtol=1e-13, atol=0)
+
+
+def test_third_axis_ideal_gas_g3_is_one(oracle_mod):
+    N, F, nbins, L = 128, 40, 3, 12000
+    rmax = L / 4.0
+    w = synth.ideal_gas(N, [L, L, L], F, rmax, nbins, layout=1, seed=(synth.SEED_BASE, 8))
+    per = np.stack([oracle_mod.hist_full(w.frames[f:f + 1], w.box, rmax, nbins,
+                                         nbins_third=2 * nbins).astype(np.float64)
+                    for f in range(F)])
+    Wt = oracle_mod.W_table(nbins, rmax / nbins, 2 * nbins)
+    E1 = N * (N - 1) * (N - 2) / float(L) ** 6 * Wt
+    m, sem = per.mean(0), per.std(0, ddof=1) / math.sqrt(F)
+    live = E1 > 50
+    assert live[:, :, nbins:].any()
+    z = (m[live] - E1[live]) / np.maximum(sem[live], 1e-9)
+    assert np.all(np.abs(z) < 5.0), z.max()
