@@ -82,6 +82,18 @@ typedef struct {
     int32_t layout;
     uint64_t* hist;
     uint64_t* pair_hist;     /* optional, may be NULL */
+    int32_t nbins_third;     /* bins of the third side (b_jk), same width
+                                rmax / nbins: 0 or nbins = third side below
+                                rmax; up to 2 nbins = below nbins_third * rmax /
+                                nbins.  With rmax = L/4 and 2 nbins this is the
+                                paper's geometry (Sec. 3.3: two sides below L/4,
+                                the third below L/2).  hist then has
+                                g3_hist_len3(nbins, nbins_third, layout) bins,
+                                index ((b_ij * nbins + b_ik) * nbins_third + c)
+                                (full) or ((rowoff(lo) + hi - lo) * nbins_third
+                                + c) (half).  Requires nbins_third * rmax /
+                                nbins <= G3_MAX_RMAX; such a system always uses
+                                the per-centre enumeration (g3_tuning). */
 } g3_system;
 
 /* Tuning knobs of the triplet kernel (chosen by g3_autotune or set by hand).
@@ -115,6 +127,10 @@ g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames,
                         int32_t nbins, int32_t layout, uint64_t* hist,
                         uint64_t* pair_hist);
 
+/* Plain form for one described system (all g3_system fields, including
+ * pair_hist and nbins_third); otherwise as g3_accumulate. */
+g3_status g3_accumulate_system(g3_plan p, const g3_system* system);
+
 /* Batched form: every frame of every system in ONE launch sequence (batched
  * cell and neighbour builds, one persistent triplet kernel pulling work items
  * from a device counter, one flush at the end), replayed as a hipGraph once
@@ -139,6 +155,9 @@ g3_status g3_query(g3_plan p);
 /* Histogram length for (nbins, layout); 0 if invalid. */
 size_t g3_hist_len(int32_t nbins, int32_t layout);
 
+/* Histogram length with nbins_third third-side bins (nbins..2 nbins). */
+size_t g3_hist_len3(int32_t nbins, int32_t nbins_third, int32_t layout);
+
 /* Host-side validation of one system's arguments (no device work). */
 g3_status g3_check_args(int32_t n_atoms, const int32_t box[3], double rmax,
                         int32_t nbins, int32_t layout);
@@ -157,6 +176,12 @@ g3_status g3_thresholds(double rmax, int32_t nbins, uint32_t* thr);
 g3_status g3_normalize(const uint64_t* hist, int32_t layout, int32_t nbins, double rmax,
                        int64_t n_frames, int32_t n_atoms, const int32_t box[3],
                        double* g3_out);
+
+/* g3_normalize for a histogram with nbins_third third-side bins (the same
+ * formula; W(a, b, c) for c up to nbins_third - 1). */
+g3_status g3_normalize3(const uint64_t* hist, int32_t layout, int32_t nbins,
+                        int32_t nbins_third, double rmax, int64_t n_frames,
+                        int32_t n_atoms, const int32_t box[3], double* g3_out);
 
 /* Ideal-gas normalisation of the pair histogram (host, fp64):
  *   g2[b] = H2[b] / E2[b],  E2[b] = n_frames * N (N-1) / V * 4 pi/3 (r_{b+1}^3 - r_b^3),

@@ -9,7 +9,8 @@
 
 namespace g3 {
 
-constexpr int kMaxSlabs = 24;          // r12 slabs per system
+constexpr int kMaxSlabs = 63;          // r12 slabs per system (slab counts fit one wave)
+constexpr int kThrMax = 512;           // threshold table entries (third-side bins + 1)
 constexpr int kTripletThreads = 1024;  // threads of the triplet workgroup
 constexpr int kTabBytes = 8192;        // LDS bytes of the bin lookup table
 constexpr int kWave = 64;
@@ -37,7 +38,10 @@ struct Sys {
     int32_t nc[3];           // cells per axis; 1 means "whole axis, explicit minimum image"
     int32_t ncell;
     int32_t C;               // ceil(rmax): every accepted component satisfies |d| <= C-1
-    uint32_t R2;             // thr[nbins]: s accepted iff s < R2
+    uint32_t R2;             // thr[nbins]: a pair is accepted iff s < R2
+    int32_t C3;              // least C3 with C3^2 >= R3: third-side components |d| <= C3-1
+    uint32_t R3;             // thr[nb3]: a third side is accepted iff s < R3
+    int32_t nb3;             // third-side bins (nbins..2 nbins); entries carry b * nb3
     int32_t nbins, layout, wide;
     int32_t sh, tab_len;     // bin table: tab[s >> sh] is b(s) or b(s)-1 or lower
     int32_t tab_bits;        // tab_len = 2^tab_bits
@@ -104,11 +108,11 @@ struct TripletArgs {
     unsigned long long* cand;  // running count of candidate (centre, {j,k}) pairs evaluated
 };
 
-// Triplet kernel LDS: thr (1 KB), bin table, 64 trash words, 32 words of
+// Triplet kernel LDS: thr (2 KB), bin table, 64 trash words, 32 words of
 // scalars, 256 sort buckets, then the histogram slab and per-item centre
 // arrays and the work-unit chunk table (uint16, one per 64 units).
 constexpr int kChunkCap = 2048;
-constexpr uint32_t kTripletLdsFixed = 1024 + kTabBytes + 256 + 128 + 1024;
+constexpr uint32_t kTripletLdsFixed = 4 * kThrMax + kTabBytes + 256 + 128 + 1024;
 inline size_t triplet_lds_bytes(int hb_max, int cb)
 {
     return kTripletLdsFixed + (size_t)hb_max * 4 + (size_t)(3 * cb + 1) * 4 + 2 * kChunkCap;

@@ -22,7 +22,7 @@ namespace {
 
 using namespace g3;
 
-constexpr int kListCap = 1024;       // neighbours per centre held by the triplet kernel
+constexpr int kListCap = 4096;       // neighbours per centre held by the triplet kernel
 constexpr int kStageCap = 1024;      // stencil atoms staged in LDS by the neighbour build
 constexpr int kTabMax = kTabBytes;   // bytes of the bin lookup table in LDS
 constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
@@ -65,11 +65,14 @@ bool t_covers(uint64_t t, int b, int nbins, const ExactR& R)
     return lhs >= bm * bm;
 }
 
-void exact_thresholds(double rmax, int nbins, std::vector<uint32_t>& thr)
+// thr[b] for b = 0..count (count >= nbins extends the bins of width
+// rmax / nbins past rmax).
+void exact_thresholds(double rmax, int nbins, std::vector<uint32_t>& thr, int count = 0)
 {
     const ExactR R = exact_of(rmax);
-    thr.resize(nbins + 1);
-    for (int b = 0; b <= nbins; ++b) {
+    if (count < nbins) count = nbins;
+    thr.resize(count + 1);
+    for (int b = 0; b <= count; ++b) {
         const long double x = (long double)b * (long double)rmax / (long double)nbins;
         long double est = std::ceil(x * x);
         uint64_t t = est > 2.0L ? (uint64_t)est - 2 : 0;
@@ -82,9 +85,10 @@ void exact_thresholds(double rmax, int nbins, std::vector<uint32_t>& thr)
 // ------------------------------------------------------------------ geometry
 struct Geometry {
     int N = 0, nbins = 0, layout = 0, wide = 0;
+    int nb3 = 0;               // third-side bins (same width), nbins..2 nbins
     int box[3] = {0, 0, 0}, nc[3] = {1, 1, 1}, ncell = 1;
-    int C = 0;
-    uint32_t R2 = 0;
+    int C = 0, C3 = 0;         // ceil of the pair cutoff; least C3 with C3^2 >= R3
+    uint32_t R2 = 0, R3 = 0;   // thr[nbins], thr[nb3]
     int sh = 0, tab_len = 0, tab_bits = 0, one_step = 0;
     std::vector<uint32_t> thr;
     std::vector<uint8_t> tab;
@@ -101,6 +105,19 @@ g3_status check(int32_t n_atoms, const int32_t box[3], double rmax, int32_t nbin
         if (box[d] <= 0 || box[d] > (1 << 29)) return G3_EINVAL;
         if (!(2.0 * rmax < (double)box[d])) return G3_EINVAL;
     }
+    return G3_OK;
+}
+
+// The third side's bin count: 0 means nbins; at most 2 nbins (the paper's
+// geometry, third side below L/2 when rmax = L/4), and its cutoff
+// nb3 * rmax / nbins within G3_MAX_RMAX.
+g3_status check3(int32_t n_atoms, const int32_t box[3], double rmax, int32_t nbins, int32_t nb3,
+                 int32_t layout)
+{
+    g3_status st = check(n_atoms, box, rmax, nbins, layout);
+    if (st) return st;
+    if (nb3 != 0 && (nb3 < nbins || nb3 > 2 * nbins)) return G3_EINVAL;
+    if (nb3 > nbins && !((double)nb3 * rmax / (double)nbins <= G3_MAX_RMAX)) return G3_EINVAL;
     return G3_OK;
 }
 
@@ -134,15 +151,20 @@ void plan_cells(Geometry& g)
 // (to fit kTabMax bytes) only costs a few more steps.
 void plan_bins(Geometry& g, double rmax)
 {
-    exact_thresholds(rmax, g.nbins, g.thr);
+    exact_thresholds(rmax, g.nbins, g.thr, g.nb3);
     g.R2 = g.thr[g.nbins];
+    g.R3 = g.thr[g.nb3];
+    g.C3 = (int)std::ceil(std::sqrt((double)g.R3));
+    while ((uint64_t)(g.C3 - 1) * (uint64_t)(g.C3 - 1) >= g.R3) --g.C3;
+    while ((uint64_t)g.C3 * (uint64_t)g.C3 < g.R3) ++g.C3;
     const double dr2 = (rmax / g.nbins) * (rmax / g.nbins);
     int sh = 0;
     while (sh < 31 && std::ldexp(1.0, sh + 1) <= dr2) ++sh;
-    while (((uint64_t)g.R2 + ((1ull << sh) - 1)) >> sh > (uint64_t)kTabMax) ++sh;
+    // the table covers every accepted third side, s < R3 (>= R2)
+    while (((uint64_t)g.R3 + ((1ull << sh) - 1)) >> sh > (uint64_t)kTabMax) ++sh;
     g.sh = sh;
     // a power-of-two table, so that a bit-field extract of s indexes it
-    const int need = (int)(((uint64_t)g.R2 + ((1ull << sh) - 1)) >> sh);
+    const int need = (int)(((uint64_t)g.R3 + ((1ull << sh) - 1)) >> sh);
     g.tab_bits = 0;
     while ((1 << g.tab_bits) < need) ++g.tab_bits;
     g.tab_len = 1 << g.tab_bits;
@@ -150,20 +172,23 @@ void plan_bins(Geometry& g, double rmax)
     int b = 0;
     for (int q = 0; q < g.tab_len; ++q) {
         const uint64_t s = (uint64_t)q << sh;
-        while (b + 1 < g.nbins && s >= g.thr[b + 1]) ++b;
+        while (b + 1 < g.nb3 && s >= g.thr[b + 1]) ++b;
         g.tab[q] = (uint8_t)b;
     }
     // one threshold step suffices iff no table cell holds two thresholds
     // strictly after its first value
     const uint32_t mask = (1u << sh) - 1u;
     g.one_step = 1;
-    for (int k = 1; k + 1 <= g.nbins - 1; ++k)
+    for (int k = 1; k + 1 <= g.nb3 - 1; ++k)
         if ((g.thr[k] >> sh) == (g.thr[k + 1] >> sh) && (g.thr[k] & mask) != 0u) g.one_step = 0;
 }
 
 // r12 slabs: consecutive rows lo0..lo1-1, each held as an extended row of
-// (nbins - lo0) * nbins bins, as many as fit hb_max.
-inline int64_t slab_bins(int lo0, int lo1, int nb) { return (int64_t)(lo1 - lo0) * (nb - lo0) * nb; }
+// (nbins - lo0) * nb3 bins, as many as fit hb_max.
+inline int64_t slab_bins(int lo0, int lo1, int nb, int nb3)
+{
+    return (int64_t)(lo1 - lo0) * (nb - lo0) * nb3;
+}
 
 bool plan_slabs(Geometry& g, int hb_max)
 {
@@ -172,7 +197,7 @@ bool plan_slabs(Geometry& g, int hb_max)
     int lo = 0;
     while (lo < g.nbins) {
         int hi = lo;
-        while (hi < g.nbins && slab_bins(lo, hi + 1, g.nbins) <= hb_max)
+        while (hi < g.nbins && slab_bins(lo, hi + 1, g.nbins, g.nb3) <= hb_max)
             ++hi;
         if (hi == lo) return false;  // a single row does not fit
         g.slab_lo.push_back(hi);
@@ -332,17 +357,19 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 g3_status prepare(const g3_system& s, int hb_max, Prepared& P)
 {
-    g3_status st = check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
+    g3_status st = check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
     if (st) return st;
     if (s.n_frames < 0 || (s.n_frames > 0 && (!s.frames || !s.hist))) return G3_EINVAL;
     Geometry& g = P.g;
     g.N = s.n_atoms;
     g.nbins = s.nbins;
+    g.nb3 = s.nbins_third > 0 ? s.nbins_third : s.nbins;
     g.layout = s.layout;
     for (int d = 0; d < 3; ++d) g.box[d] = s.box[d];
     g.C = (int)std::ceil(s.rmax);
-    g.wide = g.C > 32767 ? 1 : 0;
     plan_bins(g, s.rmax);
+    // 16-bit entries need every accepted third-side component in int16
+    g.wide = g.C3 > 32767 ? 1 : 0;
     plan_cells(g);
     if (!plan_slabs(g, hb_max)) return G3_EINVAL;
     P.in = s;
@@ -378,7 +405,7 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         P.off_nbr_cnt = o;    o = align_up(o + F * N * 4, 256);
         P.off_cursor = o;     o = align_up(o + (size_t)std::max(P.in.n_frames, 1) * kCursorStride * 4, 256);
         P.off_slab_j = o;     o = align_up(o + F * N * (S + 1) * 2, 256);
-        P.off_thr = o;        o = align_up(o + (g.nbins + 1) * 4, 256);
+        P.off_thr = o;        o = align_up(o + (g.nb3 + 1) * 4, 256);
         P.off_tab = o;        o = align_up(o + g.tab_len, 256);
         if (!worst_case) {
             // expected neighbours of a uniform fluid, with headroom; a frame
@@ -397,20 +424,29 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         P.pool_cap = std::min<int64_t>(P.pool_cap, max_cap);
         o = align_up(o + F * (size_t)(P.pool_cap + kPoolPad) * (g.wide ? 16 : 8), 256);
     }
+    // triangle-once needs every side inside the pair cutoff (nb3 == nbins);
+    // other systems use the per-centre enumeration
     for (auto& P : ps) {
-        P.tri_once = tri_once;
+        P.tri_once = tri_once && P.g.nb3 == P.g.nbins;
         P.off_tri = o;
-        if (tri_once) o = align_up(o + g3_hist_len(P.g.nbins, G3_HALF) * sizeof(uint64_t), 256);
+        if (P.tri_once) o = align_up(o + g3_hist_len(P.g.nbins, G3_HALF) * sizeof(uint64_t), 256);
     }
     return o;
 }
 
-// Byte range [begin, end) of the triangle-once buffers of a laid-out group.
+// Byte range [begin, end) of the triangle-once buffers of a laid-out group
+// (they were laid out last, back to back).
 std::pair<size_t, size_t> tri_range(const std::vector<Prepared>& ps)
 {
-    if (ps.empty() || !ps[0].tri_once) return {0, 0};
-    const Prepared& L = ps.back();
-    return {ps[0].off_tri, L.off_tri + g3_hist_len(L.g.nbins, G3_HALF) * sizeof(uint64_t)};
+    size_t b = 0, e = 0;
+    bool any = false;
+    for (const auto& P : ps) {
+        if (!P.tri_once) continue;
+        if (!any) b = P.off_tri;
+        e = P.off_tri + g3_hist_len(P.g.nbins, G3_HALF) * sizeof(uint64_t);
+        any = true;
+    }
+    return {b, e};
 }
 
 Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
@@ -428,6 +464,9 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
     s.ncell = g.ncell;
     s.C = g.C;
     s.R2 = g.R2;
+    s.C3 = g.C3;
+    s.R3 = g.R3;
+    s.nb3 = g.nb3;
     s.nbins = g.nbins;
     s.layout = g.layout;
     s.wide = g.wide;
@@ -473,8 +512,8 @@ void add_segments(const Prepared& P, int sys_index, int frame0, int n_frames, in
         s.item_begin = items;
         s.lo0 = g.slab_lo[q];
         s.lo1 = g.slab_lo[q + 1];
-        s.hb = (int)slab_bins(s.lo0, s.lo1, g.nbins);
-        s.rl = (g.nbins - s.lo0) * g.nbins;
+        s.hb = (int)slab_bins(s.lo0, s.lo1, g.nbins, g.nb3);
+        s.rl = (g.nbins - s.lo0) * g.nb3;
         segs.push_back(s);
         items += n_blocks * n_frames;
     }
@@ -619,7 +658,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
 {
     g3_status st = ensure_common(p);
     if (st) return st;
-    if (s.n_frames == 0 || s.n_atoms == 0) return check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
+    if (s.n_frames == 0 || s.n_atoms == 0) return check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
     const Tun tn = effective(p);
     std::vector<Prepared> ps(1);
     st = prepare(s, tn.hb_max, ps[0]);
@@ -699,7 +738,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
         launch_triplet(a, P.g.wide != 0, P.g.one_step != 0, n_wg, p->stream);
         timing_end(p, e0);
         launch_reduce(a, tn.hb_max, S, p->stream);
-        if (tn.tri_once) launch_expand(dsys, 1, P.g.nbins, p->stream);
+        if (P.tri_once) launch_expand(dsys, 1, P.g.nbins, p->stream);
     }
     G3_TRY_HIP(hipGetLastError());
     return G3_OK;
@@ -720,10 +759,10 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         std::vector<Prepared> ps;
         for (int i = 0; i < n_sys; ++i) {
             const g3_system& s = systems[i];
-            if ((std::ceil(s.rmax) > 32767) != wide) continue;
             if (s.n_frames == 0 || s.n_atoms == 0) continue;
             Prepared P;
             if ((st = prepare(s, tn.hb_max, P))) return st;
+            if ((P.g.wide != 0) != wide) continue;
             ps.push_back(std::move(P));
         }
         if (ps.empty()) continue;
@@ -817,7 +856,9 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         if (tri.second > tri.first)
             zero.push_back({(uint32_t*)((char*)p->arena + tri.first), (tri.second - tri.first) / 4});
         int max_nb = 0;
-        for (auto& P : ps) max_nb = std::max(max_nb, P.g.nbins);
+        for (auto& P : ps)
+            if (P.tri_once) max_nb = std::max(max_nb, P.g.nbins);
+        const bool any_tri = max_nb > 0;
         const int n_sys = (int)ps.size();
         for (auto& z : zero) {
             put(&z.first, sizeof(z.first));
@@ -835,7 +876,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_nbr_build(dsys, djobs, nj, max_cells, kStageCap, wide, one_step, sm);
             launch_triplet(a, wide, one_step, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
-            if (tn.tri_once) launch_expand(dsys, n_sys, max_nb, sm);
+            if (any_tri) launch_expand(dsys, n_sys, max_nb, sm);
         };
         if (p->timing) {
             // timed runs launch directly so that events bracket the kernel
@@ -850,7 +891,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_triplet(a, wide, one_step, n_wg, p->stream);
             timing_end(p, e0);
             launch_reduce(a, max_hb, ns, p->stream);
-            if (tn.tri_once) launch_expand(dsys, n_sys, max_nb, p->stream);
+            if (any_tri) launch_expand(dsys, n_sys, max_nb, p->stream);
             G3_TRY_HIP(hipGetLastError());
             continue;
         }
@@ -971,23 +1012,43 @@ void g3_plan_destroy(g3_plan p)
 }
 
 // pair_hist of a overlapping the histogram of b (atomics beside plain stores)
+static size_t sys_hist_len(const g3_system& s)
+{
+    return g3_hist_len3(s.nbins, s.nbins_third > 0 ? s.nbins_third : s.nbins, s.layout);
+}
+
 static bool overlaps(const g3_system& a, const g3_system& b)
 {
     if (!a.pair_hist) return false;
     const uintptr_t p0 = (uintptr_t)a.pair_hist, p1 = p0 + sizeof(uint64_t) * (size_t)a.nbins;
-    const uintptr_t h0 = (uintptr_t)b.hist,
-                    h1 = h0 + sizeof(uint64_t) * g3_hist_len(b.nbins, b.layout);
+    const uintptr_t h0 = (uintptr_t)b.hist, h1 = h0 + sizeof(uint64_t) * sys_hist_len(b);
     return p0 < h1 && h0 < p1;
+}
+
+// histograms of two systems sharing bins (each bin of a histogram has one
+// plain writer in the flush)
+static bool hists_overlap(const g3_system& a, const g3_system& b)
+{
+    const uintptr_t a0 = (uintptr_t)a.hist, a1 = a0 + sizeof(uint64_t) * sys_hist_len(a);
+    const uintptr_t b0 = (uintptr_t)b.hist, b1 = b0 + sizeof(uint64_t) * sys_hist_len(b);
+    return a0 < b1 && b0 < a1;
+}
+
+static g3_status accumulate_one(g3_plan p, g3_system s)
+{
+    g3_status st = check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
+    if (st) return st;
+    if (s.n_frames < 0 || (s.n_frames > 0 && s.n_atoms > 0 && (!s.frames || !s.hist))) return G3_EINVAL;
+    if (s.n_frames == 0 || s.n_atoms < (s.pair_hist ? 2 : 3)) return G3_OK;
+    if (s.pair_hist && overlaps(s, s)) return G3_EINVAL;
+    return run_plain(p, s, false);
 }
 
 g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames, int32_t n_atoms,
                         const int32_t box[3], double rmax, int32_t nbins, int32_t layout,
                         uint64_t* hist, uint64_t* pair_hist)
 {
-    if (!p) return G3_EINVAL;
-    g3_status st = check(n_atoms, box, rmax, nbins, layout);
-    if (st) return st;
-    if (n_frames < 0 || (n_frames > 0 && n_atoms > 0 && (!frames || !hist))) return G3_EINVAL;
+    if (!p || !box) return G3_EINVAL;
     g3_system s;
     s.frames = frames;
     s.n_frames = n_frames;
@@ -998,9 +1059,14 @@ g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames, int3
     s.layout = layout;
     s.hist = hist;
     s.pair_hist = pair_hist;
-    if (n_frames == 0 || n_atoms < (pair_hist ? 2 : 3)) return G3_OK;
-    if (pair_hist && overlaps(s, s)) return G3_EINVAL;
-    return run_plain(p, s, false);
+    s.nbins_third = 0;
+    return accumulate_one(p, s);
+}
+
+g3_status g3_accumulate_system(g3_plan p, const g3_system* s)
+{
+    if (!p || !s) return G3_EINVAL;
+    return accumulate_one(p, *s);
 }
 
 g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_systems)
@@ -1009,13 +1075,13 @@ g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_sys
     std::vector<g3_system> live;
     for (int i = 0; i < n_systems; ++i) {
         const g3_system& s = systems[i];
-        g3_status st = check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
+        g3_status st = check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
         if (st) return st;
         if (s.n_frames < 0) return G3_EINVAL;
         if (s.n_frames == 0 || s.n_atoms < (s.pair_hist ? 2 : 3)) continue;
         if (!s.frames || !s.hist) return G3_EINVAL;
         for (const auto& o : live)
-            if (o.hist == s.hist || overlaps(o, s) || overlaps(s, o)) return G3_EINVAL;
+            if (hists_overlap(o, s) || overlaps(o, s) || overlaps(s, o)) return G3_EINVAL;
         if (overlaps(s, s)) return G3_EINVAL;
         live.push_back(s);
     }
@@ -1040,13 +1106,19 @@ g3_status g3_sync(g3_plan p)
     return st;
 }
 
-size_t g3_hist_len(int32_t nbins, int32_t layout)
+size_t g3_hist_len3(int32_t nbins, int32_t nbins_third, int32_t layout)
 {
     if (nbins < 1 || nbins > G3_MAX_NBINS) return 0;
-    const size_t n = (size_t)nbins;
-    if (layout == G3_FULL) return n * n * n;
-    if (layout == G3_HALF) return n * (n + 1) / 2 * n;
+    if (nbins_third < nbins || nbins_third > 2 * nbins) return 0;
+    const size_t n = (size_t)nbins, n3 = (size_t)nbins_third;
+    if (layout == G3_FULL) return n * n * n3;
+    if (layout == G3_HALF) return n * (n + 1) / 2 * n3;
     return 0;
+}
+
+size_t g3_hist_len(int32_t nbins, int32_t layout)
+{
+    return g3_hist_len3(nbins, nbins, layout);
 }
 
 g3_status g3_check_args(int32_t n_atoms, const int32_t box[3], double rmax, int32_t nbins,
@@ -1079,8 +1151,16 @@ g3_status g3_ideal_volume(int32_t nbins, double rmax, double* W)
 g3_status g3_normalize(const uint64_t* hist, int32_t layout, int32_t nbins, double rmax,
                        int64_t n_frames, int32_t n_atoms, const int32_t box[3], double* g3_out)
 {
+    return g3_normalize3(hist, layout, nbins, nbins, rmax, n_frames, n_atoms, box, g3_out);
+}
+
+g3_status g3_normalize3(const uint64_t* hist, int32_t layout, int32_t nbins, int32_t nbins_third,
+                        double rmax, int64_t n_frames, int32_t n_atoms, const int32_t box[3],
+                        double* g3_out)
+{
     if (!hist || !g3_out || !box) return G3_EINVAL;
     if (nbins < 1 || nbins > G3_MAX_NBINS || (layout != G3_HALF && layout != G3_FULL)) return G3_EINVAL;
+    if (nbins_third < nbins || nbins_third > 2 * nbins) return G3_EINVAL;
     if (!(rmax > 0) || n_frames < 0 || n_atoms < 0) return G3_EINVAL;
     for (int d = 0; d < 3; ++d)
         if (box[d] <= 0) return G3_EINVAL;
@@ -1091,7 +1171,7 @@ g3_status g3_normalize(const uint64_t* hist, int32_t layout, int32_t nbins, doub
     size_t x = 0;
     for (int a = 0; a < nbins; ++a)
         for (int b = (layout == G3_HALF ? a : 0); b < nbins; ++b)
-            for (int c = 0; c < nbins; ++c, ++x) {
+            for (int c = 0; c < nbins_third; ++c, ++x) {
                 double E = pref * W_bin(a, b, c, dr);
                 if (layout == G3_HALF && a == b) E *= 0.5;
                 g3_out[x] = E > 0 ? (double)hist[x] / E : 0.0;
@@ -1218,8 +1298,8 @@ static std::string tune_key(const g3_system* sys, int n, int per_centre)
         const double V = (double)s.box[0] * s.box[1] * s.box[2];
         const double nexp = (double)s.n_atoms / V * 4.18879020478639 * s.rmax * s.rmax * s.rmax;
         char buf[96];
-        std::snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%d;", s.rmax > 32767 ? 1 : 0, s.nbins, s.layout,
-                      (int)std::lround(std::log2(std::max(1, s.n_atoms))),
+        std::snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%d,%d;", s.rmax > 32767 ? 1 : 0, s.nbins,
+                      s.nbins_third, s.layout, (int)std::lround(std::log2(std::max(1, s.n_atoms))),
                       (int)std::lround(2 * std::log2(std::max(1.0, nexp))), s.n_frames);
         k += buf;
     }
@@ -1231,7 +1311,7 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
     if (!p || n_systems <= 0 || !systems) return G3_EINVAL;
     for (int i = 0; i < n_systems; ++i) {
         const g3_system& s = systems[i];
-        g3_status st = check(s.n_atoms, s.box, s.rmax, s.nbins, s.layout);
+        g3_status st = check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
         if (st) return st;
         if (s.n_frames < 0 || (s.n_frames > 0 && !s.frames)) return G3_EINVAL;
     }
@@ -1249,7 +1329,7 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
     std::vector<size_t> len(n_systems);
     size_t total = 0;
     for (int i = 0; i < n_systems; ++i) {
-        len[i] = g3_hist_len(sys[i].nbins, sys[i].layout);
+        len[i] = sys_hist_len(sys[i]);
         total += len[i];
     }
     uint64_t* scratch = nullptr;

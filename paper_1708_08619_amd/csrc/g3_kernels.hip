@@ -200,13 +200,13 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
 {
     using E = typename std::conditional<WIDE, int4, uint2>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                    // [256]
-    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + 256);               // [8192]
+    uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                    // [kThrMax]
+    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + kThrMax);           // [8192]
     uint8_t* s_slab = s_tab + 8192;                                          // [256] bin -> slab
     constexpr int kWaveBuf = wave_buf<WIDE>();
     E* s_buf = reinterpret_cast<E*>(s_slab + 256);                           // [waves][kWaveBuf]
-    uint32_t* s_scnt = reinterpret_cast<uint32_t*>(s_buf + kBuildWaves * kWaveBuf);  // [waves][32]
-    uint32_t* s_g2 = s_scnt + kBuildWaves * 32;                              // [256] pair bins
+    uint32_t* s_scnt = reinterpret_cast<uint32_t*>(s_buf + kBuildWaves * kWaveBuf);  // [waves][64]
+    uint32_t* s_g2 = s_scnt + kBuildWaves * 64;                              // [256] pair bins
     uint8_t* s_sb = reinterpret_cast<uint8_t*>(s_g2 + 256);                  // [waves][kWaveBuf] slab
     int32_t* s_x = reinterpret_cast<int32_t*>(s_sb + kBuildWaves * kWaveBufMax);
     int32_t* s_y = s_x + stg_cap;
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     const int sh = S.sh, nb = S.nbins, n_slabs = S.n_slabs, list_cap = S.list_cap;
     const int tbits = S.tab_bits;
     const int64_t pool_cap = S.pool_cap;
-    uint32_t* scnt = s_scnt + wave * 32;
+    uint32_t* scnt = s_scnt + wave * 64;
     E* buf = s_buf + wave * kWaveBuf;
     uint8_t* sb = s_sb + wave * kWaveBuf;     // slab of each buffered entry
     uint32_t* flags = S.flags + f;
@@ -243,7 +243,8 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     E* pool = reinterpret_cast<E*>(S.pool) + pbase;
 
     // bin tables and the bin -> slab map, once per workgroup
-    for (int x = tid; x <= nb; x += kBuildThreads) s_thr[x] = S.thr[x];
+    const int nb3 = S.nb3;
+    for (int x = tid; x <= nb3; x += kBuildThreads) s_thr[x] = S.thr[x];
     {
         const int n16 = (S.tab_len + 15) / 16;
         const uint4* src = reinterpret_cast<const uint4*>(S.tab);
@@ -387,7 +388,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     b = s_tab[sc >> sh];
                     while (sc >= s_thr[b + 1]) ++b;
                 }
-                const int bn = __mul24(b, nb);
+                const int bn = __mul24(b, nb3);
                 if constexpr (WIDE) {
                     e = make_int4(dx, dy, dz, bn);
                 } else {
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 }
                 return ok;
             };
-            if (lane < 32) scnt[lane] = 0u;
+            scnt[lane] = 0u;
             wave_sync();
             // the one evaluation pass: count per slab, compact into the buffer
             uint32_t n = 0;
@@ -447,7 +448,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 const uint32_t v = lane < n_slabs ? scnt[lane] : 0u;
                 uint32_t x = v;
 #pragma unroll
-                for (int d = 1; d < 32; d <<= 1) {
+                for (int d = 1; d < 64; d <<= 1) {
                     const uint32_t y = __shfl_up(x, d, 64);
                     if (lane >= d) x += y;
                 }
@@ -610,8 +611,8 @@ struct GEnt<true> {
 // LDS of the triplet kernel at fixed byte addresses.  The kernel declares no
 // static LDS, so its dynamic LDS starts at address 0 (the host checks this
 // before the first launch) and table bases fold into instruction offsets.
-constexpr uint32_t kTlThr = 0;                        // uint32 thr[256]
-constexpr uint32_t kTlTab = 1024;                     // uint8 tab[kTabBytes]
+constexpr uint32_t kTlThr = 0;                        // uint32 thr[kThrMax]
+constexpr uint32_t kTlTab = 4 * kThrMax;              // uint8 tab[kTabBytes]
 constexpr uint32_t kTlTrash = kTlTab + kTabBytes;     // uint32 [64]: rejected candidates land here
 constexpr uint32_t kTlMisc = kTlTrash + 256;          // uint32 scan[17], item, slot, chunk counter
 constexpr uint32_t kTlItem = kTlMisc + 4 * 17;
@@ -706,7 +707,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             // Fallback: add the non-zero bins directly; a wave skips 64 empty
             // bins with one ballot.
             const Sys& S = A.sys[G.sys];
-            const int nb = S.nbins, RL = G.rl;
+            const int nb = S.nbins, nb3 = S.nb3, RL = G.rl;
             // triangle-once counts go to the half-layout triangle buffer
             uint64_t* const out = S.tri ? S.tri : S.hist;
             const int layout = S.tri ? 0 : S.layout;
@@ -716,17 +717,17 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 if (__ballot(v != 0u) == 0ull) continue;
                 if (v == 0u) continue;
                 const int a = G.lo0 + x / RL, rem = x - (x / RL) * RL;
-                const int b = G.lo0 + rem / nb, c = rem - (rem / nb) * nb;
+                const int b = G.lo0 + rem / nb3, c = rem - (rem / nb3) * nb3;
                 const int lo = min(a, b), hi = max(a, b);
                 if (layout == 0) {
-                    const size_t h = ((size_t)lo * nb - (size_t)lo * (lo - 1) / 2 + (hi - lo)) * nb + c;
+                    const size_t h = ((size_t)lo * nb - (size_t)lo * (lo - 1) / 2 + (hi - lo)) * nb3 + c;
                     atomicAdd((unsigned long long*)&out[h], (unsigned long long)v);
                 } else if (lo == hi) {
-                    atomicAdd((unsigned long long*)&out[((size_t)lo * nb + lo) * nb + c], 2ull * v);
+                    atomicAdd((unsigned long long*)&out[((size_t)lo * nb + lo) * nb3 + c], 2ull * v);
                 } else {
-                    atomicAdd((unsigned long long*)&out[((size_t)lo * nb + hi) * nb + c],
+                    atomicAdd((unsigned long long*)&out[((size_t)lo * nb + hi) * nb3 + c],
                               (unsigned long long)v);
-                    atomicAdd((unsigned long long*)&out[((size_t)hi * nb + lo) * nb + c],
+                    atomicAdd((unsigned long long*)&out[((size_t)hi * nb + lo) * nb3 + c],
                               (unsigned long long)v);
                 }
             }
@@ -751,7 +752,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         if (seg != cur_seg) {
             if (cur_seg >= 0) flush(cur_seg);
             if (G.sys != cur_sys) {
-                for (int x = tid; x <= S.nbins; x += kTripletThreads) st32(kTlThr + 4u * x, S.thr[x]);
+                for (int x = tid; x <= S.nb3; x += kTripletThreads) st32(kTlThr + 4u * x, S.thr[x]);
                 for (int x = tid; x < S.tab_len; x += kTripletThreads) st8(kTlTab + x, S.tab[x]);
                 cur_sys = G.sys;
             }
@@ -842,10 +843,12 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         }
         __syncthreads();
 
-        const uint32_t R2 = S.R2, R2m1 = S.R2 - 1u;
+        // the third side is accepted below R3 (R2 unless the third axis is
+        // longer); C3 - 1 bounds its components
+        const uint32_t R3 = S.R3, R3m1 = S.R3 - 1u;
         const uint32_t sh = (uint32_t)S.sh, tbits = (uint32_t)S.tab_bits;
-        const int cm1 = S.C - 1;
-        const int RL = G.rl;
+        const int cm1 = S.C3 - 1;
+        const int RL = G.rl, nb3 = S.nb3;
         const uint32_t trash = kTlTrash + 4u * (uint32_t)lane;
         // waves take chunks of 64 units from a counter, longest rows first
         for (;;) {
@@ -885,10 +888,11 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             const uint32_t eoff = ld32(kSrc + 4u * (uint32_t)cl) * ES;   // byte offset of entry J_q
             const int mm = (int)ld32(kM + 4u * (uint32_t)cl);
             const E vj = pool.load(eoff + (uint32_t)j * ES);
-            // slab index of (b_j, b_k, c) is (b_j - lo0) RL + (b_k - lo0) nb + c;
-            // entries carry b nb, and (b_j - lo0) RL = (b_j nb)(nb - lo0) - lo0 RL
+            // slab index of (b_j, b_k, c) is (b_j - lo0) RL + (b_k - lo0) nb3 + c
+            // with RL = (nb - lo0) nb3; entries carry b nb3, and
+            // (b_j - lo0) RL = (b_j nb3)(nb - lo0) - lo0 RL
             const int colj = Ent<WIDE>::col(vj);
-            const uint32_t rowbase = kTlHist + 4u * (uint32_t)(colj * (nb - lo0) - lo0 * RL - lo0 * nb);
+            const uint32_t rowbase = kTlHist + 4u * (uint32_t)(colj * (nb - lo0) - lo0 * RL - lo0 * nb3);
             uint32_t jx, jy = 0, jz;
             if constexpr (WIDE) {
                 jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
@@ -909,7 +913,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     c = ld8(kTlTab + __builtin_amdgcn_ubfe(s, sh, tbits));
                     c += (s >= ld32(kTlThr + 4u + 4u * c)) ? 1u : 0u;
                 } else {
-                    const uint32_t sc = min(s, R2m1);
+                    const uint32_t sc = min(s, R3m1);
                     c = ld8(kTlTab + (sc >> sh));
                     while (sc >= ld32(kTlThr + 4u + 4u * c)) ++c;
                 }
@@ -927,13 +931,13 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 // keep the address arithmetic unconditional (a select, not a branch)
                 asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]));
 #pragma unroll
-                for (int u = 0; u < 4; ++u) inc32(s[u] < R2 ? a[u] : trash);
+                for (int u = 0; u < 4; ++u) inc32(s[u] < R3 ? a[u] : trash);
             };
             auto eval1 = [&](const E& v) {
                 const uint32_t s = d2(v);
                 uint32_t a = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v) + bin(s));
                 asm volatile("" : "+v"(a));
-                inc32(s < R2 ? a : trash);
+                inc32(s < R3 ? a : trash);
             };
             // this unit's share [u0, u1) of the row's sequence: u < H is the
             // circular triangle (k = j + u + 1 mod rr), u >= H the rectangle
@@ -998,12 +1002,12 @@ __global__ void __launch_bounds__(256) k_reduce(TripletArgs A)
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= G.hb) return;
     const Sys& S = A.sys[G.sys];
-    const int nb = S.nbins, RL = G.rl;
+    const int nb = S.nbins, nb3 = S.nb3, RL = G.rl;
     const int a = G.lo0 + x / RL, rem = x - (x / RL) * RL;
-    const int b = G.lo0 + rem / nb, c = rem - (rem / nb) * nb;
+    const int b = G.lo0 + rem / nb3, c = rem - (rem / nb3) * nb3;
     if (b < a) return;
     const bool mirror = b != a && b < G.lo1;
-    const int xm = (b - G.lo0) * RL + (a - G.lo0) * nb + c;
+    const int xm = (b - G.lo0) * RL + (a - G.lo0) * nb3 + c;
     const uint32_t used = min(A.ctl->slots_used, (uint32_t)A.max_slots);
     uint64_t sum = 0;
     for (uint32_t s = 0; s < used; ++s)
@@ -1014,14 +1018,14 @@ __global__ void __launch_bounds__(256) k_reduce(TripletArgs A)
         }
     if (sum == 0) return;
     if (S.tri) {
-        S.tri[((size_t)a * nb - (size_t)a * (a - 1) / 2 + (b - a)) * nb + c] += sum;
+        S.tri[((size_t)a * nb - (size_t)a * (a - 1) / 2 + (b - a)) * nb3 + c] += sum;
     } else if (S.layout == 0) {
-        S.hist[((size_t)a * nb - (size_t)a * (a - 1) / 2 + (b - a)) * nb + c] += sum;
+        S.hist[((size_t)a * nb - (size_t)a * (a - 1) / 2 + (b - a)) * nb3 + c] += sum;
     } else if (a == b) {
-        S.hist[((size_t)a * nb + a) * nb + c] += 2 * sum;
+        S.hist[((size_t)a * nb + a) * nb3 + c] += 2 * sum;
     } else {
-        S.hist[((size_t)a * nb + b) * nb + c] += sum;
-        S.hist[((size_t)b * nb + a) * nb + c] += sum;
+        S.hist[((size_t)a * nb + b) * nb3 + c] += sum;
+        S.hist[((size_t)b * nb + a) * nb3 + c] += sum;
     }
 }
 
@@ -1090,7 +1094,7 @@ void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n,
 
 size_t nbr_build_lds_bytes(int stg_cap)
 {
-    return 256 * 4 + 8192 + 256 + (size_t)kBuildWaves * kBufBytes + kBuildWaves * 32 * 4 +
+    return kThrMax * 4 + 8192 + 256 + (size_t)kBuildWaves * kBufBytes + kBuildWaves * 64 * 4 +
            256 * 4 + (size_t)kBuildWaves * kWaveBufMax + (size_t)3 * stg_cap * 4;
 }
 

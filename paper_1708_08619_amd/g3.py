@@ -34,7 +34,7 @@ class System(C.Structure):
     _fields_ = [("frames", C.c_void_p), ("n_frames", C.c_int32), ("n_atoms", C.c_int32),
                 ("box", C.c_int32 * 3), ("rmax", C.c_double), ("nbins", C.c_int32),
                 ("layout", C.c_int32), ("hist", C.c_void_p),
-                ("pair_hist", C.c_void_p)]
+                ("pair_hist", C.c_void_p), ("nbins_third", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -72,6 +72,9 @@ def lib():
         "g3_plan_destroy": ([P], None),
         "g3_accumulate": ([P, P, I32, I32, P, D, I32, I32, P, P], I32),
         "g3_accumulate_batch": ([P, P, I32], I32),
+        "g3_accumulate_system": ([P, P], I32),
+        "g3_hist_len3": ([I32, I32, I32], C.c_size_t),
+        "g3_normalize3": ([P, I32, I32, I32, D, I64, I32, P, P], I32),
         "g3_sync": ([P], I32),
         "g3_query": ([P], I32),
         "g3_hist_len": ([I32, I32], C.c_size_t),
@@ -122,8 +125,9 @@ def _np_ptr(a: np.ndarray):
 
 
 # ------------------------------------------------------------------ host helpers
-def hist_len(nbins: int, layout: int) -> int:
-    return int(lib().g3_hist_len(int(nbins), int(layout)))
+def hist_len(nbins: int, layout: int, nbins_third: int | None = None) -> int:
+    """Bins of the histogram; nbins_third third-side bins (default nbins)."""
+    return int(lib().g3_hist_len3(int(nbins), int(nbins_third or nbins), int(layout)))
 
 
 def check_args(n_atoms: int, box, rmax: float, nbins: int, layout: int) -> int:
@@ -143,13 +147,15 @@ def ideal_volume(nbins: int, rmax: float) -> np.ndarray:
 
 
 def normalize(hist: np.ndarray, layout: int, nbins: int, rmax: float, n_frames: int,
-              n_atoms: int, box) -> np.ndarray:
+              n_atoms: int, box, nbins_third: int | None = None) -> np.ndarray:
+    nc = int(nbins_third or nbins)
     h = np.ascontiguousarray(hist, dtype=np.uint64).reshape(-1)
-    if h.shape[0] != hist_len(nbins, layout):
+    if h.shape[0] != hist_len(nbins, layout, nc):
         raise ValueError("histogram length does not match nbins/layout")
     out = np.zeros(h.shape[0], dtype=np.float64)
-    _check(lib().g3_normalize(_np_ptr(h), int(layout), int(nbins), float(rmax), int(n_frames),
-                              int(n_atoms), _box(box), _np_ptr(out)), "g3_normalize")
+    _check(lib().g3_normalize3(_np_ptr(h), int(layout), int(nbins), nc, float(rmax),
+                               int(n_frames), int(n_atoms), _box(box), _np_ptr(out)),
+           "g3_normalize3")
     return out
 
 
@@ -239,16 +245,10 @@ class Plan:
 
     # -- g3_accumulate: the plain per-frame form
     def accumulate(self, frames, box, rmax: float, nbins: int, layout: int, hist,
-                   pair_hist=None):
-        F, three, N = (int(x) for x in frames.shape)
-        if three != 3:
-            raise ValueError("frames must be [n_frames, 3, n_atoms]")
-        if hist.numel() != hist_len(nbins, layout):
-            raise ValueError("hist has the wrong length")
-        _check(lib().g3_accumulate(self._h, _dev_ptr(frames, "int32", "frames"), F, N, _box(box),
-                                   float(rmax), int(nbins), int(layout),
-                                   _dev_ptr(hist, "uint64", "hist"),
-                                   _pair_ptr(pair_hist, nbins)), "g3_accumulate")
+                   pair_hist=None, nbins_third: int | None = None):
+        arr = self._systems([dict(frames=frames, box=box, rmax=rmax, nbins=nbins, layout=layout,
+                                  hist=hist, pair_hist=pair_hist, nbins_third=nbins_third)])
+        _check(lib().g3_accumulate_system(self._h, arr), "g3_accumulate_system")
 
     @staticmethod
     def _systems(systems: Sequence[dict]):
@@ -258,7 +258,8 @@ class Plan:
             F, three, N = (int(x) for x in fr.shape)
             if three != 3:
                 raise ValueError("frames must be [n_frames, 3, n_atoms]")
-            if h.numel() != hist_len(s["nbins"], s["layout"]):
+            nc = int(s.get("nbins_third") or 0)
+            if h.numel() != hist_len(s["nbins"], s["layout"], nc or None):
                 raise ValueError("hist has the wrong length")
             arr[i].frames = _dev_ptr(fr, "int32", "frames")
             arr[i].n_frames = F
@@ -269,6 +270,7 @@ class Plan:
             arr[i].layout = int(s["layout"])
             arr[i].hist = _dev_ptr(h, "uint64", "hist")
             arr[i].pair_hist = _pair_ptr(s.get("pair_hist"), s["nbins"])
+            arr[i].nbins_third = nc
         return arr
 
     # -- g3_accumulate_batch: one graph launch for many systems
@@ -333,6 +335,6 @@ def new_pair_hist(nbins: int, device="cuda"):
     return torch.zeros(int(nbins), dtype=torch.uint64, device=device)
 
 
-def new_hist(nbins: int, layout: int, device="cuda"):
+def new_hist(nbins: int, layout: int, device="cuda", nbins_third: int | None = None):
     import torch
-    return torch.zeros(hist_len(nbins, layout), dtype=torch.uint64, device=device)
+    return torch.zeros(hist_len(nbins, layout, nbins_third), dtype=torch.uint64, device=device)

@@ -135,7 +135,7 @@ def test_capacity_error_still_counts_pairs(g3mod, plan, torch_dev, oracle_mod):
     rng = np.random.default_rng(5)
     box = [200000] * 3
     c = np.array(box) // 2
-    fr = (c[:, None] + rng.integers(-500, 500, size=(3, 1300)))[None].astype(np.int32)
+    fr = (c[:, None] + rng.integers(-500, 500, size=(3, 4200)))[None].astype(np.int32)
     h, p = g3mod.new_hist(10, 0, torch_dev), g3mod.new_pair_hist(10, torch_dev)
     plan.accumulate(_dev(fr, torch_dev), box, 5000.0, 10, 0, h, pair_hist=p)
     assert plan.sync_status() == g3mod.ENOMEM

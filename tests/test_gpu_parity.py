@@ -275,7 +275,7 @@ def test_pool_overflow_is_recomputed(g3mod, plan, torch_dev, oracle_mod):
 def test_too_many_neighbours_reports_enomem(g3mod, plan, torch_dev):
     rng = np.random.default_rng(5)
     box = [200000] * 3
-    N = 1300
+    N = 4200                      # more neighbours than the per-centre capacity (4096)
     c = np.array(box) // 2
     fr = (c[:, None] + rng.integers(-500, 500, size=(3, N)))[None].astype(np.int32)
     h = g3mod.new_hist(10, 0, torch_dev)
