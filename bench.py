@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests in the served (continuous batching) run; 0 skips it")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-paper-shapes", action="store_true",
+                    help="skip the replay of the paper's g3 runs (Table 2 shapes)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
@@ -175,6 +177,11 @@ def main():
         per_centre = {"value": binned / pc_s / 1e9, "ms_per_step": pc_s * 1e3,
                       "triplet_kernel_ms": pc_ms, "candidates_per_launch": pc_cand}
 
+    paper_shapes = None
+    if not args.no_paper_shapes:
+        mark("paper-shape replay: water N = 6720, 13440, 26880, 10 frames, rmax = L/4")
+        paper_shapes = paper_shape_replay(torch, dev)
+
     served = None
     if args.serve_requests > 0:
         mark(f"served: {args.serve_requests} requests at {args.serve_rate}/s, two budgets")
@@ -203,6 +210,7 @@ def main():
         "plain": plain,
         "per_centre_enumeration": per_centre,
         "served": served,
+        "paper_shapes": paper_shapes,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -225,6 +233,48 @@ def cpu_baseline(w, n_frames: int):
             "kind": "oracle", "seconds": dt,
             "sample": f"frames 0..{n_frames - 1} of {w.n_frames}, all {w.n_atoms} centres "
                       f"({binned} triplets binned)"}
+
+
+# The paper's Table 2 (g3, 10 frames, times in seconds including file reading):
+# serial CPU, GTX 780 and K40 runs of its per-frame CUDA code.
+PAPER_TABLE2_S = {6720: (596, 13, 16), 13440: (2089, 104, 132), 26880: (11515, 860, 1124)}
+
+
+def paper_shape_replay(torch, dev):
+    """The paper's g3 runs at their shapes: water-density systems of 6720,
+    13440 and 26880 sites, 10 frames, two sides below L/4 and the third below
+    L/2 (80 x 80 x 160 bins, full layout), batched form, frames resident in
+    HBM.  The paper's times are quoted for context only: other hardware, its
+    own trajectories, and its times include reading the files."""
+    from paper_1708_08619_amd import g3, synth
+    out = []
+    for N in synth.PAPER_SHAPES:
+        w = synth.water_replay(N, n_frames=10)
+        nc = w.meta["nbins_third"]
+        frames = torch.from_numpy(w.frames).to(dev)
+        hist = g3.new_hist(w.nbins, w.layout, dev, nbins_third=nc)
+        system = dict(frames=frames, box=w.box, rmax=w.rmax, nbins=w.nbins, layout=w.layout,
+                      hist=hist, nbins_third=nc)
+        with g3.Plan() as plan:
+            plan.accumulate_batch([system])
+            plan.sync()
+            binned = int(hist.sum().item()) // 2      # unordered pairs, as the headline counts
+            reps = 3
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.accumulate_batch([system])
+            plan.sync()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+        cpu_s, gtx_s, k40_s = PAPER_TABLE2_S[N]
+        out.append({"n_atoms": N, "frames": 10, "box_units": w.box[0], "unit": "2^-13 nm",
+                    "bins": [w.nbins, w.nbins, nc], "seconds": dt,
+                    "triplets_binned": binned, "G_triplets_binned_per_s": binned / dt / 1e9,
+                    "paper_cpu_s": cpu_s, "paper_gtx780_s": gtx_s, "paper_k40_s": k40_s,
+                    "ratio_vs_paper_gtx780": gtx_s / dt})
+        del frames, hist
+    return out
 
 
 def serve_bench(n_requests: int, rate_hz: float):

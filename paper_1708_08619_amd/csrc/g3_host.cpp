@@ -1364,8 +1364,12 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
                 t.lds_hist_bins = (full.hb_max * fracs[fi] / 4) & ~63;
                 p->tun = t;
                 hipMemsetAsync(scratch, 0, total * sizeof(uint64_t), p->stream);
-                // one untimed run (also the correctness check), then two timed
-                if ((st = run_batch(p, sys.data(), n_systems))) break;
+                // one untimed run (also the correctness check), then two timed;
+                // a tuning whose slabs cannot hold a system is skipped (the
+                // arguments were validated above, and nothing was queued)
+                st = run_batch(p, sys.data(), n_systems);
+                if (st == G3_EINVAL) { st = G3_OK; continue; }
+                if (st) break;
                 if ((st = drain(p))) break;
                 if (hipMemcpy(got.data(), scratch, total * sizeof(uint64_t), hipMemcpyDeviceToHost)) {
                     st = G3_EDEVICE;

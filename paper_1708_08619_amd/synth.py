@@ -172,6 +172,30 @@ def water_like(n_frames: int = 100) -> Workload:
                     {"rho": rho, "unit": "2^-16 nm"})
 
 
+# Coarser unit for the paper-shape replays, so that L/2 stays within the
+# 46340-unit limit of the third side for N up to 26880 at water density.
+REPLAY_UNIT_PER_NM = 8192
+PAPER_SHAPES = (6720, 13440, 26880)   # system sizes of the paper's Table 2 runs
+
+
+def water_replay(n_atoms: int, n_frames: int = 10, nbins: int = 80) -> Workload:
+    """Water-density oxygen-like sites (33.4 nm^-3) for a paper-shape replay
+    of the g3 runs (Table 2: N = 6720, 13440, 26880, 10 frames): jittered
+    diamond lattice (sd 0.03 nm, redrawn per frame, a seeded subset of the
+    smallest 8 n^3 >= N sites), unit 2^-13 nm, the paper's geometry -- two
+    sides below L/4, the third below L/2: rmax = L/4 with nbins bins and
+    2 nbins third-side bins; full layout (the paper keeps the whole 3-D
+    histogram).  The third-side bin count is meta["nbins_third"]."""
+    rho = 33.4
+    n = smallest_cells(n_atoms, 8)
+    L = cubic_lattice_box(n_atoms, rho, REPLAY_UNIT_PER_NM, n, 4 * n)
+    box = [L, L, L]
+    frames = lattice_frames(diamond_sites(n, L // n), n_atoms, box, 0.03 * REPLAY_UNIT_PER_NM,
+                            n_frames, [SEED_BASE + 6, n_atoms])
+    return Workload(f"water_replay{n_atoms}", frames, box, L / 4.0, nbins, FULL,
+                    {"rho": rho, "unit": "2^-13 nm", "nbins_third": 2 * nbins})
+
+
 def uneven_batch(n_systems: int = 8, frames_per_system: int = 8) -> list[Workload]:
     """Batched case: systems with N log-uniform in [512, 32768], densities
     U(0.7, 0.9) sigma^-3, jittered FCC (sd 0.1 sigma), rmax 2.5 sigma, 50 bins."""

@@ -113,3 +113,19 @@ def test_third_axis_arguments(g3mod, plan, torch_dev):
         plan.accumulate(_dev(np.zeros((1, 3, 8), np.int32), torch_dev), big, 30000.0, 10, 0, h,
                         nbins_third=20)
     plan.sync()
+
+
+def test_paper_shape_replay_frame(g3mod, plan, torch_dev, oracle_mod):
+    """One frame of the N = 6720 water-density replay (two sides below L/4,
+    the third below L/2, 80 x 80 x 160 bins, full layout), batched, equals the
+    oracle bin for bin."""
+    w = synth.water_replay(6720, n_frames=1)
+    nc = w.meta["nbins_third"]
+    want = oracle_mod.hist(w.frames, w.box, w.rmax, w.nbins, w.layout, nbins_third=nc)
+    h = g3mod.new_hist(w.nbins, w.layout, torch_dev, nbins_third=nc)
+    plan.accumulate_batch([dict(frames=_dev(w.frames, torch_dev), box=w.box, rmax=w.rmax,
+                                nbins=w.nbins, layout=w.layout, hist=h, nbins_third=nc)])
+    plan.sync()
+    got = _np(h)
+    assert np.array_equal(got, want)
+    assert got.reshape(w.nbins, w.nbins, nc)[:, :, w.nbins:].sum() > 0
