@@ -995,28 +995,50 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
 // thread of slab bin (a, b, c) with a <= b owns half bin (a, b, c): it adds
 // the mirror (b, a, c) when b is a slab row too, and writes the output
 // (half, or both mirrored full bins), so every output bin has one writer.
+// A block first lists the slots of its segment in LDS (in chunks of
+// kReduceChunk slots), so each bin sums only those.
+constexpr int kReduceChunk = 2048;
+
 __global__ void __launch_bounds__(256) k_reduce(TripletArgs A)
 {
+    __shared__ int s_idx[kReduceChunk];
+    __shared__ int s_n;
     const int seg = blockIdx.y;
     const Seg& G = A.segs[seg];
+    if ((int)blockIdx.x * 256 >= G.hb) return;      // whole block past the segment
     const int x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= G.hb) return;
     const Sys& S = A.sys[G.sys];
     const int nb = S.nbins, nb3 = S.nb3, RL = G.rl;
-    const int a = G.lo0 + x / RL, rem = x - (x / RL) * RL;
-    const int b = G.lo0 + rem / nb3, c = rem - (rem / nb3) * nb3;
-    if (b < a) return;
-    const bool mirror = b != a && b < G.lo1;
-    const int xm = (b - G.lo0) * RL + (a - G.lo0) * nb3 + c;
+    int a = 0, b = 0, c = 0, xm = 0;
+    bool active = x < G.hb;
+    if (active) {
+        a = G.lo0 + x / RL;
+        const int rem = x - (x / RL) * RL;
+        b = G.lo0 + rem / nb3;
+        c = rem - (rem / nb3) * nb3;
+        active = b >= a;
+        xm = (b - G.lo0) * RL + (a - G.lo0) * nb3 + c;
+    }
+    const bool mirror = active && b != a && b < G.lo1;
     const uint32_t used = min(A.ctl->slots_used, (uint32_t)A.max_slots);
     uint64_t sum = 0;
-    for (uint32_t s = 0; s < used; ++s)
-        if (A.slot_seg[s] == seg) {
-            const uint32_t* sl = A.slots + (size_t)s * A.hb_max;
-            sum += sl[x];
-            if (mirror) sum += sl[xm];
-        }
-    if (sum == 0) return;
+    for (uint32_t base = 0; base < used; base += kReduceChunk) {
+        const uint32_t end = min(used, base + (uint32_t)kReduceChunk);
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+        for (uint32_t s = base + threadIdx.x; s < end; s += 256)
+            if (A.slot_seg[s] == seg) s_idx[atomicAdd(&s_n, 1)] = (int)s;
+        __syncthreads();
+        const int n = s_n;
+        if (active)
+            for (int k = 0; k < n; ++k) {
+                const uint32_t* sl = A.slots + (size_t)s_idx[k] * A.hb_max;
+                sum += sl[x];
+                if (mirror) sum += sl[xm];
+            }
+        __syncthreads();
+    }
+    if (!active || sum == 0) return;
     if (S.tri) {
         S.tri[((size_t)a * nb - (size_t)a * (a - 1) / 2 + (b - a)) * nb3 + c] += sum;
     } else if (S.layout == 0) {
