@@ -122,6 +122,7 @@ inline size_t triplet_lds_bytes(int hb_max, int cb)
 // waves per workgroup and the pool entries a wave reserves at a time.
 constexpr int kBuildWavesPerWG = 4;
 constexpr uint32_t kBuildChunk = 2048;
+constexpr int kStageCap = 1024;      // stencil atoms staged in LDS per home cell
 inline int build_wgs_per_job(int n_jobs, int max_cells)
 {
     // about 4 resident workgroups per CU on 256 CUs, all in one round
@@ -135,8 +136,8 @@ void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
 void launch_cell_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
 void launch_cell_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s);
 void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
-size_t nbr_build_lds_bytes(int stg_cap);
-void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int stg_cap, bool wide,
+size_t nbr_build_lds_bytes();
+void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
                       bool one_step, hipStream_t s);
 void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);

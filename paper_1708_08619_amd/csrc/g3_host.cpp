@@ -23,7 +23,6 @@ namespace {
 using namespace g3;
 
 constexpr int kListCap = 4096;       // neighbours per centre held by the triplet kernel
-constexpr int kStageCap = 1024;      // stencil atoms staged in LDS by the neighbour build
 constexpr int kTabMax = kTabBytes;   // bytes of the bin lookup table in LDS
 constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
 constexpr size_t kLdsPerCU = 160 * 1024;
@@ -646,7 +645,7 @@ g3_status upload_geometry(g3_plan p, const std::vector<Prepared>& ps)
 g3_status set_lds_limits(g3_plan p)
 {
     if (p->lds_set) return G3_OK;
-    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_build_lds_bytes(kStageCap)));
+    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_build_lds_bytes()));
     p->lds_set = true;
     return G3_OK;
 }
@@ -728,7 +727,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
         launch_cell_count(dsys, j, 1, N, p->stream);
         launch_cell_scan(dsys, j, 1, p->stream);
         launch_cell_scatter(dsys, j, 1, N, p->stream);
-        launch_nbr_build(dsys, j, 1, P.g.ncell, kStageCap, P.g.wide != 0, P.g.one_step != 0, p->stream);
+        launch_nbr_build(dsys, j, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, p->stream);
         launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
         if (tri.second > tri.first)
             launch_zero_u32((uint32_t*)((char*)p->arena + tri.first), (tri.second - tri.first) / 4, p->stream);
@@ -873,7 +872,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_count(dsys, djobs, nj, max_n, sm);
             launch_cell_scan(dsys, djobs, nj, sm);
             launch_cell_scatter(dsys, djobs, nj, max_n, sm);
-            launch_nbr_build(dsys, djobs, nj, max_cells, kStageCap, wide, one_step, sm);
+            launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, sm);
             launch_triplet(a, wide, one_step, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
             if (any_tri) launch_expand(dsys, n_sys, max_nb, sm);
@@ -885,7 +884,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_count(dsys, djobs, nj, max_n, p->stream);
             launch_cell_scan(dsys, djobs, nj, p->stream);
             launch_cell_scatter(dsys, djobs, nj, max_n, p->stream);
-            launch_nbr_build(dsys, djobs, nj, max_cells, kStageCap, wide, one_step, p->stream);
+            launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, p->stream);
             hipEvent_t e0;
             timing_begin(p, &e0);
             launch_triplet(a, wide, one_step, n_wg, p->stream);

@@ -196,7 +196,7 @@ constexpr uint32_t kChunk = kBuildChunk;
 
 template <bool WIDE, bool ONE_STEP>
 __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restrict__ sys,
-                                                             const Job* __restrict__ jobs, int stg_cap)
+                                                             const Job* __restrict__ jobs)
 {
     using E = typename std::conditional<WIDE, int4, uint2>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -207,10 +207,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     E* s_buf = reinterpret_cast<E*>(s_slab + 256);                           // [waves][kWaveBuf]
     uint32_t* s_scnt = reinterpret_cast<uint32_t*>(s_buf + kBuildWaves * kWaveBuf);  // [waves][64]
     uint32_t* s_g2 = s_scnt + kBuildWaves * 64;                              // [256] pair bins
-    uint8_t* s_sb = reinterpret_cast<uint8_t*>(s_g2 + 256);                  // [waves][kWaveBuf] slab
-    int32_t* s_x = reinterpret_cast<int32_t*>(s_sb + kBuildWaves * kWaveBufMax);
-    int32_t* s_y = s_x + stg_cap;
-    int32_t* s_z = s_y + stg_cap;
+    uint32_t* s_idx = s_g2 + 256;            // [waves][kWaveBufMax] candidate, then slab
+    int32_t* s_x = reinterpret_cast<int32_t*>(s_idx + kBuildWaves * kWaveBufMax);  // [kStageCap]
+    int32_t* s_y = s_x + kStageCap;
+    int32_t* s_z = s_y + kStageCap;
     __shared__ Stencil st;
 
     const Job jb = jobs[blockIdx.y];
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     const int64_t pool_cap = S.pool_cap;
     uint32_t* scnt = s_scnt + wave * 64;
     E* buf = s_buf + wave * kWaveBuf;
-    uint8_t* sb = s_sb + wave * kWaveBuf;     // slab of each buffered entry
+    uint32_t* idx = s_idx + wave * kWaveBufMax;   // per buffered entry: candidate, then slab
     uint32_t* flags = S.flags + f;
     uint32_t* cursor = S.cursor + (size_t)f * kCursorStride;
     uint32_t chunk_base = 0, chunk_left = 0;   // this wave's slice of the pool
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
         }
         __syncthreads();
         const int T = st.pre[st.n];
-        const bool staged = T <= stg_cap;
+        const bool staged = T <= kStageCap;
         auto cell_of_t = [&](int t) {
             int r = 0;
             while (st.pre[r + 1] <= t) ++r;
@@ -353,16 +353,17 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             const int xi = staged ? s_x[tself] : X[ci];
             const int yi = staged ? s_y[tself] : Y[ci];
             const int zi = staged ? s_z[tself] : Z[ci];
-            // candidate t: accepted -> true with the entry and its bin
-            // Evaluated without branches: an invalid or rejected candidate
-            // still computes (garbage) values from in-range reads and returns
-            // false.  With every |d| <= C-1: narrow (C <= 32767) squares sum
-            // below 2^32; wide ones (C <= 46340) may wrap only when dz^2 is
-            // added, which the carry test catches.
-            auto test = [&](int t, E& e, int& b) -> bool {
+            // Separation of candidate t from the centre; true if accepted.
+            // Branch-free: an invalid candidate reads the centre's own
+            // coordinates (staged) and is rejected.  Every component is
+            // tested against C before the squares are summed: with |d| <= C-1
+            // narrow sums (C <= 32767) stay below 2^32; wide ones (C <= 46340)
+            // may wrap only when dz^2 is added, which the carry test catches.
+            // FAST: staged, and no axis needs an explicit minimum image.
+            auto sep = [&](auto FAST, int t, int& dx, int& dy, int& dz, uint32_t& s) -> bool {
                 const bool valid = t < T && t != tself;
                 int x, y, z;
-                if (staged) {
+                if (decltype(FAST)::value || staged) {
                     const int tc = valid ? t : tself;
                     x = s_x[tc]; y = s_y[tc]; z = s_z[tc];
                 } else {
@@ -371,55 +372,96 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     const int j = st.start[r] + (t - st.pre[r]);
                     x = X[j] + st.shx[r]; y = Y[j] + st.shy[r]; z = Z[j] + st.shz[r];
                 }
-                int dx = x - xi, dy = y - yi, dz = z - zi;
-                if (ncx == 1) dx = min_image(dx, Lx);
-                if (ncy == 1) dy = min_image(dy, Ly);
-                if (ncz == 1) dz = min_image(dz, Lz);
+                dx = x - xi; dy = y - yi; dz = z - zi;
+                if constexpr (!decltype(FAST)::value) {
+                    if (ncx == 1) dx = min_image(dx, Lx);
+                    if (ncy == 1) dy = min_image(dy, Ly);
+                    if (ncz == 1) dz = min_image(dz, Lz);
+                }
                 const bool inr = max((uint32_t)(dx + cm1), max((uint32_t)(dy + cm1), (uint32_t)(dz + cm1))) <= span;
                 const uint32_t s2 = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy);
-                const uint32_t s = s2 + (uint32_t)__mul24(dz, dz);
-                bool ok = valid && inr && s < R2;
-                if constexpr (WIDE) ok = ok && s >= s2;
+                s = s2 + (uint32_t)__mul24(dz, dz);
+                bool ok = valid & inr & (s < R2);
+                if constexpr (WIDE) ok = ok & (s >= s2);
+                return ok;
+            };
+            // pair bin of an accepted square distance s < R2
+            auto bin_of = [&](uint32_t s) -> int {
+                int b;
                 if constexpr (ONE_STEP) {
                     b = s_tab[__builtin_amdgcn_ubfe(s, (uint32_t)sh, (uint32_t)tbits)];
                     b += (s >= s_thr[b + 1]) ? 1 : 0;
                 } else {
-                    const uint32_t sc = min(s, R2 - 1u);
-                    b = s_tab[sc >> sh];
-                    while (sc >= s_thr[b + 1]) ++b;
+                    b = s_tab[s >> sh];
+                    while (s >= s_thr[b + 1]) ++b;
                 }
-                const int bn = __mul24(b, nb3);
+                return b;
+            };
+            auto pack = [&](int dx, int dy, int dz, int bn) -> E {
                 if constexpr (WIDE) {
-                    e = make_int4(dx, dy, dz, bn);
+                    return make_int4(dx, dy, dz, bn);
                 } else {
-                    e = make_uint2(((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16),
-                                   ((uint32_t)dz & 0xffffu) | ((uint32_t)bn << 16));
+                    return make_uint2(((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16),
+                                      ((uint32_t)dz & 0xffffu) | ((uint32_t)bn << 16));
                 }
-                return ok;
             };
             scnt[lane] = 0u;
             wave_sync();
-            // the one evaluation pass: count per slab, compact into the buffer
+            // Pass 1, the cheap one: test every candidate and compact the
+            // indices of the accepted ones (a list longer than the buffer
+            // overwrites its last index and is re-evaluated below).  Two
+            // groups of 64 per iteration.
             uint32_t n = 0;
-            for (int t0 = t_first; t0 < T; t0 += 64) {
-                E e;
-                int b = 0;
-                const bool acc = test(t0 + lane, e, b);
-                const uint64_t mask = __ballot(acc);
-                if (acc) {
-                    const uint32_t pos = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            auto push = [&](bool ok, int t) {
+                const uint64_t mask = __ballot(ok);
+                const uint32_t pos = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                if (ok) idx[min(pos, (uint32_t)kWaveBuf - 1u)] = (uint32_t)t;
+                n += (uint32_t)__popcll(mask);
+            };
+            // Pass 2, on the accepted candidates only: entry, pair bin, slab,
+            // slab counts (and the pair histogram).
+            auto pass12 = [&](auto FAST) {
+                for (int t0 = t_first; t0 < T; t0 += 128) {
+                    int dx, dy, dz;
+                    uint32_t sa, sb2;
+                    const bool oa = sep(FAST, t0 + lane, dx, dy, dz, sa);
+                    const bool ob = sep(FAST, t0 + 64 + lane, dx, dy, dz, sb2);
+                    push(oa, t0 + lane);
+                    push(ob, t0 + 64 + lane);
+                }
+                wave_sync();
+                if (n > (uint32_t)kWaveBuf) return;
+                for (uint32_t e = lane; e < n; e += 64) {
+                    int dx, dy, dz;
+                    uint32_t s;
+                    sep(FAST, (int)idx[e], dx, dy, dz, s);
+                    const int b = bin_of(s);
                     const uint32_t q = s_slab[b];
-                    if (pos < (uint32_t)kWaveBuf) {
-                        buf[pos] = e;
-                        sb[pos] = (uint8_t)q;
-                    }
                     atomicAdd(&scnt[q], 1u);
                     if (pair_hist) atomicAdd(&s_g2[b], pair_inc);
+                    buf[e] = pack(dx, dy, dz, __mul24(b, nb3));
+                    idx[e] = q;
                 }
-                n += (uint32_t)__popcll(mask);
-            }
+            };
+            if (staged && ncx > 1 && ncy > 1 && ncz > 1) pass12(std::true_type{});
+            else pass12(std::false_type{});
             wave_sync();
+            const bool buffered = n <= (uint32_t)kWaveBuf;
+            if (!buffered) {
+                // a long list: count the slabs by re-evaluating every candidate
+                for (int t0 = t_first; t0 < T; t0 += 64) {
+                    int dx, dy, dz;
+                    uint32_t s;
+                    if (sep(std::false_type{}, t0 + lane, dx, dy, dz, s)) {
+                        const int b = bin_of(s);
+                        atomicAdd(&scnt[s_slab[b]], 1u);
+                        if (pair_hist) atomicAdd(&s_g2[b], pair_inc);
+                    }
+                }
+                wave_sync();
+            }
+            // a centre over the list capacity has its pairs counted, no list
             if (n > (uint32_t)list_cap) {
                 if (lane == 0) {
                     atomicOr(flags, kFlagList);
@@ -458,16 +500,20 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 if (lane < n_slabs) scnt[lane] = J;
                 wave_sync();
             }
+            // Pass 3: each entry at J_{slab} + its rank in the slab
             E* P = pool + base;
-            if (n <= (uint32_t)kWaveBuf) {
+            if (buffered) {
                 for (uint32_t e = lane; e < n; e += 64) {
-                    P[atomicAdd(&scnt[sb[e]], 1u)] = buf[e];
+                    P[atomicAdd(&scnt[idx[e]], 1u)] = buf[e];
                 }
             } else {
                 for (int t0 = t_first; t0 < T; t0 += 64) {
-                    E e;
-                    int b = 0;
-                    if (test(t0 + lane, e, b)) P[atomicAdd(&scnt[s_slab[b]], 1u)] = e;
+                    int dx, dy, dz;
+                    uint32_t s;
+                    if (sep(std::false_type{}, t0 + lane, dx, dy, dz, s)) {
+                        const int b = bin_of(s);
+                        P[atomicAdd(&scnt[s_slab[b]], 1u)] = pack(dx, dy, dz, __mul24(b, nb3));
+                    }
                 }
             }
             if (lane == 0) {
@@ -1114,25 +1160,25 @@ void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n,
     hipLaunchKernelGGL(k_cell_scatter, dim3((max_n + 255) / 256, n_jobs), dim3(256), 0, s, sys, jobs);
 }
 
-size_t nbr_build_lds_bytes(int stg_cap)
+size_t nbr_build_lds_bytes()
 {
     return kThrMax * 4 + 8192 + 256 + (size_t)kBuildWaves * kBufBytes + kBuildWaves * 64 * 4 +
-           256 * 4 + (size_t)kBuildWaves * kWaveBufMax + (size_t)3 * stg_cap * 4;
+           256 * 4 + (size_t)kBuildWaves * kWaveBufMax * 4 + (size_t)3 * kStageCap * 4;
 }
 
-void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int stg_cap, bool wide,
+void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
                       bool one_step, hipStream_t s)
 {
     // enough workgroups per frame to fill the chip, each looping over cells
     const int per_job = build_wgs_per_job(n_jobs, max_cells);
-    const size_t lds = nbr_build_lds_bytes(stg_cap);
+    const size_t lds = nbr_build_lds_bytes();
     const dim3 g(per_job, n_jobs), b(kBuildThreads);
     if (wide) {
-        if (one_step) hipLaunchKernelGGL((k_nbr_build<true, true>), g, b, lds, s, sys, jobs, stg_cap);
-        else hipLaunchKernelGGL((k_nbr_build<true, false>), g, b, lds, s, sys, jobs, stg_cap);
+        if (one_step) hipLaunchKernelGGL((k_nbr_build<true, true>), g, b, lds, s, sys, jobs);
+        else hipLaunchKernelGGL((k_nbr_build<true, false>), g, b, lds, s, sys, jobs);
     } else {
-        if (one_step) hipLaunchKernelGGL((k_nbr_build<false, true>), g, b, lds, s, sys, jobs, stg_cap);
-        else hipLaunchKernelGGL((k_nbr_build<false, false>), g, b, lds, s, sys, jobs, stg_cap);
+        if (one_step) hipLaunchKernelGGL((k_nbr_build<false, true>), g, b, lds, s, sys, jobs);
+        else hipLaunchKernelGGL((k_nbr_build<false, false>), g, b, lds, s, sys, jobs);
     }
 }
 
