@@ -552,12 +552,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
 //
 // Per centre the neighbour list is sorted by pair bin.  The pairs whose
 // smaller bin lies in the slab are those with at least one member among the
-// slab rows, entries [J_q, J_q+1) (local 0..r-1 after staging from J_q):
-//   triangle:  both members in the slab rows -- row j takes k = j+1 ... j+h
-//              (mod r), h = (r-1)/2, plus k = j + r/2 for j < r/2 when r is
-//              even, so each unordered pair is visited exactly once;
-//   rectangle: j a slab row, k = r .. m-1 (bins >= lo1).
-// Every row of a centre therefore has the same length, m - r + ~r/2.
+// slab rows, entries [J_q, J_q+1) (local 0..r-1 counted from J_q; m entries
+// from J_q to the end of the list).  Row j takes k = j+1 .. m-1: the slab
+// rows above it (each unordered pair of slab rows once, at its lower row)
+// and every entry with bins >= lo1.  Rows j and r-1-j form one work unit of
+// 2m - r - 1 candidates (the middle row of an odd r is a unit of its own), so
+// the units of a centre are equally long and each is two contiguous runs.
 // Per candidate: d_jk = d_ik - d_ij (no re-wrap), s = |d_jk|^2 exact,
 // accepted iff s < R2, bin c from the table plus one threshold step.
 namespace {
@@ -848,11 +848,11 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const uint32_t bstart = block_excl_scan_at(bc, kTlMisc, &nne);
         if (tid < 256) st32(kTlKeys + 4u * tid, bstart);
         __syncthreads();
-        if (r) {
+        if (r) {   // units: row pairs; m and r packed (both <= the list capacity < 2^16)
             const uint32_t pos = ld32(kTlKeys + 4u * key) + rank;
             st32(kSrc + 4u * pos, src);
-            st32(kM + 4u * pos, m);
-            st32(kRoff + 4u * pos, r);
+            st32(kM + 4u * pos, m | (r << 16));
+            st32(kRoff + 4u * pos, (r + 1u) >> 1);
         }
         const int nne_u = __builtin_amdgcn_readfirstlane((int)nne);
         __syncthreads();
@@ -928,108 +928,99 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             }
             if (w >= U) continue;
             const uint32_t r0 = ld32(kRoff + 4u * (uint32_t)cl);
-            const int rr = (int)(ld32(kRoff + 4u * (uint32_t)cl + 4u) - r0);
             const uint32_t lw = w - (r0 << pp);
-            const int j = (int)(lw >> pp), p = (int)(lw & ((1u << pp) - 1u));
+            const int jp = (int)(lw >> pp), p = (int)(lw & ((1u << pp) - 1u));
             const uint32_t eoff = ld32(kSrc + 4u * (uint32_t)cl) * ES;   // byte offset of entry J_q
-            const int mm = (int)ld32(kM + 4u * (uint32_t)cl);
-            const E vj = pool.load(eoff + (uint32_t)j * ES);
-            // slab index of (b_j, b_k, c) is (b_j - lo0) RL + (b_k - lo0) nb3 + c
-            // with RL = (nb - lo0) nb3; entries carry b nb3, and
-            // (b_j - lo0) RL = (b_j nb3)(nb - lo0) - lo0 RL
-            const int colj = Ent<WIDE>::col(vj);
-            const uint32_t rowbase = kTlHist + 4u * (uint32_t)(colj * (nb - lo0) - lo0 * RL - lo0 * nb3);
-            uint32_t jx, jy = 0, jz;
-            if constexpr (WIDE) {
-                jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
-            } else {
-                jx = vj.x; jz = vj.y & 0xffffu;
-            }
-            auto d2 = [&](const E& vk) -> uint32_t {
-                if constexpr (WIDE)
-                    return Ent<true>::dist2(vk, (int)jx, (int)jy, (int)jz, cm1);
-                else
-                    return Ent<false>::dist2(vk, jx, jz, 0);
-            };
-            // bin of s from the table plus the threshold step(s); any value
-            // for a rejected candidate, whose increment goes to the trash
-            auto bin = [&](uint32_t s) -> uint32_t {
-                uint32_t c;
-                if constexpr (ONE_STEP) {
-                    c = ld8(kTlTab + __builtin_amdgcn_ubfe(s, sh, tbits));
-                    c += (s >= ld32(kTlThr + 4u + 4u * c)) ? 1u : 0u;
+            const uint32_t mr = ld32(kM + 4u * (uint32_t)cl);
+            const int mm = (int)(mr & 0xffffu), rr = (int)(mr >> 16);
+            // the unit's rows and their runs: row jA over [jA+1, mm), then
+            // row jB over [jB+1, mm); this part covers [u0, u1) of the two
+            const int jA = jp, jB = rr - 1 - jp;
+            const int LA = mm - 1 - jA;
+            const int LB = jB > jA ? mm - 1 - jB : 0;
+            const int Lt = LA + LB;
+            const int u0 = __mul24(p, Lt) >> pp, u1 = __mul24(p + 1, Lt) >> pp;
+            // row j against candidates [k, kend)
+            auto run = [&](int j, int k, int kend) {
+                const E vj = pool.load(eoff + (uint32_t)j * ES);
+                // slab index of (b_j, b_k, c) is (b_j - lo0) RL + (b_k - lo0) nb3 + c
+                // with RL = (nb - lo0) nb3; entries carry b nb3, and
+                // (b_j - lo0) RL = (b_j nb3)(nb - lo0) - lo0 RL
+                const int colj = Ent<WIDE>::col(vj);
+                const uint32_t rowbase =
+                    kTlHist + 4u * (uint32_t)(__mul24(colj, nb - lo0) - lo0 * RL - lo0 * nb3);
+                uint32_t jx, jy = 0, jz;
+                if constexpr (WIDE) {
+                    jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
                 } else {
-                    const uint32_t sc = min(s, R3m1);
-                    c = ld8(kTlTab + (sc >> sh));
-                    while (sc >= ld32(kTlThr + 4u + 4u * c)) ++c;
+                    jx = vj.x; jz = vj.y & 0xffffu;
                 }
-                return c;
-            };
-            // four candidates at a time: distances, bins, addresses, then the
-            // four increments (rejected ones to this lane's trash word)
-            auto eval4 = [&](const E (&v)[4]) {
-                uint32_t s[4], a[4];
+                auto d2 = [&](const E& vk) -> uint32_t {
+                    if constexpr (WIDE)
+                        return Ent<true>::dist2(vk, (int)jx, (int)jy, (int)jz, cm1);
+                    else
+                        return Ent<false>::dist2(vk, jx, jz, 0);
+                };
+                // bin of s from the table plus the threshold step(s); any value
+                // for a rejected candidate, whose increment goes to the trash
+                auto bin = [&](uint32_t s) -> uint32_t {
+                    uint32_t c;
+                    if constexpr (ONE_STEP) {
+                        c = ld8(kTlTab + __builtin_amdgcn_ubfe(s, sh, tbits));
+                        c += (s >= ld32(kTlThr + 4u + 4u * c)) ? 1u : 0u;
+                    } else {
+                        const uint32_t sc = min(s, R3m1);
+                        c = ld8(kTlTab + (sc >> sh));
+                        while (sc >= ld32(kTlThr + 4u + 4u * c)) ++c;
+                    }
+                    return c;
+                };
+                // G candidates at a time: distances, bins, addresses, then the
+                // G increments (rejected ones to this lane's trash word)
+                auto evalg = [&](const E* v, auto GN) {
+                    constexpr int G = decltype(GN)::value;
+                    uint32_t s[G], a[G];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) s[u] = d2(v[u]);
+                    for (int u = 0; u < G; ++u) s[u] = d2(v[u]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    a[u] = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v[u]) + bin(s[u]));
-                // keep the address arithmetic unconditional (a select, not a branch)
-                asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]));
+                    for (int u = 0; u < G; ++u)
+                        a[u] = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v[u]) + bin(s[u]));
+                    // keep the address arithmetic unconditional (a select, not a branch)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) inc32(s[u] < R3 ? a[u] : trash);
-            };
-            auto eval1 = [&](const E& v) {
-                const uint32_t s = d2(v);
-                uint32_t a = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v) + bin(s));
-                asm volatile("" : "+v"(a));
-                inc32(s < R3 ? a : trash);
-            };
-            // this unit's share [u0, u1) of the row's sequence: u < H is the
-            // circular triangle (k = j + u + 1 mod rr), u >= H the rectangle
-            // (k = rr + u - H)
-            const int H = (rr - 1) / 2 + (((rr & 1) == 0 && j < rr / 2) ? 1 : 0);
-            const int L = H + (mm - rr);
-            const int u0 = (p * L) >> pp, u1 = ((p + 1) * L) >> pp;
-            const int tend = min(u1, H);
-            int t = u0 + 1;
-            for (; t + 3 <= tend; t += 4) {
-                E v[4];
+                    for (int u = 0; u < G; ++u) asm volatile("" : "+v"(a[u]));
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    int k = j + t + u;
-                    k -= (k >= rr) ? rr : 0;
-                    v[u] = pool.load(eoff + (uint32_t)k * ES);
-                }
-                eval4(v);
-            }
-            for (; t <= tend; ++t) {
-                int k = j + t;
-                k -= (k >= rr) ? rr : 0;
-                eval1(pool.load(eoff + (uint32_t)k * ES));
-            }
-            // rectangle: two register groups in ping-pong, each group's loads
-            // issued one group ahead (reads may run up to 7 entries past the
-            // list, into the pool slot's padding, and are never evaluated)
-            int k = rr + max(u0, H) - H;
-            const int kend = rr + u1 - H;
-            uint32_t ko = eoff + (uint32_t)k * ES;
-            if (k + 4 <= kend) {
-                E ga[4], gb[4];
-                pool.load4(ko, ga);
-                for (; k + 8 <= kend; k += 8, ko += 8 * ES) {
-                    pool.load4(ko + 4 * ES, gb);
-                    eval4(ga);
-                    pool.load4(ko + 8 * ES, ga);
-                    eval4(gb);
-                }
+                    for (int u = 0; u < G; ++u) inc32(s[u] < R3 ? a[u] : trash);
+                };
+                auto eval1 = [&](const E& v) {
+                    const uint32_t s = d2(v);
+                    uint32_t a = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v) + bin(s));
+                    asm volatile("" : "+v"(a));
+                    inc32(s < R3 ? a : trash);
+                };
+                // two register groups in ping-pong, each group's loads issued
+                // one group ahead (reads may run up to 7 entries past the list,
+                // into the pool slot's padding, and are never evaluated)
+                using G4 = std::integral_constant<int, 4>;
+                uint32_t ko = eoff + (uint32_t)k * ES;
                 if (k + 4 <= kend) {
-                    eval4(ga);
-                    k += 4;
-                    ko += 4 * ES;
+                    E ga[4], gb[4];
+                    pool.load4(ko, ga);
+                    for (; k + 8 <= kend; k += 8, ko += 8 * ES) {
+                        pool.load4(ko + 4 * ES, gb);
+                        evalg(ga, G4{});
+                        pool.load4(ko + 8 * ES, ga);
+                        evalg(gb, G4{});
+                    }
+                    if (k + 4 <= kend) {
+                        evalg(ga, G4{});
+                        k += 4;
+                        ko += 4 * ES;
+                    }
                 }
-            }
-            for (; k < kend; ++k, ko += ES) eval1(pool.load(ko));
+                for (; k < kend; ++k, ko += ES) eval1(pool.load(ko));
+            };
+            if (u0 < LA) run(jA, jA + 1 + u0, jA + 1 + min(u1, LA));
+            if (u1 > LA) run(jB, jB + 1 + max(u0, LA) - LA, jB + 1 + u1 - LA);
         }
         __syncthreads();
     }
