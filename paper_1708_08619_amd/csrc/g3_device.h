@@ -122,11 +122,11 @@ inline size_t triplet_lds_bytes(int hb_max, int cb)
 // waves per workgroup and the pool entries a wave reserves at a time.
 constexpr int kBuildWavesPerWG = 4;
 constexpr uint32_t kBuildChunk = 2048;
-constexpr int kStageCap = 1024;      // stencil atoms staged in LDS per home cell
+constexpr int kStageCap = 768;       // stencil atoms staged in LDS per home cell
 inline int build_wgs_per_job(int n_jobs, int max_cells)
 {
-    // about 4 resident workgroups per CU on 256 CUs, all in one round
-    int per_job = 1024 / (n_jobs > 0 ? n_jobs : 1);
+    // about 5 resident workgroups per CU on 256 CUs, all in one round
+    int per_job = 1280 / (n_jobs > 0 ? n_jobs : 1);
     if (per_job > max_cells) per_job = max_cells;
     return per_job < 1 ? 1 : per_job;
 }

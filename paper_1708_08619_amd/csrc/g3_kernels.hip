@@ -185,13 +185,15 @@ __device__ __forceinline__ void wave_sync()
 constexpr int kBuildThreads = 256;
 constexpr int kBuildWaves = kBuildWavesPerWG;
 static_assert(kBuildThreads == 64 * kBuildWavesPerWG, "build workgroup shape");
-// Neighbours buffered per wave before the write: 2 KB of entries per wave
+// Neighbours buffered per wave before the write: 1 KB of entries per wave
 // either way (a longer list re-evaluates its candidates for the write).
-// Keeping the workgroup under 40 KB of LDS lets 4 of them share a CU.
-constexpr int kBufBytes = 2048;
+// Keeping the workgroup under 32 KB of LDS lets 5 of them share a CU (the
+// kernel is latency-bound; 20 waves per CU instead of 16).
+constexpr int kBufBytes = 1024;
 template <bool WIDE>
 constexpr int wave_buf() { return kBufBytes / (WIDE ? 16 : 8); }
 constexpr int kWaveBufMax = kBufBytes / 8;
+constexpr int kSplitSlabs = 8;    // slabs up to which a short list is partitioned in registers
 constexpr uint32_t kChunk = kBuildChunk;
 
 template <bool WIDE, bool ONE_STEP>
@@ -420,7 +422,14 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 n += (uint32_t)__popcll(mask);
             };
             // Pass 2, on the accepted candidates only: entry, pair bin, slab,
-            // slab counts (and the pair histogram).
+            // slab counts (and the pair histogram).  With at most 64 accepted
+            // and at most kSplitSlabs slabs it is one sweep in registers: a
+            // ballot per slab gives every entry its slab-partitioned position
+            // and lane q the boundary J_q (the write follows the pool
+            // reservation below); otherwise the slab counts go through LDS.
+            E ent{};
+            uint32_t epos = 0, jlane = 0;
+            const bool split = n_slabs <= kSplitSlabs;
             auto pass12 = [&](auto FAST) {
                 for (int t0 = t_first; t0 < T; t0 += 128) {
                     int dx, dy, dz;
@@ -431,6 +440,30 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     push(ob, t0 + 64 + lane);
                 }
                 wave_sync();
+                if (split && n <= 64u) {
+                    const bool act = (uint32_t)lane < n;
+                    uint32_t q = 0xffu;
+                    if (act) {
+                        int dx, dy, dz;
+                        uint32_t s;
+                        sep(FAST, (int)idx[lane], dx, dy, dz, s);
+                        const int b = bin_of(s);
+                        q = s_slab[b];
+                        if (pair_hist) atomicAdd(&s_g2[b], pair_inc);
+                        ent = pack(dx, dy, dz, __mul24(b, nb3));
+                    }
+                    uint32_t J = 0;
+                    for (int qq = 0; qq < n_slabs; ++qq) {
+                        const bool mine = q == (uint32_t)qq;
+                        const uint64_t mk = __ballot(mine);
+                        if (lane == qq) jlane = J;
+                        if (mine) epos = J + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                        J += (uint32_t)__popcll(mk);
+                    }
+                    if (lane == n_slabs) jlane = J;   // = n
+                    return;
+                }
                 if (n > (uint32_t)kWaveBuf) return;
                 for (uint32_t e = lane; e < n; e += 64) {
                     int dx, dy, dz;
@@ -447,8 +480,9 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             if (staged && ncx > 1 && ncy > 1 && ncz > 1) pass12(std::true_type{});
             else pass12(std::false_type{});
             wave_sync();
+            const bool in_regs = split && n <= 64u;
             const bool buffered = n <= (uint32_t)kWaveBuf;
-            if (!buffered) {
+            if (!in_regs && !buffered) {
                 // a long list: count the slabs by re-evaluating every candidate
                 for (int t0 = t_first; t0 < T; t0 += 64) {
                     int dx, dy, dz;
@@ -483,6 +517,15 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             chunk_left -= n;
             if ((int64_t)base + n > pool_cap) {
                 if (lane == 0) atomicOr(flags, kFlagPool);
+                continue;
+            }
+            if (in_regs) {
+                if (lane <= n_slabs) slab_j[(size_t)ci * (n_slabs + 1) + lane] = (uint16_t)jlane;
+                if ((uint32_t)lane < n) pool[base + epos] = ent;
+                if (lane == 0) {
+                    nbr_off[ci] = base;
+                    nbr_cnt[ci] = n;
+                }
                 continue;
             }
             // slab boundaries J_q (exclusive scan of the slab counts)
@@ -660,10 +703,11 @@ struct GEnt<true> {
 constexpr uint32_t kTlThr = 0;                        // uint32 thr[kThrMax]
 constexpr uint32_t kTlTab = 4 * kThrMax;              // uint8 tab[kTabBytes]
 constexpr uint32_t kTlTrash = kTlTab + kTabBytes;     // uint32 [64]: rejected candidates land here
-constexpr uint32_t kTlMisc = kTlTrash + 256;          // uint32 scan[17], item, slot, chunk counter
+constexpr uint32_t kTlMisc = kTlTrash + 256;          // uint32 scan[17], item, slot, chunk counter, flag
 constexpr uint32_t kTlItem = kTlMisc + 4 * 17;
 constexpr uint32_t kTlSlot = kTlItem + 4;
 constexpr uint32_t kTlNext = kTlSlot + 4;
+constexpr uint32_t kTlAny = kTlNext + 4;             // some centre of the item has rows
 constexpr uint32_t kTlKeys = kTlMisc + 128;           // uint32 [256]: centres per row length
 constexpr uint32_t kTlHist = kTlKeys + 1024;          // uint32 hist[hb_max], then per item:
                                                       // src[cb], m[cb], roff[cb+1], chunk[kChunkCap]
@@ -786,7 +830,10 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
     };
 
     for (;;) {
-        if (tid == 0) st32(kTlItem, atomicAdd(&A.ctl->next_item, 1u));
+        if (tid == 0) {
+            st32(kTlItem, atomicAdd(&A.ctl->next_item, 1u));
+            st32(kTlAny, 0u);
+        }
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane((int)ld32(kTlItem));
         __syncthreads();
@@ -836,9 +883,13 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             src = o + j0;
             key = 255u - min(r / 2u + (m - r), 255u);   // the centre's longest row
         }
+        if (r) st32(kTlAny, 1u);
         if (tid < 256) st32(kTlKeys + 4u * tid, 0u);
         if (tid == 0) st32(kTlNext, 0u);
         __syncthreads();
+        // a block with no rows in this slab (common for slabs at short
+        // distances) skips the sort and the scans
+        if (ld32(kTlAny) == 0u) continue;
         const uint32_t rank = r ? fetch_inc32(kTlKeys + 4u * key) : 0u;
         // candidate pairs of this item: r(r-1)/2 + r(m-r) per centre
         const uint32_t inc = r ? r * (r - 1) / 2 + r * (m - r) : 0u;
