@@ -947,12 +947,15 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const int cm1 = S.C3 - 1;
         const int RL = G.rl, nb3 = S.nb3;
         const uint32_t trash = kTlTrash + 4u * (uint32_t)lane;
-        // waves take chunks of 64 units from a counter, longest rows first
+        // waves take chunks of 64 units from a counter, longest rows first;
+        // the next chunk index is fetched while this chunk runs (a wave's
+        // last fetch is beyond U and unused)
+        uint32_t cix_next = 0;
+        if (lane == 0) cix_next = fetch_inc32(kTlNext);
         for (;;) {
-            uint32_t cix = 0;
-            if (lane == 0) cix = fetch_inc32(kTlNext);
-            const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(cix, 0, 64)) * 64u;
+            const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(cix_next, 0, 64)) * 64u;
             if (w0 >= U) break;
+            if (lane == 0) cix_next = fetch_inc32(kTlNext);
             const uint32_t w = w0 + (uint32_t)lane;
             // (compacted) centre of unit w: the wave's first centre from the
             // chunk table, then one step per centre boundary inside the wave's
@@ -991,9 +994,9 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             const int LB = jB > jA ? mm - 1 - jB : 0;
             const int Lt = LA + LB;
             const int u0 = __mul24(p, Lt) >> pp, u1 = __mul24(p + 1, Lt) >> pp;
-            // row j against candidates [k, kend)
-            auto run = [&](int j, int k, int kend) {
-                const E vj = pool.load(eoff + (uint32_t)j * ES);
+            // row j against candidates [k, kend); vj is entry j and ga holds
+            // entries [k, k+4) (loaded by the caller, possibly ahead of time)
+            auto run = [&](const E vj, E (&ga)[4], int k, int kend) {
                 // slab index of (b_j, b_k, c) is (b_j - lo0) RL + (b_k - lo0) nb3 + c
                 // with RL = (nb - lo0) nb3; entries carry b nb3, and
                 // (b_j - lo0) RL = (b_j nb3)(nb - lo0) - lo0 RL
@@ -1054,8 +1057,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 using G4 = std::integral_constant<int, 4>;
                 uint32_t ko = eoff + (uint32_t)k * ES;
                 if (k + 4 <= kend) {
-                    E ga[4], gb[4];
-                    pool.load4(ko, ga);
+                    E gb[4];
                     for (; k + 8 <= kend; k += 8, ko += 8 * ES) {
                         pool.load4(ko + 4 * ES, gb);
                         evalg(ga, G4{});
@@ -1070,8 +1072,34 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 }
                 for (; k < kend; ++k, ko += ES) eval1(pool.load(ko));
             };
-            if (u0 < LA) run(jA, jA + 1 + u0, jA + 1 + min(u1, LA));
-            if (u1 > LA) run(jB, jB + 1 + max(u0, LA) - LA, jB + 1 + u1 - LA);
+            // Both runs' row entries and first groups are loaded before run A
+            // starts, so run B begins without a memory round trip (the wide
+            // form, short of registers, loads run B's when it starts).  A
+            // first group may read up to 3 entries past its run, into the
+            // pool padding; they are never evaluated.
+            const bool hasA = u0 < LA, hasB = u1 > LA;
+            const int kA = jA + 1 + u0, kB = jB + 1 + max(u0, LA) - LA;
+            E vA{}, gA[4];
+            if (hasA) {
+                vA = pool.load(eoff + (uint32_t)jA * ES);
+                pool.load4(eoff + (uint32_t)kA * ES, gA);
+            }
+            if constexpr (!WIDE) {
+                E vB{}, gB[4];
+                if (hasB) {
+                    vB = pool.load(eoff + (uint32_t)jB * ES);
+                    pool.load4(eoff + (uint32_t)kB * ES, gB);
+                }
+                if (hasA) run(vA, gA, kA, jA + 1 + min(u1, LA));
+                if (hasB) run(vB, gB, kB, jB + 1 + u1 - LA);
+            } else {
+                if (hasA) run(vA, gA, kA, jA + 1 + min(u1, LA));
+                if (hasB) {
+                    E vB = pool.load(eoff + (uint32_t)jB * ES), gB[4];
+                    pool.load4(eoff + (uint32_t)kB * ES, gB);
+                    run(vB, gB, kB, jB + 1 + u1 - LA);
+                }
+            }
         }
         __syncthreads();
     }
