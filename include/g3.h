@@ -108,6 +108,12 @@ typedef struct {
                                 atoms); default: meet each triangle once, at its
                                 lowest-ranked atom, and expand it exactly into the
                                 three histogram entries it owes */
+    int32_t slot_limit;      /* partial-histogram slots of one triplet launch; a
+                                workgroup whose slab cannot take a slot adds it
+                                to the output with 64-bit atomics instead.
+                                Default: one per workgroup and segment, up to
+                                256 MiB of slots; small values force the atomic
+                                path (for tests).  The autotuner keeps it. */
 } g3_tuning;
 
 /* Create a plan bound to a HIP stream (hipStream_t passed as void*, NULL =

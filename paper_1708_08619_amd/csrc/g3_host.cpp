@@ -323,6 +323,7 @@ hipError_t grow(void** ptr, size_t* have, size_t need)
 struct Tun {
     int hb_max, cb, wg_per_cu;
     bool tri_once;
+    int slot_limit;   // 0: automatic
 };
 
 Tun effective(const g3_plan p)
@@ -331,6 +332,7 @@ Tun effective(const g3_plan p)
     t.cb = p->tun.centres_per_item > 0 ? std::min(p->tun.centres_per_item, kTripletThreads) : 512;
     t.wg_per_cu = p->tun.wg_per_cu == 2 ? 2 : 1;
     t.tri_once = p->tun.per_centre != 1;
+    t.slot_limit = std::max(p->tun.slot_limit, 0);
     const size_t budget = kLdsPerCU / t.wg_per_cu - 256;   // static shared memory headroom
     const size_t fixed = triplet_lds_bytes(0, t.cb);
     int hb = budget > fixed ? (int)((budget - fixed) / 4) : 0;
@@ -492,6 +494,19 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
     s.per_frame = P.per_frame;
     s.flags = flags;
     return s;
+}
+
+// Partial slots of one triplet launch.  A workgroup flushes its slab at
+// most once per segment it works on (plus rare flushes that keep its uint32
+// counters exact), so n_wg per segment avoids the atomic fallback; the pool
+// is capped at 256 MiB (the fallback then takes the excess flushes).
+int slot_count(int n_wg, int n_segs, int hb_max, int limit)
+{
+    const int64_t want = (int64_t)n_wg * std::max(n_segs, 1) + 64;
+    const int64_t cap = std::max<int64_t>((int64_t)n_wg * 3 + 64,
+                                          ((int64_t)256 << 20) / ((int64_t)std::max(hb_max, 1) * 4));
+    const int n = (int)std::min(want, cap);
+    return limit > 0 ? std::min(limit, n) : n;
 }
 
 void add_segments(const Prepared& P, int sys_index, int frame0, int n_frames, int cb,
@@ -687,7 +702,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     }
     const int S = (int)P.g.slab_lo.size() - 1;
     const int n_wg = p->n_cu * tn.wg_per_cu;
-    const int max_slots = n_wg * 3 + 64;
+    const int max_slots = slot_count(n_wg, S, tn.hb_max, tn.slot_limit);
     // tables: [Sys][jobs][segs]
     const size_t o_sys = tables_base, o_jobs = align_up(o_sys + sizeof(Sys), 256),
                  o_segs = align_up(o_jobs + sizeof(Job) * F, 256),
@@ -794,7 +809,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         bool one_step = true;
         for (auto& P : ps) one_step = one_step && P.g.one_step;
         const int n_wg = p->n_cu * tn.wg_per_cu;
-        const int max_slots = n_wg * 3 + 2 * (int)segs.size() + 64;
+        const int max_slots = slot_count(n_wg, (int)segs.size(), tn.hb_max, tn.slot_limit);
         const size_t o_sys = 0, o_jobs = align_up(sizeof(Sys) * sys.size(), 256),
                      o_segs = align_up(o_jobs + sizeof(Job) * jobs.size(), 256),
                      o_slotseg = align_up(o_segs + sizeof(Seg) * segs.size(), 256),
@@ -819,7 +834,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         put(&wide, sizeof(wide));
         put(&one_step, sizeof(one_step));
         // tuning fields one by one (the struct's padding bytes are undefined)
-        const int32_t tk[4] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0};
+        const int32_t tk[5] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0, tn.slot_limit};
         put(tk, sizeof(tk));
         int nj = (int)jobs.size(), ns = (int)segs.size();
         put(&nj, 4); put(&ns, 4); put(&items, 4); put(&max_n, 4); put(&max_hb, 4); put(&max_cells, 4);
@@ -1250,6 +1265,7 @@ g3_status g3_get_tuning(g3_plan p, g3_tuning* t)
     t->centres_per_item = tn.cb;
     t->wg_per_cu = tn.wg_per_cu;
     t->per_centre = tn.tri_once ? 0 : 1;
+    t->slot_limit = tn.slot_limit;
     return G3_OK;
 }
 
@@ -1317,8 +1333,10 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
     const std::string key = tune_key(systems, n_systems, p->tun.per_centre);
     auto hit = p->tuned.find(key);
     if (hit != p->tuned.end()) {
+        const int32_t slot_limit = p->tun.slot_limit;   // kept, not tuned
         p->tun = hit->second;
-        if (best) *best = hit->second;
+        p->tun.slot_limit = slot_limit;
+        if (best) *best = p->tun;
         return G3_OK;
     }
     g3_status st = drain(p);
@@ -1356,6 +1374,7 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
             for (int fi = 0; fi < 2 && st == G3_OK; ++fi) {
                 g3_tuning t{};
                 t.per_centre = saved.per_centre;
+                t.slot_limit = saved.slot_limit;
                 t.wg_per_cu = wgs[wi];
                 t.centres_per_item = cbs[ci];
                 p->tun = t;

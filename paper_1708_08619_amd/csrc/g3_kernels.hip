@@ -843,7 +843,8 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const Seg& G = A.segs[seg];
         const Sys& S = A.sys[G.sys];
         if (seg != cur_seg) {
-            if (cur_seg >= 0) flush(cur_seg);
+            // (nothing added since the slab was zeroed: nothing to flush)
+            if (cur_seg >= 0 && pending) flush(cur_seg);
             if (G.sys != cur_sys) {
                 for (int x = tid; x <= S.nb3; x += kTripletThreads) st32(kTlThr + 4u * x, S.thr[x]);
                 for (int x = tid; x < S.tab_len; x += kTripletThreads) st8(kTlTab + x, S.tab[x]);
@@ -1103,7 +1104,7 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         }
         __syncthreads();
     }
-    if (cur_seg >= 0) flush(cur_seg);
+    if (cur_seg >= 0 && pending) flush(cur_seg);
     if (tid == 0 && evaluated) atomicAdd(A.cand, (unsigned long long)evaluated);
 }
 
@@ -1146,12 +1147,26 @@ __global__ void __launch_bounds__(256) k_reduce(TripletArgs A)
             if (A.slot_seg[s] == seg) s_idx[atomicAdd(&s_n, 1)] = (int)s;
         __syncthreads();
         const int n = s_n;
-        if (active)
-            for (int k = 0; k < n; ++k) {
+        if (active) {
+            // four slots per step, their reads in flight together
+            int k = 0;
+            for (; k + 4 <= n; k += 4) {
+                uint32_t v[4], u[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t* sl = A.slots + (size_t)s_idx[k + e] * A.hb_max;
+                    v[e] = sl[x];
+                    if (mirror) u[e] = sl[xm];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sum += (uint64_t)v[e] + u[e];
+            }
+            for (; k < n; ++k) {
                 const uint32_t* sl = A.slots + (size_t)s_idx[k] * A.hb_max;
                 sum += sl[x];
                 if (mirror) sum += sl[xm];
             }
+        }
         __syncthreads();
     }
     if (!active || sum == 0) return;

@@ -40,7 +40,7 @@ class System(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("lds_hist_bins", C.c_int32),
                 ("centres_per_item", C.c_int32), ("wg_per_cu", C.c_int32),
-                ("per_centre", C.c_int32)]
+                ("per_centre", C.c_int32), ("slot_limit", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -219,6 +219,29 @@ def test_tuning_does_not_change_results(g3mod, plan, torch_dev, oracle_mod, tun)
     assert_same(b, want, f"batched {tun}")
 
 
+@pytest.mark.parametrize("per_centre", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1])
+def test_atomic_flush_fallback(g3mod, plan, torch_dev, oracle_mod, per_centre, layout):
+    """One partial slot per launch: nearly every slab flush takes the 64-bit
+    atomic path (mirror writes of the full layout, the triangle buffer of
+    the default enumeration, a longer third axis); results are unchanged in
+    both forms."""
+    w = synth.lj_small("fcc", n_frames=3)
+    plan.set_tuning(slot_limit=1, lds_hist_bins=4096, per_centre=per_centre)
+    assert plan.get_tuning()["slot_limit"] == 1
+    want = oracle_mod.hist(w.frames, w.box, w.rmax, w.nbins, layout)
+    a, b = both(g3mod, plan, torch_dev, w.frames, w.box, w.rmax, w.nbins, layout)
+    assert_same(a, want, "plain")
+    assert_same(b, want, "batched")
+    L = w.box[0]
+    want3 = oracle_mod.hist(w.frames, w.box, L / 4.0, 16, layout, nbins_third=32)
+    h = g3mod.new_hist(16, layout, torch_dev, nbins_third=32)
+    plan.accumulate(_dev(w.frames.astype(np.int32), torch_dev), w.box, L / 4.0, 16, layout, h,
+                    nbins_third=32)
+    plan.sync()
+    assert_same(h.cpu().numpy().astype(np.uint64), want3, "third axis")
+
+
 # ------------------------------------------------------------------ edge cases
 def test_empty_and_tiny(g3mod, plan, torch_dev):
     import torch
