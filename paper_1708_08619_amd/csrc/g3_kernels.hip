@@ -28,6 +28,8 @@ __device__ __forceinline__ int cell_of(int x, int nc, int L)
     return (int)(((int64_t)x * nc) / L);
 }
 
+typedef short short2x __attribute__((ext_vector_type(2)));   // packed int16 pair
+
 // Minimum image of one component (only used on axes with a single cell);
 // |d| < L <= 2^29, so 2d fits int32.
 __device__ __forceinline__ int min_image(int d, int L)
@@ -375,6 +377,16 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     x = X[j] + st.shx[r]; y = Y[j] + st.shy[r]; z = Z[j] + st.shz[r];
                 }
                 dx = x - xi; dy = y - yi; dz = z - zi;
+                if constexpr (!WIDE && decltype(FAST)::value) {
+                    // narrow (C <= 32767): components saturated to int16 and
+                    // the squares summed with a clamped dot product; any
+                    // saturated component or clamped sum is >= R2, and an
+                    // accepted candidate's s is exact
+                    const short2x pk = __builtin_amdgcn_cvt_pk_i16(dx, dy);
+                    const int dzc = min(max(dz, -32768), 32767);
+                    s = (uint32_t)__builtin_amdgcn_sdot2(pk, pk, __mul24(dzc, dzc), true);
+                    return valid & (s < R2);
+                }
                 if constexpr (!decltype(FAST)::value) {
                     if (ncx == 1) dx = min_image(dx, Lx);
                     if (ncy == 1) dy = min_image(dy, Ly);

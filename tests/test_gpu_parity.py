@@ -242,6 +242,23 @@ def test_atomic_flush_fallback(g3mod, plan, torch_dev, oracle_mod, per_centre, l
     assert_same(h.cpu().numpy().astype(np.uint64), want3, "third axis")
 
 
+@pytest.mark.parametrize("per_centre", [0, 1])
+def test_narrow_components_beyond_int16(g3mod, plan, torch_dev, oracle_mod, per_centre):
+    """rmax = 30000 units in a 100000-unit box: 3 cells of 33333 units per
+    axis, so stencil components reach +-66666 while entries stay narrow
+    (C <= 32767).  The neighbour test saturates components to int16; every
+    saturated candidate must be rejected, every accepted one exact."""
+    rng = np.random.default_rng(77)
+    box = [100000, 100000, 100000]
+    fr = np.stack([np.stack([rng.integers(0, L, size=500) for L in box]) for _ in range(2)])
+    plan.set_tuning(per_centre=per_centre)
+    for layout in (0, 1):
+        want = oracle_mod.hist(fr, box, 30000.0, 20, layout)
+        a, b = both(g3mod, plan, torch_dev, fr, box, 30000.0, 20, layout)
+        assert_same(a, want, f"plain layout {layout}")
+        assert_same(b, want, f"batched layout {layout}")
+
+
 # ------------------------------------------------------------------ edge cases
 def test_empty_and_tiny(g3mod, plan, torch_dev):
     import torch
