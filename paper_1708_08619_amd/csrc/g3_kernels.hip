@@ -23,9 +23,13 @@ __device__ __forceinline__ size_t fr_off(const Sys& S, int f, size_t size)
     return S.per_frame ? (size_t)f * size : 0;
 }
 
+// floor(x nc / L) for 0 <= x < L <= 2^29, nc <= 2^10.  In double: x nc is
+// exact, and a non-integer quotient lies at least 1/L > 2^-30 from the next
+// integer while the rounded quotient is off by at most 2^-43, so the floor
+// of the correctly rounded quotient is exact.
 __device__ __forceinline__ int cell_of(int x, int nc, int L)
 {
-    return (int)(((int64_t)x * nc) / L);
+    return (int)((double)x * (double)nc / (double)L);
 }
 
 typedef short short2x __attribute__((ext_vector_type(2)));   // packed int16 pair
@@ -98,7 +102,29 @@ __global__ void __launch_bounds__(256) k_cell_count(const Sys* __restrict__ sys,
                          S.nc[0] +
                      cell_of(x, S.nc[0], S.box[0]);
     int32_t* cc = S.cell_count + fr_off(S, f, S.ncell);
-    const int rank = atomicAdd(&cc[cell], 1);
+    // Lanes of a wave in the same cell share one atomic (frames stored in a
+    // spatial order put many lanes in few cells); after 8 rounds the rest
+    // take one atomic each.
+    int rank = 0;
+    bool todo = true;
+    const int lane = threadIdx.x & 63;
+    for (int round = 0; round < 8; ++round) {
+        const uint64_t open = __ballot(todo);
+        if (!open) break;
+        const int leader = __builtin_ctzll(open);
+        const int lc = __shfl(cell, leader, 64);
+        const bool mine = todo && cell == lc;
+        const uint64_t m = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cc[lc], (int)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if (mine) {
+            rank = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            todo = false;
+        }
+    }
+    if (todo) rank = atomicAdd(&cc[cell], 1);
     S.atom_cell[fr_off(S, f, N) + a] = cell;
     S.atom_rank[fr_off(S, f, N) + a] = rank;
 }
