@@ -120,13 +120,13 @@ inline size_t triplet_lds_bytes(int hb_max, int cb)
 
 // Neighbour build launch shape: workgroups per frame (each loops over cells),
 // waves per workgroup and the pool entries a wave reserves at a time.
-constexpr int kBuildWavesPerWG = 4;
+constexpr int kBuildWavesPerWG = 8;
 constexpr uint32_t kBuildChunk = 2048;
 constexpr int kStageCap = 768;       // stencil atoms staged in LDS per home cell
 inline int build_wgs_per_job(int n_jobs, int max_cells)
 {
-    // about 5 resident workgroups per CU on 256 CUs, all in one round
-    int per_job = 1280 / (n_jobs > 0 ? n_jobs : 1);
+    // about 3 resident workgroups per CU on 256 CUs, all in one round
+    int per_job = 768 / (n_jobs > 0 ? n_jobs : 1);
     if (per_job > max_cells) per_job = max_cells;
     return per_job < 1 ? 1 : per_job;
 }

@@ -210,13 +210,13 @@ __device__ __forceinline__ void wave_sync()
 
 }  // namespace
 
-constexpr int kBuildThreads = 256;
+constexpr int kBuildThreads = 512;
 constexpr int kBuildWaves = kBuildWavesPerWG;
 static_assert(kBuildThreads == 64 * kBuildWavesPerWG, "build workgroup shape");
 // Neighbours buffered per wave before the write: 1 KB of entries per wave
 // either way (a longer list re-evaluates its candidates for the write).
-// Keeping the workgroup under 32 KB of LDS lets 5 of them share a CU (the
-// kernel is latency-bound; 20 waves per CU instead of 16).
+// Eight waves share a cell's staged stencil; at 35 KB of LDS and 71 VGPRs
+// three workgroups (24 waves) share a CU (the kernel is latency-bound).
 constexpr int kBufBytes = 1024;
 template <bool WIDE>
 constexpr int wave_buf() { return kBufBytes / (WIDE ? 16 : 8); }
