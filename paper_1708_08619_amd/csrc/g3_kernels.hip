@@ -177,12 +177,15 @@ __global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sy
 // pair closer than rmax; an axis with a single cell gets an explicit minimum
 // image.  The list is staged in LDS when it fits (else read from the
 // cell-sorted arrays in global memory).  Each wave takes one centre:
-//   one pass over the candidates accepts |d|^2 < R2, bins it, counts it per
-//   r12 slab and compacts it into a per-wave LDS buffer (ballot + mbcnt);
-//   one atomic on the frame's pool cursor reserves the list;
-//   the slab counts are scanned into the boundaries J_q and every neighbour
-//   is written at J_{slab(b)} + its rank in the slab: the list comes out
-//   partitioned by slab, which is all the triplet kernel needs.
+//   pass 1 tests every candidate (|d|^2 < R2) and compacts the indices of
+//   the accepted ones into a per-wave LDS list (ballot + mbcnt);
+//   pass 2, on the accepted ones only, forms the entries and their pair
+//   bins and r12 slabs: a short list is partitioned by slab in registers
+//   (one ballot per slab), a longer one counts its slabs in LDS;
+//   the list is reserved from the wave's chunk of the frame's pool, the slab
+//   boundaries J_q are stored, and every neighbour is written at
+//   J_{slab(b)} + its rank in the slab: the list comes out partitioned by
+//   slab, which is all the triplet kernel needs.
 // A centre with more neighbours than the buffer re-evaluates its candidates
 // for the write.  Components are tested against C before squaring, then
 // s = dx^2 + dy^2 (+ dz^2 only if still below R2): exact in uint32 for
@@ -963,10 +966,10 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         pending += itot;
         evaluated += itot;
 
-        // Work units: every row is cut into Pp = 2^pp parts of its candidate
-        // sequence (circular triangle part, then the rectangle), about two
-        // units per thread; unit w of centre cl is row (w - roff[cl] Pp) >> pp,
-        // part (w - roff[cl] Pp) & (Pp - 1).
+        // Work units: every row pair is cut into Pp = 2^pp parts of its
+        // candidate sequence (run A, then run B), about two units per thread;
+        // unit w of centre cl is pair (w - roff[cl] Pp) >> pp, part
+        // (w - roff[cl] Pp) & (Pp - 1).
         int pp = 0;
         while (pp < 4 && (rtot << (pp + 1)) <= 2u * kTripletThreads) ++pp;
         const uint32_t U = rtot << pp;
