@@ -187,9 +187,10 @@ __global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sy
 //   J_{slab(b)} + its rank in the slab: the list comes out partitioned by
 //   slab, which is all the triplet kernel needs.
 // A centre with more neighbours than the buffer re-evaluates its candidates
-// for the write.  Components are tested against C before squaring, then
-// s = dx^2 + dy^2 (+ dz^2 only if still below R2): exact in uint32 for
-// C <= 46340, products on the 24-bit multiplier (|d| < 2^16).
+// for the write.  Narrow staged candidates saturate their components to
+// int16 and sum the squares with a clamped dot product; otherwise the
+// components are tested against C before squaring (exact in uint32 for
+// C <= 46340, products on the 24-bit multiplier).
 namespace {
 
 // The stencil of a cell: the home cell first, then the other cells.  Atoms
