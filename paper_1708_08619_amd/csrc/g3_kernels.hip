@@ -473,13 +473,19 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             uint32_t epos = 0, jlane = 0;
             const bool split = n_slabs <= kSplitSlabs;
             auto pass12 = [&](auto FAST) {
-                for (int t0 = t_first; t0 < T; t0 += 128) {
+                int t0 = t_first;
+                for (; t0 + 64 < T; t0 += 128) {
                     int dx, dy, dz;
                     uint32_t sa, sb2;
                     const bool oa = sep(FAST, t0 + lane, dx, dy, dz, sa);
                     const bool ob = sep(FAST, t0 + 64 + lane, dx, dy, dz, sb2);
                     push(oa, t0 + lane);
                     push(ob, t0 + 64 + lane);
+                }
+                if (t0 < T) {   // at most 64 left: one group
+                    int dx, dy, dz;
+                    uint32_t sa;
+                    push(sep(FAST, t0 + lane, dx, dy, dz, sa), t0 + lane);
                 }
                 wave_sync();
                 if (split && n <= 64u) {
