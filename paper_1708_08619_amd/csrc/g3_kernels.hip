@@ -389,15 +389,20 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             const int zi = staged ? s_z[tself] : Z[ci];
             // Separation of candidate t from the centre; true if accepted.
             // Branch-free: an invalid candidate reads the centre's own
-            // coordinates (staged) and is rejected.  Every component is
-            // tested against C before the squares are summed: with |d| <= C-1
-            // narrow sums (C <= 32767) stay below 2^32; wide ones (C <= 46340)
-            // may wrap only when dz^2 is added, which the carry test catches.
-            // FAST: staged, and no axis needs an explicit minimum image.
-            auto sep = [&](auto FAST, int t, int& dx, int& dy, int& dz, uint32_t& s) -> bool {
-                const bool valid = t < T && t != tself;
+            // coordinates (staged) and is rejected.  Outside the narrow FAST
+            // form every component is tested against C before the squares
+            // are summed: with |d| <= C-1 narrow sums (C <= 32767) stay below
+            // 2^32; wide ones (C <= 46340) may wrap only when dz^2 is added,
+            // which the carry test catches.
+            // MODE bit 0 (FAST): staged, and no axis needs an explicit minimum
+            // image; bit 1: every candidate ranks above the centre
+            // (triangle-once lists), so t != tself holds without a test.
+            auto sep = [&](auto MODE, int t, int& dx, int& dy, int& dz, uint32_t& s) -> bool {
+                constexpr bool FAST = (decltype(MODE)::value & 1) != 0;
+                constexpr bool ABOVE = (decltype(MODE)::value & 2) != 0;
+                const bool valid = t < T && (ABOVE || t != tself);
                 int x, y, z;
-                if (decltype(FAST)::value || staged) {
+                if (FAST || staged) {
                     const int tc = valid ? t : tself;
                     x = s_x[tc]; y = s_y[tc]; z = s_z[tc];
                 } else {
@@ -407,7 +412,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     x = X[j] + st.shx[r]; y = Y[j] + st.shy[r]; z = Z[j] + st.shz[r];
                 }
                 dx = x - xi; dy = y - yi; dz = z - zi;
-                if constexpr (!WIDE && decltype(FAST)::value) {
+                if constexpr (!WIDE && FAST) {
                     // narrow (C <= 32767): components saturated to int16 and
                     // the squares summed with a clamped dot product; any
                     // saturated component or clamped sum is >= R2, and an
@@ -417,7 +422,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     s = (uint32_t)__builtin_amdgcn_sdot2(pk, pk, __mul24(dzc, dzc), true);
                     return valid & (s < R2);
                 }
-                if constexpr (!decltype(FAST)::value) {
+                if constexpr (!FAST) {
                     if (ncx == 1) dx = min_image(dx, Lx);
                     if (ncy == 1) dy = min_image(dy, Ly);
                     if (ncz == 1) dz = min_image(dz, Lz);
@@ -472,20 +477,20 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             E ent{};
             uint32_t epos = 0, jlane = 0;
             const bool split = n_slabs <= kSplitSlabs;
-            auto pass12 = [&](auto FAST) {
+            auto pass12 = [&](auto MODE) {
                 int t0 = t_first;
                 for (; t0 + 64 < T; t0 += 128) {
                     int dx, dy, dz;
                     uint32_t sa, sb2;
-                    const bool oa = sep(FAST, t0 + lane, dx, dy, dz, sa);
-                    const bool ob = sep(FAST, t0 + 64 + lane, dx, dy, dz, sb2);
+                    const bool oa = sep(MODE, t0 + lane, dx, dy, dz, sa);
+                    const bool ob = sep(MODE, t0 + 64 + lane, dx, dy, dz, sb2);
                     push(oa, t0 + lane);
                     push(ob, t0 + 64 + lane);
                 }
                 if (t0 < T) {   // at most 64 left: one group
                     int dx, dy, dz;
                     uint32_t sa;
-                    push(sep(FAST, t0 + lane, dx, dy, dz, sa), t0 + lane);
+                    push(sep(MODE, t0 + lane, dx, dy, dz, sa), t0 + lane);
                 }
                 wave_sync();
                 if (split && n <= 64u) {
@@ -494,7 +499,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     if (act) {
                         int dx, dy, dz;
                         uint32_t s;
-                        sep(FAST, (int)idx[lane], dx, dy, dz, s);
+                        sep(MODE, (int)idx[lane], dx, dy, dz, s);
                         const int b = bin_of(s);
                         q = s_slab[b];
                         if (pair_hist) atomicAdd(&s_g2[b], pair_inc);
@@ -516,7 +521,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                 for (uint32_t e = lane; e < n; e += 64) {
                     int dx, dy, dz;
                     uint32_t s;
-                    sep(FAST, (int)idx[e], dx, dy, dz, s);
+                    sep(MODE, (int)idx[e], dx, dy, dz, s);
                     const int b = bin_of(s);
                     const uint32_t q = s_slab[b];
                     atomicAdd(&scnt[q], 1u);
@@ -525,8 +530,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
                     idx[e] = q;
                 }
             };
-            if (staged && ncx > 1 && ncy > 1 && ncz > 1) pass12(std::true_type{});
-            else pass12(std::false_type{});
+            const bool fast = staged && ncx > 1 && ncy > 1 && ncz > 1;
+            if (fast && tri_once) pass12(std::integral_constant<int, 3>{});
+            else if (fast) pass12(std::integral_constant<int, 1>{});
+            else pass12(std::integral_constant<int, 0>{});
             wave_sync();
             const bool in_regs = split && n <= 64u;
             const bool buffered = n <= (uint32_t)kWaveBuf;
