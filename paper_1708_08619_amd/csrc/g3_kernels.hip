@@ -311,27 +311,43 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
     const int nst = (2 * rx + 1) * (2 * ry + 1) * (2 * rz + 1);
     const int home = nst / 2;   // (0,0,0) sits in the middle of the odd stencil grid
 
+    // A cell's atom range and, in wave 0 (lane e: stencil offset e), its
+    // stencil cells' index, start, end and periodic shift are loaded one cell
+    // ahead, while the previous cell is processed.
+    int p_c0 = 0, p_c1 = 0, p_c = 0x7fffffff, p_a = 0, p_e = 0, p_sx = 0, p_sy = 0, p_sz = 0;
+    auto fetch_cell = [&](int cl) {
+        if (cl >= ncell) return;
+        p_c0 = cs[cl];
+        p_c1 = cs[cl + 1];
+        if (wave == 0) {
+            p_c = 0x7fffffff; p_a = 0; p_e = 0; p_sx = 0; p_sy = 0; p_sz = 0;
+            if (lane < nst) {
+                const int kx = cl % ncx, ky = (cl / ncx) % ncy, kz = cl / (ncx * ncy);
+                const int ox = lane % (2 * rx + 1) - rx;
+                const int oy = (lane / (2 * rx + 1)) % (2 * ry + 1) - ry;
+                const int oz = lane / ((2 * rx + 1) * (2 * ry + 1)) - rz;
+                int x = kx + ox, y = ky + oy, z = kz + oz;
+                if (x < 0) { x += ncx; p_sx = -Lx; } else if (x >= ncx) { x -= ncx; p_sx = Lx; }
+                if (y < 0) { y += ncy; p_sy = -Ly; } else if (y >= ncy) { y -= ncy; p_sy = Ly; }
+                if (z < 0) { z += ncz; p_sz = -Lz; } else if (z >= ncz) { z -= ncz; p_sz = Lz; }
+                p_c = (z * ncy + y) * ncx + x;
+                p_a = cs[p_c];
+                p_e = cs[p_c + 1];
+            }
+        }
+    };
+    fetch_cell(blockIdx.x);
+
     for (int cell = blockIdx.x; cell < ncell; cell += gridDim.x) {
-        const int c0 = cs[cell], c1 = cs[cell + 1];
+        const int c0 = p_c0, c1 = p_c1;
+        const int c = p_c, a = p_a, e_end = p_e, shx = p_sx, shy = p_sy, shz = p_sz;
+        fetch_cell(cell + gridDim.x);
         if (c0 == c1) continue;   // uniform over the workgroup
         // stencil table: lane e of wave 0 takes stencil offset e; the home
         // cell goes to position 0, the kept others follow in lane order (the
         // cells are distinct), then a prefix sum of the counts in that order
         if (wave == 0) {
-            int c = 0x7fffffff, a = 0, cnt_e = 0, shx = 0, shy = 0, shz = 0;
-            if (lane < nst) {
-                const int kx = cell % ncx, ky = (cell / ncx) % ncy, kz = cell / (ncx * ncy);
-                const int ox = lane % (2 * rx + 1) - rx;
-                const int oy = (lane / (2 * rx + 1)) % (2 * ry + 1) - ry;
-                const int oz = lane / ((2 * rx + 1) * (2 * ry + 1)) - rz;
-                int x = kx + ox, y = ky + oy, z = kz + oz;
-                if (x < 0) { x += ncx; shx = -Lx; } else if (x >= ncx) { x -= ncx; shx = Lx; }
-                if (y < 0) { y += ncy; shy = -Ly; } else if (y >= ncy) { y -= ncy; shy = Ly; }
-                if (z < 0) { z += ncz; shz = -Lz; } else if (z >= ncz) { z -= ncz; shz = Lz; }
-                c = (z * ncy + y) * ncx + x;
-                a = cs[c];
-                cnt_e = cs[c + 1] - a;
-            }
+            const int cnt_e = lane < nst ? e_end - a : 0;
             const int c_home = __shfl(c, home, 64);
             const bool other = lane < nst && lane != home && (!tri_once || c > c_home);
             const uint64_t om = __ballot(other);
