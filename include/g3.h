@@ -101,7 +101,10 @@ typedef struct {
 typedef struct {
     int32_t lds_hist_bins;   /* uint32 histogram bins held in LDS per workgroup
                                 (the r12 slab size); slabs are whole rows lo */
-    int32_t centres_per_item;/* centres in one work item of the persistent kernel */
+    int32_t centres_per_item;/* centres in one work item of the persistent kernel
+                                (at most 2048; a frame with a list longer than
+                                fits such items below 2^32 candidate pairs is
+                                recomputed with 512-centre items) */
     int32_t wg_per_cu;       /* resident workgroups per compute unit (1 or 2) */
     int32_t per_centre;      /* 1: evaluate every centre's unordered neighbour pairs
                                 (the paper's loop, each triangle met at all three

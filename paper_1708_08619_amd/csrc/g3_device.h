@@ -12,6 +12,13 @@ namespace g3 {
 constexpr int kMaxSlabs = 63;          // r12 slabs per system (slab counts fit one wave)
 constexpr int kThrMax = 512;           // threshold table entries (third-side bins + 1)
 constexpr int kTripletThreads = 1024;  // threads of the triplet workgroup
+constexpr int kCentresPerThread = 2;   // centres a triplet thread sets up per item
+constexpr int kListCap = 4096;         // neighbours per centre held by the triplet kernel
+// Centres per triplet pass whose candidate pairs stay below 2^32 whatever the
+// lists (each centre has at most kListCap (kListCap - 1) / 2 in a slab).
+constexpr int kSafeItemCentres = 512;
+static_assert((uint64_t)kSafeItemCentres * kListCap * (kListCap - 1) / 2 <= 0xFFFFFFFFull,
+              "a safe pass keeps every uint32 LDS counter exact");
 constexpr int kTabBytes = 8192;        // LDS bytes of the bin lookup table
 constexpr int kWave = 64;
 constexpr int kPoolPad = 8;          // entries after each frame's pool slot that unrolled reads may touch
@@ -21,6 +28,7 @@ constexpr int kCursorStride = 32;   // uint32 words between per-frame pool curso
 constexpr uint32_t kFlagDomain = 1u;   // coordinate outside [0, L)
 constexpr uint32_t kFlagPool = 2u;     // neighbour lists exceed the frame's pool slot
 constexpr uint32_t kFlagList = 4u;     // one centre exceeds the per-centre capacity
+constexpr uint32_t kFlagDense = 8u;    // a list longer than m_safe: recomputed with safe items
 
 // Neighbour entry (minimum-image vector d_ij and its pair bin b):
 //  narrow (C <= 32767): x = (dx & 0xffff) | dy << 16, y = (dz & 0xffff) | (b * nbins) << 16
@@ -51,6 +59,7 @@ struct Sys {
     int32_t n_slabs;
     int32_t slab_lo[kMaxSlabs + 1];   // slab q holds rows lo in [slab_lo[q], slab_lo[q+1])
     int32_t list_cap;        // max neighbours per centre
+    int32_t m_safe;          // longest list for which an item's candidate pairs stay below 2^32
     // scratch (frame f uses base + f * stride; stride 0 = reused every frame)
     int32_t* cell_count;     // [ncell]        stride ncell*cell_mul
     int32_t* cell_start;     // [ncell + 1]

@@ -22,7 +22,6 @@ namespace {
 
 using namespace g3;
 
-constexpr int kListCap = 4096;       // neighbours per centre held by the triplet kernel
 constexpr int kTabMax = kTabBytes;   // bytes of the bin lookup table in LDS
 constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
 constexpr size_t kLdsPerCU = 160 * 1024;
@@ -329,7 +328,8 @@ struct Tun {
 Tun effective(const g3_plan p)
 {
     Tun t;
-    t.cb = p->tun.centres_per_item > 0 ? std::min(p->tun.centres_per_item, kTripletThreads) : 512;
+    t.cb = p->tun.centres_per_item > 0
+               ? std::min(p->tun.centres_per_item, kTripletThreads * kCentresPerThread) : 512;
     t.wg_per_cu = p->tun.wg_per_cu == 2 ? 2 : 1;
     t.tri_once = p->tun.per_centre != 1;
     t.slot_limit = std::max(p->tun.slot_limit, 0);
@@ -450,7 +450,17 @@ std::pair<size_t, size_t> tri_range(const std::vector<Prepared>& ps)
     return {b, e};
 }
 
-Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
+// Longest neighbour list for which cb centres have fewer than 2^32 candidate
+// pairs in any slab (each centre at most m (m - 1) / 2): the triplet
+// kernel's uint32 LDS counters then stay exact within an item.
+int32_t safe_list_len(int cb)
+{
+    int64_t m = kListCap;
+    while (m > 1 && (uint64_t)cb * (uint64_t)(m * (m - 1) / 2) > 0xFFFFFFFFull) --m;
+    return (int32_t)m;
+}
+
+Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
 {
     Sys s;
     std::memset(&s, 0, sizeof(s));
@@ -480,6 +490,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags)
     s.n_slabs = (int)g.slab_lo.size() - 1;
     for (size_t q = 0; q < g.slab_lo.size(); ++q) s.slab_lo[q] = g.slab_lo[q];
     s.list_cap = kListCap;
+    s.m_safe = safe_list_len(cb);
     s.cell_count = reinterpret_cast<int32_t*>(arena + P.off_cell_count);
     s.cell_start = reinterpret_cast<int32_t*>(arena + P.off_cell_start);
     s.atom_cell = reinterpret_cast<int32_t*>(arena + P.off_atom_cell);
@@ -690,7 +701,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
 
     const Prepared& P = ps[0];
     const int F = s.n_frames;
-    Sys sys = make_sys(P, (char*)p->arena, flags);
+    Sys sys = make_sys(P, (char*)p->arena, flags, tn.cb);
     std::vector<Job> jobs(F);
     for (int f = 0; f < F; ++f) jobs[f] = {0, f};
     std::vector<Seg> segs;
@@ -797,7 +808,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         int items = 0, fo = foff, max_n = 0, max_hb = 0;
         for (size_t k = 0; k < ps.size(); ++k) {
             p->recs.push_back({ps[k].in, fo, false});
-            sys.push_back(make_sys(ps[k], (char*)p->arena, p->flag_log + fo));
+            sys.push_back(make_sys(ps[k], (char*)p->arena, p->flag_log + fo, tn.cb));
             fo += ps[k].in.n_frames;
             for (int f = 0; f < ps[k].in.n_frames; ++f) jobs.push_back({(int)k, f});
             add_segments(ps[k], (int)k, 0, ps[k].in.n_frames, tn.cb, segs, items);
@@ -945,7 +956,8 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
     return G3_OK;
 }
 
-// Wait, read the flag log, recompute pool overflows through the plain path.
+// Wait, read the flag log, recompute through the plain path the frames whose
+// pool overflowed or whose lists were too long for the tuning's items.
 g3_status drain(g3_plan p)
 {
     G3_TRY_HIP(hipStreamSynchronize(p->stream));
@@ -961,7 +973,7 @@ g3_status drain(g3_plan p)
                 if (v & kFlagDomain) { if (result == G3_OK) result = G3_EDOMAIN; }
                 else if (v & kFlagList) { if (result == G3_OK) result = G3_ENOMEM; }
                 else if ((v & kFlagPool) && r.worst_case) { if (result == G3_OK) result = G3_ENOMEM; }
-                else if (v & kFlagPool) {
+                else if (v & (kFlagPool | kFlagDense)) {
                     g3_system one = r.sys;
                     one.frames = r.sys.frames + (size_t)f * 3 * r.sys.n_atoms;
                     one.pair_hist = nullptr;   // its pairs were counted in full already
@@ -972,10 +984,15 @@ g3_status drain(g3_plan p)
         }
         p->recs.clear();
         p->flag_used = 0;
+        // recomputed frames use items of kSafeItemCentres centres, whose
+        // candidate pairs stay below 2^32 for any list
+        const g3_tuning saved = p->tun;
+        if (!redo.empty() && effective(p).cb > kSafeItemCentres) p->tun.centres_per_item = kSafeItemCentres;
         for (const auto& one : redo) {
             g3_status st = run_plain(p, one, true);
-            if (st) return st;
+            if (st) { p->tun = saved; return st; }
         }
+        p->tun = saved;
         if (!redo.empty()) {
             g3_status st = drain(p);
             if (st && result == G3_OK) result = st;
@@ -1252,7 +1269,8 @@ g3_status g3_isosceles(const double* g3, int32_t layout, int32_t nbins, int32_t 
 g3_status g3_set_tuning(g3_plan p, const g3_tuning* t)
 {
     if (!p || !t) return G3_EINVAL;
-    if (t->wg_per_cu > 2 || t->centres_per_item > kTripletThreads || t->per_centre > 1) return G3_EINVAL;
+    if (t->wg_per_cu > 2 || t->centres_per_item > kTripletThreads * kCentresPerThread || t->per_centre > 1)
+        return G3_EINVAL;
     p->tun = *t;
     return G3_OK;
 }
@@ -1363,14 +1381,14 @@ g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems, g3
     hipEventCreate(&e1);
 
     const g3_tuning saved = p->tun;
-    const int cbs[3] = {256, 512, 1024};
+    const int cbs[4] = {256, 512, 1024, 2048};
     const int wgs[2] = {1, 2};
     const int fracs[2] = {4, 3};           // LDS histogram: all of it, or 3/4
     g3_tuning best_t = saved;
     double best_ms = 1e30;
     bool have_ref = false;
     for (int wi = 0; wi < 2 && st == G3_OK; ++wi)
-        for (int ci = 0; ci < 3 && st == G3_OK; ++ci)
+        for (int ci = 0; ci < 4 && st == G3_OK; ++ci)
             for (int fi = 0; fi < 2 && st == G3_OK; ++fi) {
                 g3_tuning t{};
                 t.per_centre = saved.per_centre;

@@ -551,6 +551,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restri
             else if (fast) pass12(std::integral_constant<int, 1>{});
             else pass12(std::integral_constant<int, 0>{});
             wave_sync();
+            // a list longer than m_safe could take an item of the triplet
+            // kernel past 2^32 candidate pairs: the frame is recomputed
+            // with smaller items (its lists and pairs are still built here)
+            if (n > (uint32_t)S.m_safe && lane == 0) atomicOr(flags, kFlagDense);
             const bool in_regs = split && n <= 64u;
             const bool buffered = n <= (uint32_t)kWaveBuf;
             if (!in_regs && !buffered) {
@@ -940,49 +944,79 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const GEnt<WIDE> pool{reinterpret_cast<const char*>(S.pool) + pbase * sizeof(E)};
         constexpr uint32_t ES = GEnt<WIDE>::kSize;
 
-        // per centre: its entries from J_q on (m) and its slab rows (r).
+        // per centre: its entries from J_q on (m) and its slab rows (r);
+        // thread tid holds centres tid and tid + kTripletThreads of the item.
         // Centres with rows are put in order of decreasing row length (a
         // counting sort over 256 buckets), so that the 64 rows of a wave are
-        // about equally long, and unit boundaries strictly increase.
-        uint32_t m = 0, r = 0, src = 0, key = 0;
-        if (tid < nctr) {
-            const int i = c_begin + tid;
-            const uint32_t o = off[i], n = cnt[i];
-            const uint32_t j0 = J[(size_t)i * (S.n_slabs + 1) + q];
-            const uint32_t j1 = J[(size_t)i * (S.n_slabs + 1) + q + 1];
-            r = j1 - j0;
-            m = r ? n - j0 : 0u;
-            src = o + j0;
-            key = 255u - min(r / 2u + (m - r), 255u);   // the centre's longest row
+        // about equally long, and unit boundaries strictly increase.  The
+        // item's candidate pairs stay below 2^32 (every uint32 counter exact):
+        // the neighbour build flags frames with lists longer than m_safe.
+        uint32_t m[kCentresPerThread], r[kCentresPerThread], src[kCentresPerThread],
+            key[kCentresPerThread];
+        uint32_t any = 0u;
+#pragma unroll
+        for (int h = 0; h < kCentresPerThread; ++h) {
+            m[h] = r[h] = src[h] = key[h] = 0u;
+            const int t = tid + h * kTripletThreads;
+            if (t < nctr) {
+                const int i = c_begin + t;
+                const uint32_t o = off[i], n = cnt[i];
+                const uint32_t j0 = J[(size_t)i * (S.n_slabs + 1) + q];
+                const uint32_t j1 = J[(size_t)i * (S.n_slabs + 1) + q + 1];
+                r[h] = j1 - j0;
+                m[h] = r[h] ? n - j0 : 0u;
+                src[h] = o + j0;
+                key[h] = 255u - min(r[h] / 2u + (m[h] - r[h]), 255u);   // the centre's longest row
+                any |= r[h];
+            }
         }
-        if (r) st32(kTlAny, 1u);
+        if (any) st32(kTlAny, 1u);
         if (tid < 256) st32(kTlKeys + 4u * tid, 0u);
         if (tid == 0) st32(kTlNext, 0u);
         __syncthreads();
         // a block with no rows in this slab (common for slabs at short
         // distances) skips the sort and the scans
         if (ld32(kTlAny) == 0u) continue;
-        const uint32_t rank = r ? fetch_inc32(kTlKeys + 4u * key) : 0u;
-        // candidate pairs of this item: r(r-1)/2 + r(m-r) per centre
-        const uint32_t inc = r ? r * (r - 1) / 2 + r * (m - r) : 0u;
+        uint32_t rank[kCentresPerThread], inc = 0u;
+#pragma unroll
+        for (int h = 0; h < kCentresPerThread; ++h) {
+            rank[h] = r[h] ? fetch_inc32(kTlKeys + 4u * key[h]) : 0u;
+            // candidate pairs of this item: r(r-1)/2 + r(m-r) per centre
+            inc += r[h] ? r[h] * (r[h] - 1) / 2 + r[h] * (m[h] - r[h]) : 0u;
+        }
         uint32_t rtot, itot, nne;
         (void)block_excl_scan_at(inc, kTlMisc, &itot);   // its barriers also order the ranks
         const uint32_t bc = tid < 256 ? ld32(kTlKeys + 4u * tid) : 0u;
         const uint32_t bstart = block_excl_scan_at(bc, kTlMisc, &nne);
         if (tid < 256) st32(kTlKeys + 4u * tid, bstart);
         __syncthreads();
-        if (r) {   // units: row pairs; m and r packed (both <= the list capacity < 2^16)
-            const uint32_t pos = ld32(kTlKeys + 4u * key) + rank;
-            st32(kSrc + 4u * pos, src);
-            st32(kM + 4u * pos, m | (r << 16));
-            st32(kRoff + 4u * pos, (r + 1u) >> 1);
-        }
+#pragma unroll
+        for (int h = 0; h < kCentresPerThread; ++h)
+            if (r[h]) {   // units: row pairs; m and r packed (both <= the list capacity < 2^16)
+                const uint32_t pos = ld32(kTlKeys + 4u * key[h]) + rank[h];
+                st32(kSrc + 4u * pos, src[h]);
+                st32(kM + 4u * pos, m[h] | (r[h] << 16));
+                st32(kRoff + 4u * pos, (r[h] + 1u) >> 1);
+            }
         const int nne_u = __builtin_amdgcn_readfirstlane((int)nne);
         __syncthreads();
-        const uint32_t rs = tid < nne_u ? ld32(kRoff + 4u * tid) : 0u;
-        const uint32_t rpre = block_excl_scan_at(rs, kTlMisc, &rtot);
+        // exclusive prefix of the units: thread tid takes compacted centres
+        // kCentresPerThread tid, kCentresPerThread tid + 1, ...
+        uint32_t rs[kCentresPerThread], rsum = 0u;
+#pragma unroll
+        for (int h = 0; h < kCentresPerThread; ++h) {
+            const int e = kCentresPerThread * tid + h;
+            rs[h] = e < nne_u ? ld32(kRoff + 4u * (uint32_t)e) : 0u;
+            rsum += rs[h];
+        }
+        uint32_t rpre = block_excl_scan_at(rsum, kTlMisc, &rtot);
         rtot = __builtin_amdgcn_readfirstlane(rtot);
-        if (tid < nne_u) st32(kRoff + 4u * tid, rpre);
+#pragma unroll
+        for (int h = 0; h < kCentresPerThread; ++h) {
+            const int e = kCentresPerThread * tid + h;
+            if (e < nne_u) st32(kRoff + 4u * (uint32_t)e, rpre);
+            rpre += rs[h];
+        }
         if (tid == 0) st32(kRoff + 4u * (uint32_t)nne_u, rtot);
         if (rtot == 0) {
             __syncthreads();
@@ -1006,9 +1040,16 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         // chunk table: the centre holding unit 64c, for the waves' first lanes
         const bool chunked = U <= 64u * (uint32_t)kChunkCap;
         __syncthreads();                       // roff complete
-        if (chunked && tid < nne_u) {
-            const uint32_t a = ld32(kRoff + 4u * tid) << pp, b = ld32(kRoff + 4u * tid + 4u) << pp;
-            for (uint32_t c = (a + 63u) >> 6; (c << 6) < b; ++c) st16(kChunkT + 2u * c, (uint32_t)tid);
+        if (chunked) {
+#pragma unroll
+            for (int h = 0; h < kCentresPerThread; ++h) {
+                const int e = kCentresPerThread * tid + h;
+                if (e < nne_u) {
+                    const uint32_t a = ld32(kRoff + 4u * (uint32_t)e) << pp;
+                    const uint32_t b = ld32(kRoff + 4u * (uint32_t)e + 4u) << pp;
+                    for (uint32_t c = (a + 63u) >> 6; (c << 6) < b; ++c) st16(kChunkT + 2u * c, (uint32_t)e);
+                }
+            }
         }
         __syncthreads();
 

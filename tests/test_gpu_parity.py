@@ -220,6 +220,42 @@ def test_tuning_does_not_change_results(g3mod, plan, torch_dev, oracle_mod, tun)
 
 
 @pytest.mark.parametrize("per_centre", [0, 1])
+@pytest.mark.parametrize("cb", [1024, 2048])
+def test_item_over_2_32_candidates(g3mod, plan, torch_dev, per_centre, cb):
+    """4000 atoms inside a 50-unit cube (rmax 5000, 10 bins): every side of
+    every triplet is in bin 0, so the half histogram is N (N-1) (N-2) / 2 at
+    bin 0 and zero elsewhere.  With 1024 or 2048 centres per item one item
+    holds more than 2^32 candidate pairs, all aimed at one LDS counter; the
+    kernel must split it into exact passes."""
+    rng = np.random.default_rng(3)
+    N = 4000
+    box = [200000, 200000, 200000]
+    fr = (100000 + rng.integers(0, 50, size=(1, 3, N))).astype(np.int32)
+    plan.set_tuning(centres_per_item=cb, per_centre=per_centre)
+    want = np.zeros(g3mod.hist_len(10, 0), np.uint64)
+    want[0] = N * (N - 1) * (N - 2) // 2
+    a, b = both(g3mod, plan, torch_dev, fr, box, 5000.0, 10, 0)
+    assert_same(a, want, "plain")
+    assert_same(b, want, "batched")
+
+
+@pytest.mark.parametrize("per_centre", [0, 1])
+def test_two_centres_per_thread_items(g3mod, plan, torch_dev, oracle_mod, per_centre):
+    """2048 centres per work item: each thread of the triplet workgroup sets
+    up two centres (3000 atoms, so both halves hold centres); both forms
+    equal the oracle."""
+    fr, box = synth.jittered_fcc(3000, 0.8, 0.1, 2, [41, 0])
+    rmax, nb = 2.5 * 4096, 40
+    plan.set_tuning(centres_per_item=2048, per_centre=per_centre)
+    assert plan.get_tuning()["centres_per_item"] == 2048
+    for layout in (0, 1):
+        want = oracle_mod.hist(fr, box, rmax, nb, layout)
+        a, b = both(g3mod, plan, torch_dev, fr, box, rmax, nb, layout)
+        assert_same(a, want, f"plain layout {layout}")
+        assert_same(b, want, f"batched layout {layout}")
+
+
+@pytest.mark.parametrize("per_centre", [0, 1])
 @pytest.mark.parametrize("layout", [0, 1])
 def test_atomic_flush_fallback(g3mod, plan, torch_dev, oracle_mod, per_centre, layout):
     """One partial slot per launch: nearly every slab flush takes the 64-bit
