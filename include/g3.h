@@ -153,8 +153,10 @@ g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_sys
  * nothing to hist or pair_hist), G3_ENOMEM if a centre exceeded the
  * per-centre neighbour capacity (its frame adds nothing to hist; its pairs
  * are still counted in pair_hist), G3_EDEVICE on a HIP error.  Frames whose
- * neighbour lists overflowed the batched scratch estimate are recomputed here
- * through the plain path before returning, so they are never lost. */
+ * neighbour lists overflowed the batched scratch estimate, or were too long
+ * for the tuning's work items to keep every 32-bit counter exact, are
+ * recomputed here through the plain path (with 512-centre items) before
+ * returning, so they are never lost or miscounted. */
 g3_status g3_sync(g3_plan p);
 
 /* Non-blocking: G3_OK if all work queued on the plan's stream has finished
