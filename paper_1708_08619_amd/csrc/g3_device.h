@@ -134,8 +134,8 @@ constexpr uint32_t kBuildChunk = 2048;
 constexpr int kStageCap = 768;       // stencil atoms staged in LDS per home cell
 inline int build_wgs_per_job(int n_jobs, int max_cells)
 {
-    // about 3 resident workgroups per CU on 256 CUs, all in one round
-    int per_job = 768 / (n_jobs > 0 ? n_jobs : 1);
+    // about 4 resident workgroups per CU on 256 CUs, all in one round
+    int per_job = 1024 / (n_jobs > 0 ? n_jobs : 1);
     if (per_job > max_cells) per_job = max_cells;
     return per_job < 1 ? 1 : per_job;
 }

@@ -228,8 +228,10 @@ constexpr int kWaveBufMax = kBufBytes / 8;
 constexpr int kSplitSlabs = 8;    // slabs up to which a short list is partitioned in registers
 constexpr uint32_t kChunk = kBuildChunk;
 
+// At most 64 VGPRs (8 waves per SIMD), so that four 8-wave workgroups share a
+// CU: the build is latency-bound, and its few spills sit outside the pass-1 loop.
 template <bool WIDE, bool ONE_STEP>
-__global__ void __launch_bounds__(kBuildThreads) k_nbr_build(const Sys* __restrict__ sys,
+__global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __restrict__ sys,
                                                              const Job* __restrict__ jobs)
 {
     using E = typename std::conditional<WIDE, int4, uint2>::type;
