@@ -56,6 +56,11 @@ struct Sys {
     int32_t one_step;        // 1: tab[s >> sh] is b(s) or b(s)-1
     const uint32_t* thr;     // device [nbins + 1]
     const uint8_t* tab;      // device [tab_len]
+    // step table (one read per bin): for s < R3 in cell q = s >> step_sh,
+    // b(s) = (step[q] + s) >> step_sh; null when no such table of at most
+    // kTabBytes / 4 cells exists
+    const uint32_t* step;    // device [step_len]
+    int32_t step_sh, step_bits, step_len;
     int32_t n_slabs;
     int32_t slab_lo[kMaxSlabs + 1];   // slab q holds rows lo in [slab_lo[q], slab_lo[q+1])
     int32_t list_cap;        // max neighbours per centre
@@ -148,7 +153,10 @@ void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n,
 size_t nbr_build_lds_bytes();
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
                       bool one_step, hipStream_t s);
-void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s);
+// Bin lookups of the triplet kernel: u8 table then threshold steps (loop or
+// one step), or the step table.
+enum Lookup : int { kLookupSteps = 0, kLookupOneStep = 1, kLookupStepTable = 2 };
+void launch_triplet(const TripletArgs& a, bool wide, int lookup, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
 void launch_expand(const Sys* sys, int n_sys, int max_nbins, hipStream_t s);
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes);

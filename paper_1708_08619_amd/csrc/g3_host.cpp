@@ -88,8 +88,10 @@ struct Geometry {
     int C = 0, C3 = 0;         // ceil of the pair cutoff; least C3 with C3^2 >= R3
     uint32_t R2 = 0, R3 = 0;   // thr[nbins], thr[nb3]
     int sh = 0, tab_len = 0, tab_bits = 0, one_step = 0;
+    int step_sh = 0, step_bits = 0, step_ok = 0;
     std::vector<uint32_t> thr;
     std::vector<uint8_t> tab;
+    std::vector<uint32_t> step;
     std::vector<int> slab_lo;  // n_slabs + 1 boundaries
 };
 
@@ -144,6 +146,45 @@ void plan_cells(Geometry& g)
     g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
 }
 
+// Step table: cells of 2^ssh values, the fewest that cover s < R3 in at most
+// kTabMax / 4 entries (a power of two of them).  Cell q (values from
+// v = q 2^ssh) has bin b_q = b(v) at its start and holds at most one
+// threshold strictly inside, at v + o_q (o_q = 2^ssh if none).  Its entry is
+// ((b_q + 1 - q) 2^ssh - o_q) mod 2^32, so that for s = v + u (u < 2^ssh)
+//     entry + s = b_q 2^ssh + (2^ssh - o_q + u),
+// whose bits from ssh up are b_q + [u >= o_q] = b(s): one table read and an
+// add, exact while (b_q + 2) 2^ssh < 2^32.  A cell with two inner thresholds
+// leaves no step table (the u8 table and threshold steps are used instead).
+void plan_step_table(Geometry& g)
+{
+    constexpr uint64_t kStepMax = (uint64_t)kTabMax / 4;
+    int ssh = 0;
+    while ((((uint64_t)g.R3 + ((1ull << ssh) - 1)) >> ssh) > kStepMax) ++ssh;
+    const uint64_t need = ((uint64_t)g.R3 + ((1ull << ssh) - 1)) >> ssh;
+    int bits = 0;
+    while ((1ull << bits) < need) ++bits;
+    const uint64_t w = 1ull << ssh;
+    g.step_ok = ((uint64_t)(g.nb3 + 1) << ssh) < (1ull << 32) ? 1 : 0;
+    g.step.assign((size_t)1 << bits, 0u);
+    int b = 0;
+    for (uint64_t q = 0; q < g.step.size(); ++q) {
+        const uint64_t v = q << ssh;
+        while (b + 1 < g.nb3 && v >= g.thr[b + 1]) ++b;
+        // thresholds thr[1 .. nb3-1] strictly inside the cell (thr[nb3] = R3
+        // only bounds accepted values)
+        uint64_t o = w;
+        int inner = 0;
+        for (int k = b + 1; k <= g.nb3 - 1 && g.thr[k] < v + w; ++k) {
+            if (inner++ == 0) o = g.thr[k] - v;
+        }
+        if (inner > 1) g.step_ok = 0;
+        g.step[q] = (uint32_t)(((int64_t)(b + 1) - (int64_t)q) * (int64_t)w - (int64_t)o);
+    }
+    g.step_sh = ssh;
+    g.step_bits = bits;
+    if (!g.step_ok) g.step.clear();
+}
+
 // Bin table: tab[q] = b(q << sh).  With 2^sh <= dr^2 no cell of width 2^sh
 // holds two thresholds, so one step up finishes the lookup; a coarser table
 // (to fit kTabMax bytes) only costs a few more steps.
@@ -171,7 +212,7 @@ void plan_bins(Geometry& g, double rmax)
     for (int q = 0; q < g.tab_len; ++q) {
         const uint64_t s = (uint64_t)q << sh;
         while (b + 1 < g.nb3 && s >= g.thr[b + 1]) ++b;
-        g.tab[q] = (uint8_t)b;
+        g.tab[q] = (uint8_t)std::min(b, 255);   // a lower bound past 255 bins
     }
     // one threshold step suffices iff no table cell holds two thresholds
     // strictly after its first value
@@ -179,6 +220,7 @@ void plan_bins(Geometry& g, double rmax)
     g.one_step = 1;
     for (int k = 1; k + 1 <= g.nb3 - 1; ++k)
         if ((g.thr[k] >> sh) == (g.thr[k + 1] >> sh) && (g.thr[k] & mask) != 0u) g.one_step = 0;
+    plan_step_table(g);
 }
 
 // r12 slabs: consecutive rows lo0..lo1-1, each held as an extended row of
@@ -347,7 +389,7 @@ struct Prepared {
     Geometry g;
     g3_system in;
     size_t off_cell_count, off_cell_start, off_atom_cell, off_atom_rank, off_sorted, off_nbr_off,
-        off_nbr_cnt, off_cursor, off_slab_j, off_pool, off_thr, off_tab;
+        off_nbr_cnt, off_cursor, off_slab_j, off_pool, off_thr, off_tab, off_step;
     size_t off_tri;          // triangle-once counts (half layout, uint64), if tri_once
     bool tri_once;
     int64_t pool_cap;
@@ -408,6 +450,7 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         P.off_slab_j = o;     o = align_up(o + F * N * (S + 1) * 2, 256);
         P.off_thr = o;        o = align_up(o + (g.nb3 + 1) * 4, 256);
         P.off_tab = o;        o = align_up(o + g.tab_len, 256);
+        P.off_step = o;       o = align_up(o + g.step.size() * 4, 256);
         if (!worst_case) {
             // expected neighbours of a uniform fluid, with headroom; a frame
             // that overflows is recomputed by g3_sync with the worst case
@@ -460,6 +503,13 @@ int32_t safe_list_len(int cb)
     return (int32_t)m;
 }
 
+// The triplet kernel's bin lookup for a system (a batch takes the weakest
+// of its systems').
+int lookup_of(const Geometry& g)
+{
+    return g.step_ok ? kLookupStepTable : g.one_step ? kLookupOneStep : kLookupSteps;
+}
+
 Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
 {
     Sys s;
@@ -487,6 +537,10 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
     s.one_step = g.one_step;
     s.thr = reinterpret_cast<const uint32_t*>(arena + P.off_thr);
     s.tab = reinterpret_cast<const uint8_t*>(arena + P.off_tab);
+    s.step = g.step_ok ? reinterpret_cast<const uint32_t*>(arena + P.off_step) : nullptr;
+    s.step_sh = g.step_sh;
+    s.step_bits = g.step_bits;
+    s.step_len = (int32_t)g.step.size();
     s.n_slabs = (int)g.slab_lo.size() - 1;
     for (size_t q = 0; q < g.slab_lo.size(); ++q) s.slab_lo[q] = g.slab_lo[q];
     s.list_cap = kListCap;
@@ -652,7 +706,9 @@ g3_status end_upload(g3_plan p)
 size_t geometry_bytes(const std::vector<Prepared>& ps)
 {
     size_t n = 0;
-    for (const auto& P : ps) n += align_up(P.g.thr.size() * 4, 64) + align_up(P.g.tab.size(), 64);
+    for (const auto& P : ps)
+        n += align_up(P.g.thr.size() * 4, 64) + align_up(P.g.tab.size(), 64) +
+             align_up(P.g.step.size() * 4, 64);
     return n;
 }
 
@@ -664,6 +720,10 @@ g3_status upload_geometry(g3_plan p, const std::vector<Prepared>& ps)
         if (st) return st;
         st = upload(p, A + P.off_tab, P.g.tab.data(), P.g.tab.size());
         if (st) return st;
+        if (!P.g.step.empty()) {
+            st = upload(p, A + P.off_step, P.g.step.data(), P.g.step.size() * 4);
+            if (st) return st;
+        }
     }
     return G3_OK;
 }
@@ -760,7 +820,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
         a.segs = dsegs + (size_t)f * S;
         hipEvent_t e0;
         timing_begin(p, &e0);
-        launch_triplet(a, P.g.wide != 0, P.g.one_step != 0, n_wg, p->stream);
+        launch_triplet(a, P.g.wide != 0, lookup_of(P.g), n_wg, p->stream);
         timing_end(p, e0);
         launch_reduce(a, tn.hb_max, S, p->stream);
         if (P.tri_once) launch_expand(dsys, 1, P.g.nbins, p->stream);
@@ -817,8 +877,12 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         for (auto& s : segs) max_hb = std::max(max_hb, s.hb);
         int max_cells = 0;
         for (auto& P : ps) max_cells = std::max(max_cells, P.g.ncell);
-        bool one_step = true;
-        for (auto& P : ps) one_step = one_step && P.g.one_step;
+        bool one_step = true, step_ok = true;
+        for (auto& P : ps) {
+            one_step = one_step && P.g.one_step;
+            step_ok = step_ok && P.g.step_ok;
+        }
+        const int lookup = step_ok ? kLookupStepTable : one_step ? kLookupOneStep : kLookupSteps;
         const int n_wg = p->n_cu * tn.wg_per_cu;
         const int max_slots = slot_count(n_wg, (int)segs.size(), tn.hb_max, tn.slot_limit);
         const size_t o_sys = 0, o_jobs = align_up(sizeof(Sys) * sys.size(), 256),
@@ -844,6 +908,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         auto put = [&](const void* d, size_t n) { key.append((const char*)d, n); };
         put(&wide, sizeof(wide));
         put(&one_step, sizeof(one_step));
+        put(&lookup, sizeof(lookup));
         // tuning fields one by one (the struct's padding bytes are undefined)
         const int32_t tk[5] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0, tn.slot_limit};
         put(tk, sizeof(tk));
@@ -899,7 +964,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_scan(dsys, djobs, nj, sm);
             launch_cell_scatter(dsys, djobs, nj, max_n, sm);
             launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, sm);
-            launch_triplet(a, wide, one_step, n_wg, sm);
+            launch_triplet(a, wide, lookup, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
             if (any_tri) launch_expand(dsys, n_sys, max_nb, sm);
         };
@@ -913,7 +978,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, p->stream);
             hipEvent_t e0;
             timing_begin(p, &e0);
-            launch_triplet(a, wide, one_step, n_wg, p->stream);
+            launch_triplet(a, wide, lookup, n_wg, p->stream);
             timing_end(p, e0);
             launch_reduce(a, max_hb, ns, p->stream);
             if (any_tri) launch_expand(dsys, n_sys, max_nb, p->stream);

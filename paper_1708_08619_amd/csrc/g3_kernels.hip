@@ -845,7 +845,7 @@ __device__ uint32_t block_excl_scan_at(uint32_t v, uint32_t tmp, uint32_t* total
 
 }  // namespace
 
-template <bool WIDE, bool ONE_STEP>
+template <bool WIDE, int LOOKUP>
 __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
 {
     using E = typename Ent<WIDE>::T;
@@ -924,7 +924,10 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             if (cur_seg >= 0 && pending) flush(cur_seg);
             if (G.sys != cur_sys) {
                 for (int x = tid; x <= S.nb3; x += kTripletThreads) st32(kTlThr + 4u * x, S.thr[x]);
-                for (int x = tid; x < S.tab_len; x += kTripletThreads) st8(kTlTab + x, S.tab[x]);
+                if constexpr (LOOKUP == kLookupStepTable)
+                    for (int x = tid; x < S.step_len; x += kTripletThreads) st32(kTlTab + 4u * x, S.step[x]);
+                else
+                    for (int x = tid; x < S.tab_len; x += kTripletThreads) st8(kTlTab + x, S.tab[x]);
                 cur_sys = G.sys;
             }
             zero_hist(G.hb);
@@ -1058,7 +1061,9 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         // the third side is accepted below R3 (R2 unless the third axis is
         // longer); C3 - 1 bounds its components
         const uint32_t R3 = S.R3, R3m1 = S.R3 - 1u;
-        const uint32_t sh = (uint32_t)S.sh, tbits = (uint32_t)S.tab_bits;
+        constexpr bool kStep = LOOKUP == kLookupStepTable;
+        const uint32_t sh = (uint32_t)(kStep ? S.step_sh : S.sh);
+        const uint32_t tbits = (uint32_t)(kStep ? S.step_bits : S.tab_bits);
         const int cm1 = S.C3 - 1;
         const int RL = G.rl, nb3 = S.nb3;
         const uint32_t trash = kTlTrash + 4u * (uint32_t)lane;
@@ -1134,7 +1139,11 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 // for a rejected candidate, whose increment goes to the trash
                 auto bin = [&](uint32_t s) -> uint32_t {
                     uint32_t c;
-                    if constexpr (ONE_STEP) {
+                    if constexpr (kStep) {
+                        // one read: the cell's entry carries its bin and the
+                        // offset of the threshold inside it
+                        c = (ld32(kTlTab + 4u * __builtin_amdgcn_ubfe(s, sh, tbits)) + s) >> sh;
+                    } else if constexpr (LOOKUP == kLookupOneStep) {
                         c = ld8(kTlTab + __builtin_amdgcn_ubfe(s, sh, tbits));
                         c += (s >= ld32(kTlThr + 4u + 4u * c)) ? 1u : 0u;
                     } else {
@@ -1383,8 +1392,9 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
 
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
 {
-    const void* trip[4] = {(const void*)k_triplet<false, false>, (const void*)k_triplet<false, true>,
-                           (const void*)k_triplet<true, false>, (const void*)k_triplet<true, true>};
+    const void* trip[6] = {(const void*)k_triplet<false, 0>, (const void*)k_triplet<false, 1>,
+                           (const void*)k_triplet<false, 2>, (const void*)k_triplet<true, 0>,
+                           (const void*)k_triplet<true, 1>, (const void*)k_triplet<true, 2>};
     hipError_t e;
     for (const void* k : trip) {
         // the triplet kernel addresses LDS from 0: it must have no static LDS
@@ -1402,19 +1412,18 @@ hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
     return hipSuccess;
 }
 
-void launch_triplet(const TripletArgs& a, bool wide, bool one_step, int n_wg, hipStream_t s)
+void launch_triplet(const TripletArgs& a, bool wide, int lookup, int n_wg, hipStream_t s)
 {
     const size_t lds = triplet_lds_bytes(a.hb_max, a.cb);
+    const dim3 g(n_wg), b(kTripletThreads);
     if (wide) {
-        if (one_step)
-            hipLaunchKernelGGL((k_triplet<true, true>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
-        else
-            hipLaunchKernelGGL((k_triplet<true, false>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+        if (lookup == kLookupStepTable) hipLaunchKernelGGL((k_triplet<true, 2>), g, b, lds, s, a);
+        else if (lookup == kLookupOneStep) hipLaunchKernelGGL((k_triplet<true, 1>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_triplet<true, 0>), g, b, lds, s, a);
     } else {
-        if (one_step)
-            hipLaunchKernelGGL((k_triplet<false, true>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
-        else
-            hipLaunchKernelGGL((k_triplet<false, false>), dim3(n_wg), dim3(kTripletThreads), lds, s, a);
+        if (lookup == kLookupStepTable) hipLaunchKernelGGL((k_triplet<false, 2>), g, b, lds, s, a);
+        else if (lookup == kLookupOneStep) hipLaunchKernelGGL((k_triplet<false, 1>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_triplet<false, 0>), g, b, lds, s, a);
     }
 }
 

@@ -1,0 +1,59 @@
+// Host-side check of the bin lookup tables built by the runtime (compiled
+// with the runtime's source and stub launchers; no GPU).  For every value
+// s < R3 of each geometry below, against b(s) = the largest b < nb3 with
+// thr[b] <= s:
+//   * the u8 table gives a lower bound, within one step when one_step is set;
+//   * the step table, when built, gives b(s) exactly.
+// Exit status: the number of geometries with a failure.
+#include "../paper_1708_08619_amd/csrc/g3_host.cpp"
+
+namespace g3 {
+void launch_zero_u32(uint32_t*, size_t, hipStream_t) {}
+void launch_cell_count(const Sys*, const Job*, int, int, hipStream_t) {}
+void launch_cell_scan(const Sys*, const Job*, int, hipStream_t) {}
+void launch_cell_scatter(const Sys*, const Job*, int, int, hipStream_t) {}
+size_t nbr_build_lds_bytes() { return 0; }
+void launch_nbr_build(const Sys*, const Job*, int, int, bool, bool, hipStream_t) {}
+void launch_triplet(const TripletArgs&, bool, int, int, hipStream_t) {}
+void launch_reduce(const TripletArgs&, int, int, hipStream_t) {}
+void launch_expand(const Sys*, int, int, hipStream_t) {}
+hipError_t set_kernel_lds_limits(size_t, size_t) { return hipSuccess; }
+}  // namespace g3
+
+int main()
+{
+    // rmax in coordinate units, pair bins, third-side bins
+    struct Case { double rmax; int nb, nb3; } cases[] = {
+        {3.0 * 4096, 60, 60},   {2.5 * 4096, 50, 50},   {2.0 * 4096, 40, 40},
+        {0.6 * 65536, 60, 60},  {7.0, 7, 7},            {1000.5, 13, 26},
+        {3.0 * 4096, 60, 120},  {23170.0, 160, 160},    {100.0, 1, 1},
+        {1.0, 1, 2},            {33.3, 30, 30},         {12345.678, 77, 77},
+        {40000.0, 45, 90},      {5000.0, 150, 300},     {2.5 * 4096, 50, 100}};
+    int failed = 0, with_step = 0;
+    for (const Case& c : cases) {
+        Geometry g;
+        g.nbins = c.nb;
+        g.nb3 = c.nb3;
+        plan_bins(g, c.rmax);
+        uint64_t bad_tab = 0, bad_step = 0;
+        int b = 0;
+        const uint32_t qmask = (1u << g.step_bits) - 1u;
+        for (uint64_t s = 0; s < g.R3; ++s) {
+            while (b + 1 < g.nb3 && s >= g.thr[b + 1]) ++b;
+            const int t = g.tab[(size_t)(s >> g.sh)];
+            if (t > b || (g.one_step && b - t > 1)) ++bad_tab;
+            if (g.step_ok) {
+                const uint32_t e = g.step[(uint32_t)(s >> g.step_sh) & qmask];
+                if (((e + (uint32_t)s) >> g.step_sh) != (uint32_t)b) ++bad_step;
+            }
+        }
+        with_step += g.step_ok;
+        std::printf("rmax %.3f nbins %d nb3 %d: R3 %u one_step %d step_table %d (%zu cells of 2^%d) "
+                    "bad %llu %llu\n", c.rmax, c.nb, c.nb3, g.R3, g.one_step, g.step_ok, g.step.size(),
+                    g.step_sh, (unsigned long long)bad_tab, (unsigned long long)bad_step);
+        failed += (bad_tab || bad_step) ? 1 : 0;
+    }
+    // the benchmark-like geometries must get the step table
+    if (with_step < 8) ++failed;
+    return failed;
+}
