@@ -1121,8 +1121,11 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 // with RL = (nb - lo0) nb3; entries carry b nb3, and
                 // (b_j - lo0) RL = (b_j nb3)(nb - lo0) - lo0 RL
                 const int colj = Ent<WIDE>::col(vj);
-                const uint32_t rowbase =
+                uint32_t rowbase =
                     kTlHist + 4u * (uint32_t)(__mul24(colj, nb - lo0) - lo0 * RL - lo0 * nb3);
+                // one opaque value: the address below is then (col + c) << 2
+                // plus rowbase, col read from the entry's high half in place
+                asm volatile("" : "+v"(rowbase));
                 uint32_t jx, jy = 0, jz;
                 if constexpr (WIDE) {
                     jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
