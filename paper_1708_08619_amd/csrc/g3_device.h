@@ -14,6 +14,11 @@ constexpr int kThrMax = 512;           // threshold table entries (third-side bi
 constexpr int kTripletThreads = 1024;  // threads of the triplet workgroup
 constexpr int kCentresPerThread = 2;   // centres a triplet thread sets up per item
 constexpr int kListCap = 4096;         // neighbours per centre held by the triplet kernel
+// Entries written after every non-empty list: never accepted as a neighbour
+// of any row (narrow: components -32768, when the geometry guarantees it;
+// wide: 2^30), so the triplet kernel may evaluate a run's last group of 4
+// past the list's end instead of a remainder loop.
+constexpr int kListPad = 3;
 // Centres per triplet pass whose candidate pairs stay below 2^32 whatever the
 // lists (each centre has at most kListCap (kListCap - 1) / 2 in a slab).
 constexpr int kSafeItemCentres = 512;
@@ -64,6 +69,7 @@ struct Sys {
     int32_t n_slabs;
     int32_t slab_lo[kMaxSlabs + 1];   // slab q holds rows lo in [slab_lo[q], slab_lo[q+1])
     int32_t list_cap;        // max neighbours per centre
+    int32_t pad_ok;          // the pad entries are rejected by every row
     int32_t m_safe;          // longest list for which an item's candidate pairs stay below 2^32
     // scratch (frame f uses base + f * stride; stride 0 = reused every frame)
     int32_t* cell_count;     // [ncell]        stride ncell*cell_mul
@@ -156,7 +162,7 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
 // Bin lookups of the triplet kernel: u8 table then threshold steps (loop or
 // one step), or the step table.
 enum Lookup : int { kLookupSteps = 0, kLookupOneStep = 1, kLookupStepTable = 2 };
-void launch_triplet(const TripletArgs& a, bool wide, int lookup, int n_wg, hipStream_t s);
+void launch_triplet(const TripletArgs& a, bool wide, int lookup, bool padded, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
 void launch_expand(const Sys* sys, int n_sys, int max_nbins, hipStream_t s);
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes);

@@ -457,10 +457,10 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
             const double V = (double)g.box[0] * g.box[1] * g.box[2];
             const double rc = (double)P.in.rmax;
             const double nexp = (double)g.N / V * 4.18879020478639 * rc * rc * rc;
-            int64_t cap = (int64_t)(N * (1.35 * std::min(nexp, (double)N) + 16.0)) + 4096 + slack;
-            P.pool_cap = std::min<int64_t>(cap, (int64_t)N * std::min<int64_t>(kListCap, N) + slack);
+            int64_t cap = (int64_t)(N * (1.35 * std::min(nexp, (double)N) + 16.0 + kListPad)) + 4096 + slack;
+            P.pool_cap = std::min<int64_t>(cap, (int64_t)N * (std::min<int64_t>(kListCap, N) + kListPad) + slack);
         } else {
-            P.pool_cap = (int64_t)N * std::min<int64_t>(kListCap, std::max<int64_t>(N, 1)) + slack;
+            P.pool_cap = (int64_t)N * (std::min<int64_t>(kListCap, std::max<int64_t>(N, 1)) + kListPad) + slack;
         }
         P.off_pool = o;
         // byte offsets inside a slot must fit 32 bits
@@ -510,6 +510,19 @@ int lookup_of(const Geometry& g)
     return g.step_ok ? kLookupStepTable : g.one_step ? kLookupOneStep : kLookupSteps;
 }
 
+// Whether every row rejects the pad entries after the lists.  Narrow: a row's
+// components are at most C - 1 in size, so each saturated difference with
+// -32768 is at least 32769 - C and the clamped squared length at least
+// min(3 (32769 - C)^2, 2^31 - 1), which must reach R3.  Wide: the component
+// pre-test rejects 2^30 (coordinates differ by less than 2^17).
+bool pads_rejected(const Geometry& g)
+{
+    if (g.wide) return true;
+    const uint64_t d = (uint64_t)(32769 - (int64_t)g.C);
+    const uint64_t s = std::min<uint64_t>(3ull * d * d, 0x7fffffffull);
+    return s >= (uint64_t)g.R3;
+}
+
 Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
 {
     Sys s;
@@ -544,6 +557,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
     s.n_slabs = (int)g.slab_lo.size() - 1;
     for (size_t q = 0; q < g.slab_lo.size(); ++q) s.slab_lo[q] = g.slab_lo[q];
     s.list_cap = kListCap;
+    s.pad_ok = pads_rejected(g) ? 1 : 0;
     s.m_safe = safe_list_len(cb);
     s.cell_count = reinterpret_cast<int32_t*>(arena + P.off_cell_count);
     s.cell_start = reinterpret_cast<int32_t*>(arena + P.off_cell_start);
@@ -820,7 +834,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
         a.segs = dsegs + (size_t)f * S;
         hipEvent_t e0;
         timing_begin(p, &e0);
-        launch_triplet(a, P.g.wide != 0, lookup_of(P.g), n_wg, p->stream);
+        launch_triplet(a, P.g.wide != 0, lookup_of(P.g), pads_rejected(P.g), n_wg, p->stream);
         timing_end(p, e0);
         launch_reduce(a, tn.hb_max, S, p->stream);
         if (P.tri_once) launch_expand(dsys, 1, P.g.nbins, p->stream);
@@ -877,10 +891,11 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         for (auto& s : segs) max_hb = std::max(max_hb, s.hb);
         int max_cells = 0;
         for (auto& P : ps) max_cells = std::max(max_cells, P.g.ncell);
-        bool one_step = true, step_ok = true;
+        bool one_step = true, step_ok = true, padded = true;
         for (auto& P : ps) {
             one_step = one_step && P.g.one_step;
             step_ok = step_ok && P.g.step_ok;
+            padded = padded && pads_rejected(P.g);
         }
         const int lookup = step_ok ? kLookupStepTable : one_step ? kLookupOneStep : kLookupSteps;
         const int n_wg = p->n_cu * tn.wg_per_cu;
@@ -909,6 +924,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         put(&wide, sizeof(wide));
         put(&one_step, sizeof(one_step));
         put(&lookup, sizeof(lookup));
+        put(&padded, sizeof(padded));
         // tuning fields one by one (the struct's padding bytes are undefined)
         const int32_t tk[5] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0, tn.slot_limit};
         put(tk, sizeof(tk));
@@ -964,7 +980,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_scan(dsys, djobs, nj, sm);
             launch_cell_scatter(dsys, djobs, nj, max_n, sm);
             launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, sm);
-            launch_triplet(a, wide, lookup, n_wg, sm);
+            launch_triplet(a, wide, lookup, padded, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
             if (any_tri) launch_expand(dsys, n_sys, max_nb, sm);
         };
@@ -978,7 +994,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, p->stream);
             hipEvent_t e0;
             timing_begin(p, &e0);
-            launch_triplet(a, wide, lookup, n_wg, p->stream);
+            launch_triplet(a, wide, lookup, padded, n_wg, p->stream);
             timing_end(p, e0);
             launch_reduce(a, max_hb, ns, p->stream);
             if (any_tri) launch_expand(dsys, n_sys, max_nb, p->stream);

@@ -81,6 +81,28 @@ __global__ void k_zero_u32(uint32_t* p, size_t n)
         p[i] = 0u;
 }
 
+// Global-memory pointers.  Pointers read from a table (Sys) are generic, and
+// generic accesses compile to flat instructions, which also count against the
+// LDS wait counter: an LDS wait then waits for outstanding global loads and
+// stores too.  Casting to the global address space gives global instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gp(T* p)
+{
+    return (gptr<T>)p;
+}
+// (HIP's vector types assign through generic references only)
+__device__ __forceinline__ void gstore(gptr<uint2> p, uint2 v)
+{
+    *(gptr<unsigned long long>)p = (unsigned long long)v.x | ((unsigned long long)v.y << 32);
+}
+__device__ __forceinline__ void gstore(gptr<int4> p, int4 v)
+{
+    typedef int int4v __attribute__((ext_vector_type(4)));
+    *(gptr<int4v>)p = int4v{v.x, v.y, v.z, v.w};
+}
+
 // ------------------------------------------------------------------ cell build
 // Validate coordinates, count atoms per cell and remember each atom's rank
 // inside its cell (the atomic's return value).
@@ -252,14 +274,14 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
     const Job jb = jobs[blockIdx.y];
     const Sys& S = sys[jb.sys];
     const int f = jb.frame, N = S.N;
-    if (S.flags[f] & kFlagDomain) return;
+    if (gp(S.flags)[f] & kFlagDomain) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ncx = S.nc[0], ncy = S.nc[1], ncz = S.nc[2], ncell = S.ncell;
     const int Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
-    const int32_t* cs = S.cell_start + fr_off(S, f, ncell + 1);
-    const int32_t* X = S.sorted + fr_off(S, f, (size_t)3 * N);
-    const int32_t* Y = X + N;
-    const int32_t* Z = Y + N;
+    const gptr<const int32_t> cs = gp(S.cell_start + fr_off(S, f, ncell + 1));
+    const gptr<const int32_t> X = gp(S.sorted + fr_off(S, f, (size_t)3 * N));
+    const gptr<const int32_t> Y = X + N;
+    const gptr<const int32_t> Z = Y + N;
     const int cm1 = S.C - 1;
     const uint32_t span = 2u * (uint32_t)cm1;
     const uint32_t R2 = S.R2;
@@ -269,22 +291,22 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
     uint32_t* scnt = s_scnt + wave * 64;
     E* buf = s_buf + wave * kWaveBuf;
     uint32_t* idx = s_idx + wave * kWaveBufMax;   // per buffered entry: candidate, then slab
-    uint32_t* flags = S.flags + f;
-    uint32_t* cursor = S.cursor + (size_t)f * kCursorStride;
+    const gptr<uint32_t> flags = gp(S.flags + f);
+    const gptr<uint32_t> cursor = gp(S.cursor + (size_t)f * kCursorStride);
     uint32_t chunk_base = 0, chunk_left = 0;   // this wave's slice of the pool
-    uint32_t* nbr_off = S.nbr_off + fr_off(S, f, N);
-    uint32_t* nbr_cnt = S.nbr_cnt + fr_off(S, f, N);
-    uint16_t* slab_j = S.slab_j + fr_off(S, f, (size_t)N * (n_slabs + 1));
+    const gptr<uint32_t> nbr_off = gp(S.nbr_off + fr_off(S, f, N));
+    const gptr<uint32_t> nbr_cnt = gp(S.nbr_cnt + fr_off(S, f, N));
+    const gptr<uint16_t> slab_j = gp(S.slab_j + fr_off(S, f, (size_t)N * (n_slabs + 1)));
     const size_t pbase = S.per_frame ? (size_t)f * (size_t)(pool_cap + kPoolPad) : 0;
-    E* pool = reinterpret_cast<E*>(S.pool) + pbase;
+    const gptr<E> pool = gp(reinterpret_cast<E*>(S.pool) + pbase);
 
     // bin tables and the bin -> slab map, once per workgroup
     const int nb3 = S.nb3;
-    for (int x = tid; x <= nb3; x += kBuildThreads) s_thr[x] = S.thr[x];
+    for (int x = tid; x <= nb3; x += kBuildThreads) s_thr[x] = gp(S.thr)[x];
     {
-        const int n16 = (S.tab_len + 15) / 16;
-        const uint4* src = reinterpret_cast<const uint4*>(S.tab);
-        for (int x = tid; x < n16; x += kBuildThreads) reinterpret_cast<uint4*>(s_tab)[x] = src[x];
+        const int n4 = (S.tab_len + 3) / 4;
+        const gptr<const uint32_t> src = gp(reinterpret_cast<const uint32_t*>(S.tab));
+        for (int x = tid; x < n4; x += kBuildThreads) reinterpret_cast<uint32_t*>(s_tab)[x] = src[x];
     }
     for (int b = tid; b < 256; b += kBuildThreads) {
         int q = 0;
@@ -304,7 +326,8 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
         for (int b = tid; b < nb; b += kBuildThreads) {
             const uint32_t v = s_g2[b];
             if (v) {
-                atomicAdd(reinterpret_cast<unsigned long long*>(pair_hist + b), (unsigned long long)v);
+                __hip_atomic_fetch_add(gp(reinterpret_cast<unsigned long long*>(pair_hist + b)),
+                                       (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 s_g2[b] = 0u;
             }
         }
@@ -464,6 +487,11 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
                 }
                 return b;
             };
+            // entry after every list that no row accepts (see kListPad)
+            auto pad_entry = [&]() -> E {
+                if constexpr (WIDE) return make_int4(1 << 30, 1 << 30, 1 << 30, 0);
+                else return make_uint2(0x80008000u, 0x00008000u);
+            };
             auto pack = [&](int dx, int dy, int dz, int bn) -> E {
                 if constexpr (WIDE) {
                     return make_int4(dx, dy, dz, bn);
@@ -556,7 +584,8 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
             // a list longer than m_safe could take an item of the triplet
             // kernel past 2^32 candidate pairs: the frame is recomputed
             // with smaller items (its lists and pairs are still built here)
-            if (n > (uint32_t)S.m_safe && lane == 0) atomicOr(flags, kFlagDense);
+            if (n > (uint32_t)S.m_safe && lane == 0)
+                __hip_atomic_fetch_or(flags, kFlagDense, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const bool in_regs = split && n <= 64u;
             const bool buffered = n <= (uint32_t)kWaveBuf;
             if (!in_regs && !buffered) {
@@ -575,30 +604,37 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
             // a centre over the list capacity has its pairs counted, no list
             if (n > (uint32_t)list_cap) {
                 if (lane == 0) {
-                    atomicOr(flags, kFlagList);
+                    __hip_atomic_fetch_or(flags, kFlagList, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     nbr_off[ci] = 0u;
                     nbr_cnt[ci] = 0u;
                 }
                 continue;
             }
-            // bump-allocate from the wave's chunk; one global atomic per chunk
-            if (n > chunk_left) {
-                const uint32_t want = n > kChunk ? n : kChunk;
+            // bump-allocate from the wave's chunk (the list and its pad
+            // entries); one global atomic per chunk
+            const uint32_t nres = n ? n + (uint32_t)kListPad : 0u;
+            if (nres > chunk_left) {
+                const uint32_t want = nres > kChunk ? nres : kChunk;
                 uint32_t got = 0;
-                if (lane == 0) got = atomicAdd(cursor, want);
+                if (lane == 0) got = __hip_atomic_fetch_add(cursor, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 chunk_base = __shfl(got, 0, 64);
                 chunk_left = want;
             }
             const uint32_t base = chunk_base;
-            chunk_base += n;
-            chunk_left -= n;
-            if ((int64_t)base + n > pool_cap) {
-                if (lane == 0) atomicOr(flags, kFlagPool);
+            chunk_base += nres;
+            chunk_left -= nres;
+            if ((int64_t)base + nres > pool_cap) {
+                if (lane == 0) __hip_atomic_fetch_or(flags, kFlagPool, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 continue;
             }
             if (in_regs) {
                 if (lane <= n_slabs) slab_j[(size_t)ci * (n_slabs + 1) + lane] = (uint16_t)jlane;
-                if ((uint32_t)lane < n) pool[base + epos] = ent;
+                // entries and (one store) the pads that fit in the wave's lanes
+                if (n && (uint32_t)lane < n + (uint32_t)kListPad)
+                    gstore(pool + (base + ((uint32_t)lane < n ? epos : (uint32_t)lane)),
+                           (uint32_t)lane < n ? ent : pad_entry());
+                if (n + (uint32_t)kListPad > 64u && (uint32_t)lane < n + (uint32_t)kListPad - 64u)
+                    gstore(pool + (base + 64u + lane), pad_entry());
                 if (lane == 0) {
                     nbr_off[ci] = base;
                     nbr_cnt[ci] = n;
@@ -621,10 +657,11 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
                 wave_sync();
             }
             // Pass 3: each entry at J_{slab} + its rank in the slab
-            E* P = pool + base;
+            const gptr<E> P = pool + base;
+            if (n && lane < kListPad) gstore(P + (n + lane), pad_entry());
             if (buffered) {
                 for (uint32_t e = lane; e < n; e += 64) {
-                    P[atomicAdd(&scnt[idx[e]], 1u)] = buf[e];
+                    gstore(P + atomicAdd(&scnt[idx[e]], 1u), buf[e]);
                 }
             } else {
                 for (int t0 = t_first; t0 < T; t0 += 64) {
@@ -632,7 +669,7 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
                     uint32_t s;
                     if (sep(std::false_type{}, t0 + lane, dx, dy, dz, s)) {
                         const int b = bin_of(s);
-                        P[atomicAdd(&scnt[s_slab[b]], 1u)] = pack(dx, dy, dz, __mul24(b, nb3));
+                        gstore(P + atomicAdd(&scnt[s_slab[b]], 1u), pack(dx, dy, dz, __mul24(b, nb3)));
                     }
                 }
             }
@@ -845,7 +882,7 @@ __device__ uint32_t block_excl_scan_at(uint32_t v, uint32_t tmp, uint32_t* total
 
 }  // namespace
 
-template <bool WIDE, int LOOKUP>
+template <bool WIDE, int LOOKUP, bool PADDED>
 __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
 {
     using E = typename Ent<WIDE>::T;
@@ -863,11 +900,13 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
     auto flush = [&](int seg) {
         const Seg& G = A.segs[seg];
         __syncthreads();
-        if (tid == 0) st32(kTlSlot, atomicAdd(&A.ctl->slots_used, 1u));
+        if (tid == 0)
+            st32(kTlSlot, __hip_atomic_fetch_add(gp(&A.ctl->slots_used), 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT));
         __syncthreads();
         const uint32_t slot = ld32(kTlSlot);
         if (slot < (uint32_t)A.max_slots) {
-            uint32_t* dst = A.slots + (size_t)slot * A.hb_max;
+            const gptr<uint32_t> dst = gp(A.slots + (size_t)slot * A.hb_max);
             for (int x = tid; x < G.hb; x += kTripletThreads) dst[x] = ld32(kTlHist + 4u * x);
             if (tid == 0) A.slot_seg[slot] = seg;
         } else {
@@ -908,7 +947,8 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
 
     for (;;) {
         if (tid == 0) {
-            st32(kTlItem, atomicAdd(&A.ctl->next_item, 1u));
+            st32(kTlItem, __hip_atomic_fetch_add(gp(&A.ctl->next_item), 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT));
             st32(kTlAny, 0u);
         }
         __syncthreads();
@@ -923,11 +963,11 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             // (nothing added since the slab was zeroed: nothing to flush)
             if (cur_seg >= 0 && pending) flush(cur_seg);
             if (G.sys != cur_sys) {
-                for (int x = tid; x <= S.nb3; x += kTripletThreads) st32(kTlThr + 4u * x, S.thr[x]);
+                for (int x = tid; x <= S.nb3; x += kTripletThreads) st32(kTlThr + 4u * x, gp(S.thr)[x]);
                 if constexpr (LOOKUP == kLookupStepTable)
-                    for (int x = tid; x < S.step_len; x += kTripletThreads) st32(kTlTab + 4u * x, S.step[x]);
+                    for (int x = tid; x < S.step_len; x += kTripletThreads) st32(kTlTab + 4u * x, gp(S.step)[x]);
                 else
-                    for (int x = tid; x < S.tab_len; x += kTripletThreads) st8(kTlTab + x, S.tab[x]);
+                    for (int x = tid; x < S.tab_len; x += kTripletThreads) st8(kTlTab + x, gp(S.tab)[x]);
                 cur_sys = G.sys;
             }
             zero_hist(G.hb);
@@ -938,13 +978,13 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         const int local = item - G.item_begin;
         const int f = G.frame0 + local / G.n_blocks;
         const int blk = local - (local / G.n_blocks) * G.n_blocks;
-        if (S.flags[f] != 0u) continue;
+        if (gp(S.flags)[f] != 0u) continue;
         const int N = S.N, q = G.slab, nb = S.nbins, lo0 = G.lo0;
         const int c_begin = blk * A.cb;
         const int nctr = min(A.cb, N - c_begin);
-        const uint32_t* off = S.nbr_off + (S.per_frame ? (size_t)f * N : 0);
-        const uint32_t* cnt = S.nbr_cnt + (S.per_frame ? (size_t)f * N : 0);
-        const uint16_t* J = S.slab_j + (S.per_frame ? (size_t)f * N * (S.n_slabs + 1) : 0);
+        const gptr<const uint32_t> off = gp(S.nbr_off + (S.per_frame ? (size_t)f * N : 0));
+        const gptr<const uint32_t> cnt = gp(S.nbr_cnt + (S.per_frame ? (size_t)f * N : 0));
+        const gptr<const uint16_t> J = gp(S.slab_j + (S.per_frame ? (size_t)f * N * (S.n_slabs + 1) : 0));
         const size_t pbase = S.per_frame ? (size_t)f * (size_t)(S.pool_cap + kPoolPad) : 0;
         const GEnt<WIDE> pool{reinterpret_cast<const char*>(S.pool) + pbase * sizeof(E)};
         constexpr uint32_t ES = GEnt<WIDE>::kSize;
@@ -1112,8 +1152,6 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             const int jA = jp, jB = rr - 1 - jp;
             const int LA = mm - 1 - jA;
             const int LB = jB > jA ? mm - 1 - jB : 0;
-            const int Lt = LA + LB;
-            const int u0 = __mul24(p, Lt) >> pp, u1 = __mul24(p + 1, Lt) >> pp;
             // row j against candidates [k, kend); vj is entry j and ga holds
             // entries [k, k+4) (loaded by the caller, possibly ahead of time)
             auto run = [&](const E vj, E (&ga)[4], int k, int kend) {
@@ -1199,6 +1237,96 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 }
                 for (; k < kend; ++k, ko += ES) eval1(pool.load(ko));
             };
+            // Padded lists: whole groups of 4 only.  [k, kend) spans a whole
+            // number of groups; a run's last group may reach up to 3 entries
+            // past the list, into its pad entries, which every row rejects.
+            // The next group's loads may read 3 entries further (into the
+            // next list or the pool slot's padding); they are never evaluated.
+            auto run4 = [&](const E vj, E (&ga)[4], int k, int kend) {
+                const int colj = Ent<WIDE>::col(vj);
+                uint32_t rowbase =
+                    kTlHist + 4u * (uint32_t)(__mul24(colj, nb - lo0) - lo0 * RL - lo0 * nb3);
+                asm volatile("" : "+v"(rowbase));
+                uint32_t jx, jy = 0, jz;
+                if constexpr (WIDE) {
+                    jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
+                } else {
+                    jx = vj.x; jz = vj.y & 0xffffu;
+                }
+                auto d2 = [&](const E& vk) -> uint32_t {
+                    if constexpr (WIDE)
+                        return Ent<true>::dist2(vk, (int)jx, (int)jy, (int)jz, cm1);
+                    else
+                        return Ent<false>::dist2(vk, jx, jz, 0);
+                };
+                auto bin = [&](uint32_t s) -> uint32_t {
+                    uint32_t c;
+                    if constexpr (kStep) {
+                        c = (ld32(kTlTab + 4u * __builtin_amdgcn_ubfe(s, sh, tbits)) + s) >> sh;
+                    } else if constexpr (LOOKUP == kLookupOneStep) {
+                        c = ld8(kTlTab + __builtin_amdgcn_ubfe(s, sh, tbits));
+                        c += (s >= ld32(kTlThr + 4u + 4u * c)) ? 1u : 0u;
+                    } else {
+                        const uint32_t sc = min(s, R3m1);
+                        c = ld8(kTlTab + (sc >> sh));
+                        while (sc >= ld32(kTlThr + 4u + 4u * c)) ++c;
+                    }
+                    return c;
+                };
+                auto evalg = [&](const E* v) {
+                    uint32_t s[4], a[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) s[u] = d2(v[u]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        a[u] = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v[u]) + bin(s[u]));
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) asm volatile("" : "+v"(a[u]));
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) inc32(s[u] < R3 ? a[u] : trash);
+                };
+                uint32_t ko = eoff + (uint32_t)k * ES;
+                E gb[4];
+                for (; k + 4 < kend; k += 8, ko += 8 * ES) {   // two groups left at least
+                    pool.load4(ko + 4 * ES, gb);
+                    evalg(ga);
+                    pool.load4(ko + 8 * ES, ga);
+                    evalg(gb);
+                }
+                if (k < kend) evalg(ga);
+            };
+            if constexpr (PADDED) {
+                // the unit as groups of 4: gA of row jA, then gB of row jB;
+                // part p takes groups [g0, g1)
+                const int gA = (LA + 3) >> 2, gB = (LB + 3) >> 2, Gt = gA + gB;
+                const int g0 = __mul24(p, Gt) >> pp, g1 = __mul24(p + 1, Gt) >> pp;
+                const bool hasA = g0 < gA, hasB = g1 > gA;
+                const int kA = jA + 1 + 4 * g0, kB = jB + 1 + 4 * (max(g0, gA) - gA);
+                E vA{}, gAv[4];
+                if (hasA) {
+                    vA = pool.load(eoff + (uint32_t)jA * ES);
+                    pool.load4(eoff + (uint32_t)kA * ES, gAv);
+                }
+                if constexpr (!WIDE) {
+                    E vB{}, gBv[4];
+                    if (hasB) {
+                        vB = pool.load(eoff + (uint32_t)jB * ES);
+                        pool.load4(eoff + (uint32_t)kB * ES, gBv);
+                    }
+                    if (hasA) run4(vA, gAv, kA, jA + 1 + 4 * min(g1, gA));
+                    if (hasB) run4(vB, gBv, kB, jB + 1 + 4 * (g1 - gA));
+                } else {
+                    if (hasA) run4(vA, gAv, kA, jA + 1 + 4 * min(g1, gA));
+                    if (hasB) {
+                        E vB = pool.load(eoff + (uint32_t)jB * ES), gBv[4];
+                        pool.load4(eoff + (uint32_t)kB * ES, gBv);
+                        run4(vB, gBv, kB, jB + 1 + 4 * (g1 - gA));
+                    }
+                }
+                continue;
+            }
+            const int Lt = LA + LB;
+            const int u0 = __mul24(p, Lt) >> pp, u1 = __mul24(p + 1, Lt) >> pp;
             // Both runs' row entries and first groups are loaded before run A
             // starts, so run B begins without a memory round trip (the wide
             // form, short of registers, loads run B's when it starts).  A
@@ -1395,9 +1523,12 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
 
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
 {
-    const void* trip[6] = {(const void*)k_triplet<false, 0>, (const void*)k_triplet<false, 1>,
-                           (const void*)k_triplet<false, 2>, (const void*)k_triplet<true, 0>,
-                           (const void*)k_triplet<true, 1>, (const void*)k_triplet<true, 2>};
+    const void* trip[9] = {
+        (const void*)k_triplet<false, 0, false>, (const void*)k_triplet<false, 1, false>,
+        (const void*)k_triplet<false, 2, false>, (const void*)k_triplet<false, 0, true>,
+        (const void*)k_triplet<false, 1, true>,  (const void*)k_triplet<false, 2, true>,
+        (const void*)k_triplet<true, 0, true>,   (const void*)k_triplet<true, 1, true>,
+        (const void*)k_triplet<true, 2, true>};
     hipError_t e;
     for (const void* k : trip) {
         // the triplet kernel addresses LDS from 0: it must have no static LDS
@@ -1415,18 +1546,23 @@ hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
     return hipSuccess;
 }
 
-void launch_triplet(const TripletArgs& a, bool wide, int lookup, int n_wg, hipStream_t s)
+void launch_triplet(const TripletArgs& a, bool wide, int lookup, bool padded, int n_wg, hipStream_t s)
 {
     const size_t lds = triplet_lds_bytes(a.hb_max, a.cb);
     const dim3 g(n_wg), b(kTripletThreads);
+    // wide pad entries are always rejected: the wide form always runs padded
     if (wide) {
-        if (lookup == kLookupStepTable) hipLaunchKernelGGL((k_triplet<true, 2>), g, b, lds, s, a);
-        else if (lookup == kLookupOneStep) hipLaunchKernelGGL((k_triplet<true, 1>), g, b, lds, s, a);
-        else hipLaunchKernelGGL((k_triplet<true, 0>), g, b, lds, s, a);
+        if (lookup == kLookupStepTable) hipLaunchKernelGGL((k_triplet<true, 2, true>), g, b, lds, s, a);
+        else if (lookup == kLookupOneStep) hipLaunchKernelGGL((k_triplet<true, 1, true>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_triplet<true, 0, true>), g, b, lds, s, a);
+    } else if (padded) {
+        if (lookup == kLookupStepTable) hipLaunchKernelGGL((k_triplet<false, 2, true>), g, b, lds, s, a);
+        else if (lookup == kLookupOneStep) hipLaunchKernelGGL((k_triplet<false, 1, true>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_triplet<false, 0, true>), g, b, lds, s, a);
     } else {
-        if (lookup == kLookupStepTable) hipLaunchKernelGGL((k_triplet<false, 2>), g, b, lds, s, a);
-        else if (lookup == kLookupOneStep) hipLaunchKernelGGL((k_triplet<false, 1>), g, b, lds, s, a);
-        else hipLaunchKernelGGL((k_triplet<false, 0>), g, b, lds, s, a);
+        if (lookup == kLookupStepTable) hipLaunchKernelGGL((k_triplet<false, 2, false>), g, b, lds, s, a);
+        else if (lookup == kLookupOneStep) hipLaunchKernelGGL((k_triplet<false, 1, false>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_triplet<false, 0, false>), g, b, lds, s, a);
     }
 }
 

@@ -41,7 +41,7 @@ def _bodies(text, name):
 
 def test_triplet_kernel_has_no_flat_stores(asm):
     bodies = _bodies(asm, "k_triplet")
-    assert len(bodies) == 6
+    assert len(bodies) == 9
     for sym, body in bodies.items():
         assert "flat_store" not in body, sym
 
