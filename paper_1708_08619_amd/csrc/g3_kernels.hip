@@ -1125,13 +1125,22 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 const int c0 = (int)ld16(kChunkT + 2u * (w0 >> 6));
                 const int ci = c0 + 1 + lane;
                 const uint32_t bnd = ci <= nne_u ? ld32(kRoff + 4u * (uint32_t)ci) << pp : 0xffffffffu;
-                uint64_t M = __ballot(bnd <= w0 + 63u);
-                cl = c0;
-                while (M) {
-                    const int l = __builtin_ctzll(M);
-                    M &= M - 1ull;
-                    cl += (w >= (uint32_t)__builtin_amdgcn_readlane((int)bnd, l)) ? 1 : 0;
-                }
+                // mark, in this wave's 64 bytes of the sort buckets (free
+                // once the item is set up), the offsets bnd - w0 (1..63, one
+                // per centre, in increasing order) at which a centre after c0
+                // starts inside the chunk; lane l's centre is c0 plus the marks
+                // at offsets <= l.  (Lanes read each other's stores: the
+                // wave fences keep the compiler from reordering or forwarding.)
+                const uint32_t fl = kTlKeys + 64u * (uint32_t)wave;
+                st8(fl + (uint32_t)lane, 0u);
+                wave_sync();
+                if (bnd <= w0 + 63u) st8(fl + (bnd - w0), 1u);
+                wave_sync();
+                const uint32_t own = ld8(fl + (uint32_t)lane);
+                const uint64_t marks = __ballot(own != 0u);
+                cl = c0 + (int)own +
+                     (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(marks >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)marks, 0u));
             } else {
                 int lo = 0, hi = nne_u - 1;
                 while (lo < hi) {

@@ -295,6 +295,29 @@ def test_narrow_components_beyond_int16(g3mod, plan, torch_dev, oracle_mod, per_
         assert_same(b, want, f"batched layout {layout}")
 
 
+@pytest.mark.parametrize("per_centre", [0, 1])
+def test_pad_entries_near_their_bound(g3mod, plan, torch_dev, oracle_mod, per_centre):
+    """Neighbour lists end in pad entries that every row must reject: with
+    rmax = 15000 units and a third axis of twice the bins (third side up to
+    30000), the narrow pads (components -32768) sit close to the bound the
+    host checks, 3 (32769 - C)^2 >= R3, so the triplet kernel runs its
+    padded form on rows with large components."""
+    rng = np.random.default_rng(91)
+    box = [64000, 64000, 64000]
+    fr = np.stack([np.stack([rng.integers(0, L, size=700) for L in box]) for _ in range(2)])
+    plan.set_tuning(per_centre=per_centre)
+    for layout in (0, 1):
+        want = oracle_mod.hist(fr, box, 15000.0, 12, layout, nbins_third=24)
+        h = g3mod.new_hist(12, layout, torch_dev, nbins_third=24)
+        plan.accumulate(_dev(fr.astype(np.int32), torch_dev), box, 15000.0, 12, layout, h,
+                        nbins_third=24)
+        plan.sync()
+        assert_same(h.cpu().numpy().astype(np.uint64), want, f"layout {layout}")
+        a, b = both(g3mod, plan, torch_dev, fr, box, 15000.0, 12, layout)
+        assert_same(a, oracle_mod.hist(fr, box, 15000.0, 12, layout), f"plain layout {layout}")
+        assert_same(b, oracle_mod.hist(fr, box, 15000.0, 12, layout), f"batched layout {layout}")
+
+
 # ------------------------------------------------------------------ edge cases
 def test_empty_and_tiny(g3mod, plan, torch_dev):
     import torch
