@@ -1161,9 +1161,9 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             const int jA = jp, jB = rr - 1 - jp;
             const int LA = mm - 1 - jA;
             const int LB = jB > jA ? mm - 1 - jB : 0;
-            // row j against candidates [k, kend); vj is entry j and ga holds
-            // entries [k, k+4) (loaded by the caller, possibly ahead of time)
-            auto run = [&](const E vj, E (&ga)[4], int k, int kend) {
+            // Row j's evaluators: d2, the exact bin, and the increments of a
+            // group of 4 candidates (evalg) or of one (eval1), handed to body.
+            auto with_row = [&](const E vj, auto&& body) {
                 // slab index of (b_j, b_k, c) is (b_j - lo0) RL + (b_k - lo0) nb3 + c
                 // with RL = (nb - lo0) nb3; entries carry b nb3, and
                 // (b_j - lo0) RL = (b_j nb3)(nb - lo0) - lo0 RL
@@ -1185,8 +1185,8 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     else
                         return Ent<false>::dist2(vk, jx, jz, 0);
                 };
-                // bin of s from the table plus the threshold step(s); any value
-                // for a rejected candidate, whose increment goes to the trash
+                // bin of s; any value for a rejected candidate, whose
+                // increment goes to the trash
                 auto bin = [&](uint32_t s) -> uint32_t {
                     uint32_t c;
                     if constexpr (kStep) {
@@ -1203,85 +1203,8 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     }
                     return c;
                 };
-                // G candidates at a time: distances, bins, addresses, then the
-                // G increments (rejected ones to this lane's trash word)
-                auto evalg = [&](const E* v, auto GN) {
-                    constexpr int G = decltype(GN)::value;
-                    uint32_t s[G], a[G];
-#pragma unroll
-                    for (int u = 0; u < G; ++u) s[u] = d2(v[u]);
-#pragma unroll
-                    for (int u = 0; u < G; ++u)
-                        a[u] = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v[u]) + bin(s[u]));
-                    // keep the address arithmetic unconditional (a select, not a branch)
-#pragma unroll
-                    for (int u = 0; u < G; ++u) asm volatile("" : "+v"(a[u]));
-#pragma unroll
-                    for (int u = 0; u < G; ++u) inc32(s[u] < R3 ? a[u] : trash);
-                };
-                auto eval1 = [&](const E& v) {
-                    const uint32_t s = d2(v);
-                    uint32_t a = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v) + bin(s));
-                    asm volatile("" : "+v"(a));
-                    inc32(s < R3 ? a : trash);
-                };
-                // two register groups in ping-pong, each group's loads issued
-                // one group ahead (reads may run up to 7 entries past the list,
-                // into the pool slot's padding, and are never evaluated)
-                using G4 = std::integral_constant<int, 4>;
-                uint32_t ko = eoff + (uint32_t)k * ES;
-                if (k + 4 <= kend) {
-                    E gb[4];
-                    for (; k + 8 <= kend; k += 8, ko += 8 * ES) {
-                        pool.load4(ko + 4 * ES, gb);
-                        evalg(ga, G4{});
-                        pool.load4(ko + 8 * ES, ga);
-                        evalg(gb, G4{});
-                    }
-                    if (k + 4 <= kend) {
-                        evalg(ga, G4{});
-                        k += 4;
-                        ko += 4 * ES;
-                    }
-                }
-                for (; k < kend; ++k, ko += ES) eval1(pool.load(ko));
-            };
-            // Padded lists: whole groups of 4 only.  [k, kend) spans a whole
-            // number of groups; a run's last group may reach up to 3 entries
-            // past the list, into its pad entries, which every row rejects.
-            // The next group's loads may read 3 entries further (into the
-            // next list or the pool slot's padding); they are never evaluated.
-            auto run4 = [&](const E vj, E (&ga)[4], int k, int kend) {
-                const int colj = Ent<WIDE>::col(vj);
-                uint32_t rowbase =
-                    kTlHist + 4u * (uint32_t)(__mul24(colj, nb - lo0) - lo0 * RL - lo0 * nb3);
-                asm volatile("" : "+v"(rowbase));
-                uint32_t jx, jy = 0, jz;
-                if constexpr (WIDE) {
-                    jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
-                } else {
-                    jx = vj.x; jz = vj.y & 0xffffu;
-                }
-                auto d2 = [&](const E& vk) -> uint32_t {
-                    if constexpr (WIDE)
-                        return Ent<true>::dist2(vk, (int)jx, (int)jy, (int)jz, cm1);
-                    else
-                        return Ent<false>::dist2(vk, jx, jz, 0);
-                };
-                auto bin = [&](uint32_t s) -> uint32_t {
-                    uint32_t c;
-                    if constexpr (kStep) {
-                        c = (ld32(kTlTab + 4u * __builtin_amdgcn_ubfe(s, sh, tbits)) + s) >> sh;
-                    } else if constexpr (LOOKUP == kLookupOneStep) {
-                        c = ld8(kTlTab + __builtin_amdgcn_ubfe(s, sh, tbits));
-                        c += (s >= ld32(kTlThr + 4u + 4u * c)) ? 1u : 0u;
-                    } else {
-                        const uint32_t sc = min(s, R3m1);
-                        c = ld8(kTlTab + (sc >> sh));
-                        while (sc >= ld32(kTlThr + 4u + 4u * c)) ++c;
-                    }
-                    return c;
-                };
+                // 4 candidates at a time: distances, bins, addresses, then the
+                // 4 increments (rejected ones to this lane's trash word)
                 auto evalg = [&](const E* v) {
                     uint32_t s[4], a[4];
 #pragma unroll
@@ -1289,20 +1212,63 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
                         a[u] = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v[u]) + bin(s[u]));
+                    // keep the address arithmetic unconditional (a select, not a branch)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) asm volatile("" : "+v"(a[u]));
 #pragma unroll
                     for (int u = 0; u < 4; ++u) inc32(s[u] < R3 ? a[u] : trash);
                 };
-                uint32_t ko = eoff + (uint32_t)k * ES;
-                E gb[4];
-                for (; k + 4 < kend; k += 8, ko += 8 * ES) {   // two groups left at least
-                    pool.load4(ko + 4 * ES, gb);
-                    evalg(ga);
-                    pool.load4(ko + 8 * ES, ga);
-                    evalg(gb);
-                }
-                if (k < kend) evalg(ga);
+                auto eval1 = [&](const E& v) {
+                    const uint32_t s = d2(v);
+                    uint32_t a = rowbase + 4u * ((uint32_t)Ent<WIDE>::col(v) + bin(s));
+                    asm volatile("" : "+v"(a));
+                    inc32(s < R3 ? a : trash);
+                };
+                body(evalg, eval1);
+            };
+            // Row j against candidates [k, kend); vj is entry j and ga holds
+            // entries [k, k+4) (loaded by the caller, possibly ahead of time).
+            // Two register groups in ping-pong, each group's loads issued one
+            // group ahead (reads may run up to 7 entries past the list, into
+            // the next list or the pool slot's padding, and are never
+            // evaluated), then a group of 4 and single candidates.
+            auto run = [&](const E vj, E (&ga)[4], int k, int kend) {
+                with_row(vj, [&](auto& evalg, auto& eval1) {
+                    uint32_t ko = eoff + (uint32_t)k * ES;
+                    if (k + 4 <= kend) {
+                        E gb[4];
+                        for (; k + 8 <= kend; k += 8, ko += 8 * ES) {
+                            pool.load4(ko + 4 * ES, gb);
+                            evalg(ga);
+                            pool.load4(ko + 8 * ES, ga);
+                            evalg(gb);
+                        }
+                        if (k + 4 <= kend) {
+                            evalg(ga);
+                            k += 4;
+                            ko += 4 * ES;
+                        }
+                    }
+                    for (; k < kend; ++k, ko += ES) eval1(pool.load(ko));
+                });
+            };
+            // Padded lists: whole groups of 4 only.  [k, kend) spans a whole
+            // number of groups; a run's last group may reach up to 3 entries
+            // past the list, into its pad entries, which every row rejects.
+            // The next group's loads may read 3 entries further (into the
+            // next list or the pool slot's padding); they are never evaluated.
+            auto run4 = [&](const E vj, E (&ga)[4], int k, int kend) {
+                with_row(vj, [&](auto& evalg, auto&) {
+                    uint32_t ko = eoff + (uint32_t)k * ES;
+                    E gb[4];
+                    for (; k + 4 < kend; k += 8, ko += 8 * ES) {   // two groups left at least
+                        pool.load4(ko + 4 * ES, gb);
+                        evalg(ga);
+                        pool.load4(ko + 8 * ES, ga);
+                        evalg(gb);
+                    }
+                    if (k < kend) evalg(ga);
+                });
             };
             if constexpr (PADDED) {
                 // the unit as groups of 4: gA of row jA, then gB of row jB;
