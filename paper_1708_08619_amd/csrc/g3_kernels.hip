@@ -114,16 +114,16 @@ __global__ void __launch_bounds__(256) k_cell_count(const Sys* __restrict__ sys,
     const int a = blockIdx.x * 256 + threadIdx.x;
     if (a >= S.N) return;
     const int N = S.N, f = jb.frame;
-    const int32_t* fr = S.frames + (size_t)f * 3 * N;
+    const gptr<const int32_t> fr = gp(S.frames + (size_t)f * 3 * N);
     const int x = fr[a], y = fr[N + a], z = fr[2 * N + a];
     if (x < 0 || x >= S.box[0] || y < 0 || y >= S.box[1] || z < 0 || z >= S.box[2]) {
-        atomicOr(&S.flags[f], kFlagDomain);
+        __hip_atomic_fetch_or(gp(&S.flags[f]), kFlagDomain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
     const int cell = (cell_of(z, S.nc[2], S.box[2]) * S.nc[1] + cell_of(y, S.nc[1], S.box[1])) *
                          S.nc[0] +
                      cell_of(x, S.nc[0], S.box[0]);
-    int32_t* cc = S.cell_count + fr_off(S, f, S.ncell);
+    const gptr<int32_t> cc = gp(S.cell_count + fr_off(S, f, S.ncell));
     // Lanes of a wave in the same cell share one atomic (frames stored in a
     // spatial order put many lanes in few cells); after 8 rounds the rest
     // take one atomic each.
@@ -138,7 +138,8 @@ __global__ void __launch_bounds__(256) k_cell_count(const Sys* __restrict__ sys,
         const bool mine = todo && cell == lc;
         const uint64_t m = __ballot(mine);
         int base = 0;
-        if (lane == leader) base = atomicAdd(&cc[lc], (int)__popcll(m));
+        if (lane == leader)
+            base = __hip_atomic_fetch_add(cc + lc, (int)__popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         base = __shfl(base, leader, 64);
         if (mine) {
             rank = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -146,9 +147,9 @@ __global__ void __launch_bounds__(256) k_cell_count(const Sys* __restrict__ sys,
             todo = false;
         }
     }
-    if (todo) rank = atomicAdd(&cc[cell], 1);
-    S.atom_cell[fr_off(S, f, N) + a] = cell;
-    S.atom_rank[fr_off(S, f, N) + a] = rank;
+    if (todo) rank = __hip_atomic_fetch_add(cc + cell, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gp(S.atom_cell)[fr_off(S, f, N) + a] = cell;
+    gp(S.atom_rank)[fr_off(S, f, N) + a] = rank;
 }
 
 // Exclusive scan of the cell counts into cell_start[0..ncell].
@@ -181,11 +182,11 @@ __global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sy
     const Sys& S = sys[jb.sys];
     const int a = blockIdx.x * 256 + threadIdx.x;
     const int N = S.N, f = jb.frame;
-    if (a >= N || (S.flags[f] & kFlagDomain)) return;
-    const int32_t* fr = S.frames + (size_t)f * 3 * N;
-    const int cell = S.atom_cell[fr_off(S, f, N) + a];
-    const int pos = S.cell_start[fr_off(S, f, S.ncell + 1) + cell] + S.atom_rank[fr_off(S, f, N) + a];
-    int32_t* so = S.sorted + fr_off(S, f, (size_t)3 * N);
+    if (a >= N || (gp(S.flags)[f] & kFlagDomain)) return;
+    const gptr<const int32_t> fr = gp(S.frames + (size_t)f * 3 * N);
+    const int cell = gp(S.atom_cell)[fr_off(S, f, N) + a];
+    const int pos = gp(S.cell_start)[fr_off(S, f, S.ncell + 1) + cell] + gp(S.atom_rank)[fr_off(S, f, N) + a];
+    const gptr<int32_t> so = gp(S.sorted + fr_off(S, f, (size_t)3 * N));
     so[pos] = fr[a];
     so[N + pos] = fr[N + a];
     so[2 * N + pos] = fr[2 * N + a];
@@ -204,10 +205,10 @@ __global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sy
 //   pass 2, on the accepted ones only, forms the entries and their pair
 //   bins and r12 slabs: a short list is partitioned by slab in registers
 //   (one ballot per slab), a longer one counts its slabs in LDS;
-//   the list is reserved from the wave's chunk of the frame's pool, the slab
-//   boundaries J_q are stored, and every neighbour is written at
-//   J_{slab(b)} + its rank in the slab: the list comes out partitioned by
-//   slab, which is all the triplet kernel needs.
+//   the list and its kListPad pad entries are reserved from the wave's chunk
+//   of the frame's pool, the slab boundaries J_q are stored, and every
+//   neighbour is written at J_{slab(b)} + its rank in the slab: the list
+//   comes out partitioned by slab, which is all the triplet kernel needs.
 // A centre with more neighbours than the buffer re-evaluates its candidates
 // for the write.  Narrow staged candidates saturate their components to
 // int16 and sum the squares with a clamped dot product; otherwise the
@@ -915,8 +916,12 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             const Sys& S = A.sys[G.sys];
             const int nb = S.nbins, nb3 = S.nb3, RL = G.rl;
             // triangle-once counts go to the half-layout triangle buffer
-            uint64_t* const out = S.tri ? S.tri : S.hist;
+            const gptr<unsigned long long> out =
+                gp(reinterpret_cast<unsigned long long*>(S.tri ? S.tri : S.hist));
             const int layout = S.tri ? 0 : S.layout;
+            auto add = [](gptr<unsigned long long> p, unsigned long long v) {
+                __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            };
             for (int x0 = wave * 64; x0 < G.hb; x0 += kTripletThreads) {
                 const int x = x0 + lane;
                 const uint32_t v = x < G.hb ? ld32(kTlHist + 4u * x) : 0u;
@@ -927,14 +932,12 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 const int lo = min(a, b), hi = max(a, b);
                 if (layout == 0) {
                     const size_t h = ((size_t)lo * nb - (size_t)lo * (lo - 1) / 2 + (hi - lo)) * nb3 + c;
-                    atomicAdd((unsigned long long*)&out[h], (unsigned long long)v);
+                    add(out + h, (unsigned long long)v);
                 } else if (lo == hi) {
-                    atomicAdd((unsigned long long*)&out[((size_t)lo * nb + lo) * nb3 + c], 2ull * v);
+                    add(out + ((size_t)lo * nb + lo) * nb3 + c, 2ull * v);
                 } else {
-                    atomicAdd((unsigned long long*)&out[((size_t)lo * nb + hi) * nb3 + c],
-                              (unsigned long long)v);
-                    atomicAdd((unsigned long long*)&out[((size_t)hi * nb + lo) * nb3 + c],
-                              (unsigned long long)v);
+                    add(out + ((size_t)lo * nb + hi) * nb3 + c, (unsigned long long)v);
+                    add(out + ((size_t)hi * nb + lo) * nb3 + c, (unsigned long long)v);
                 }
             }
         }

@@ -54,3 +54,15 @@ def test_triplet_kernel_has_no_static_lds_and_no_spills(asm):
         assert re.search(r"\.group_segment_fixed_size:\s+0\b", meta), sym
         assert re.search(r"\.private_segment_fixed_size:\s+0\b", meta), sym
         assert re.search(r"\.vgpr_spill_count:\s+0\b", meta), sym
+
+
+def test_hot_kernels_use_no_flat_memory_instructions(asm):
+    """Flat loads, stores and atomics also count against the LDS wait counter,
+    so an LDS wait would also wait for outstanding global accesses: the
+    neighbour build and the triplet kernel address global memory through
+    global-address-space pointers only."""
+    for name, count in (("k_triplet", 9), ("k_nbr_build", 4)):
+        bodies = _bodies(asm, name)
+        assert len(bodies) == count, name
+        for sym, body in bodies.items():
+            assert not re.search(r"^\s+flat_", body, re.M), sym
