@@ -1164,24 +1164,35 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
             const int jA = jp, jB = rr - 1 - jp;
             const int LA = mm - 1 - jA;
             const int LB = jB > jA ? mm - 1 - jB : 0;
-            // Row j's evaluators: d2, the exact bin, and the increments of a
-            // group of 4 candidates (evalg) or of one (eval1), handed to body.
-            auto with_row = [&](const E vj, auto&& body) {
+            // Row evaluators: d2, the exact bin, and the increments of a group
+            // of 4 candidates (evalg) or of one (eval1) against the current
+            // row, which starts as entry v1; second() moves it to entry v2.
+            auto with_rows = [&](const E v1, const E v2, auto&& body) {
                 // slab index of (b_j, b_k, c) is (b_j - lo0) RL + (b_k - lo0) nb3 + c
                 // with RL = (nb - lo0) nb3; entries carry b nb3, and
                 // (b_j - lo0) RL = (b_j nb3)(nb - lo0) - lo0 RL
-                const int colj = Ent<WIDE>::col(vj);
-                uint32_t rowbase =
-                    kTlHist + 4u * (uint32_t)(__mul24(colj, nb - lo0) - lo0 * RL - lo0 * nb3);
-                // one opaque value: the address below is then (col + c) << 2
-                // plus rowbase, col read from the entry's high half in place
-                asm volatile("" : "+v"(rowbase));
-                uint32_t jx, jy = 0, jz;
+                auto row_base = [&](const E vj) {
+                    uint32_t rb = kTlHist +
+                                  4u * (uint32_t)(__mul24(Ent<WIDE>::col(vj), nb - lo0) - lo0 * RL - lo0 * nb3);
+                    // one opaque value: the address below is then (col + c) << 2
+                    // plus rowbase, col read from the entry's high half in place
+                    asm volatile("" : "+v"(rb));
+                    return rb;
+                };
+                uint32_t rowbase = row_base(v1), jx, jy = 0, jz;
                 if constexpr (WIDE) {
-                    jx = (uint32_t)vj.x; jy = (uint32_t)vj.y; jz = (uint32_t)vj.z;
+                    jx = (uint32_t)v1.x; jy = (uint32_t)v1.y; jz = (uint32_t)v1.z;
                 } else {
-                    jx = vj.x; jz = vj.y & 0xffffu;
+                    jx = v1.x; jz = v1.y & 0xffffu;
                 }
+                auto second = [&]() {
+                    rowbase = row_base(v2);
+                    if constexpr (WIDE) {
+                        jx = (uint32_t)v2.x; jy = (uint32_t)v2.y; jz = (uint32_t)v2.z;
+                    } else {
+                        jx = v2.x; jz = v2.y & 0xffffu;
+                    }
+                };
                 auto d2 = [&](const E& vk) -> uint32_t {
                     if constexpr (WIDE)
                         return Ent<true>::dist2(vk, (int)jx, (int)jy, (int)jz, cm1);
@@ -1227,7 +1238,10 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     asm volatile("" : "+v"(a));
                     inc32(s < R3 ? a : trash);
                 };
-                body(evalg, eval1);
+                body(evalg, eval1, second);
+            };
+            auto with_row = [&](const E vj, auto&& body) {
+                with_rows(vj, vj, [&](auto& evalg, auto& eval1, auto&) { body(evalg, eval1); });
             };
             // Row j against candidates [k, kend); vj is entry j and ga holds
             // entries [k, k+4) (loaded by the caller, possibly ahead of time).
@@ -1286,13 +1300,39 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     pool.load4(eoff + (uint32_t)kA * ES, gAv);
                 }
                 if constexpr (!WIDE) {
-                    E vB{}, gBv[4];
-                    if (hasB) {
-                        vB = pool.load(eoff + (uint32_t)jB * ES);
-                        pool.load4(eoff + (uint32_t)kB * ES, gBv);
+                    // One loop over the part's groups, switching from row jA
+                    // to row jB after A's last one (koSw), so that a wave's
+                    // lanes run their A and B groups together instead of
+                    // every A loop as long as the longest, then every B loop.
+                    const int nA = hasA ? min(g1, gA) - g0 : 0;
+                    const int n = g1 - g0;
+                    if (n <= 0) continue;
+                    const uint32_t koB = eoff + (uint32_t)kB * ES;
+                    const uint32_t ko0 = hasA ? eoff + (uint32_t)kA * ES : koB;
+                    const uint32_t koSw = hasA && hasB ? ko0 + (uint32_t)(nA - 1) * (4u * ES) : 0xffffffffu;
+                    const E vB = hasB ? pool.load(eoff + (uint32_t)jB * ES) : E{};
+                    if (!hasA) {
+                        pool.load4(koB, gAv);
+                        vA = vB;
                     }
-                    if (hasA) run4(vA, gAv, kA, jA + 1 + 4 * min(g1, gA));
-                    if (hasB) run4(vB, gBv, kB, jB + 1 + 4 * (g1 - gA));
+                    with_rows(vA, vB, [&](auto& evalg, auto&, auto& second) {
+                        uint32_t ko = ko0;
+                        int left = n;
+                        E gb[4];
+                        for (; left >= 2; left -= 2) {
+                            const bool s1 = ko == koSw;
+                            const uint32_t k1 = s1 ? koB : ko + 4u * ES;
+                            pool.load4(k1, gb);
+                            evalg(gAv);
+                            if (s1) second();
+                            const bool s2 = k1 == koSw;
+                            ko = s2 ? koB : k1 + 4u * ES;
+                            pool.load4(ko, gAv);
+                            evalg(gb);
+                            if (s2) second();
+                        }
+                        if (left) evalg(gAv);
+                    });
                 } else {
                     if (hasA) run4(vA, gAv, kA, jA + 1 + 4 * min(g1, gA));
                     if (hasB) {
