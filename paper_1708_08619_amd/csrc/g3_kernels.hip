@@ -1269,24 +1269,6 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     for (; k < kend; ++k, ko += ES) eval1(pool.load(ko));
                 });
             };
-            // Padded lists: whole groups of 4 only.  [k, kend) spans a whole
-            // number of groups; a run's last group may reach up to 3 entries
-            // past the list, into its pad entries, which every row rejects.
-            // The next group's loads may read 3 entries further (into the
-            // next list or the pool slot's padding); they are never evaluated.
-            auto run4 = [&](const E vj, E (&ga)[4], int k, int kend) {
-                with_row(vj, [&](auto& evalg, auto&) {
-                    uint32_t ko = eoff + (uint32_t)k * ES;
-                    E gb[4];
-                    for (; k + 4 < kend; k += 8, ko += 8 * ES) {   // two groups left at least
-                        pool.load4(ko + 4 * ES, gb);
-                        evalg(ga);
-                        pool.load4(ko + 8 * ES, ga);
-                        evalg(gb);
-                    }
-                    if (k < kend) evalg(ga);
-                });
-            };
             if constexpr (PADDED) {
                 // the unit as groups of 4: gA of row jA, then gB of row jB;
                 // part p takes groups [g0, g1)
@@ -1299,48 +1281,43 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     vA = pool.load(eoff + (uint32_t)jA * ES);
                     pool.load4(eoff + (uint32_t)kA * ES, gAv);
                 }
-                if constexpr (!WIDE) {
-                    // One loop over the part's groups, switching from row jA
-                    // to row jB after A's last one (koSw), so that a wave's
-                    // lanes run their A and B groups together instead of
-                    // every A loop as long as the longest, then every B loop.
-                    const int nA = hasA ? min(g1, gA) - g0 : 0;
-                    const int n = g1 - g0;
-                    if (n <= 0) continue;
-                    const uint32_t koB = eoff + (uint32_t)kB * ES;
-                    const uint32_t ko0 = hasA ? eoff + (uint32_t)kA * ES : koB;
-                    const uint32_t koSw = hasA && hasB ? ko0 + (uint32_t)(nA - 1) * (4u * ES) : 0xffffffffu;
-                    const E vB = hasB ? pool.load(eoff + (uint32_t)jB * ES) : E{};
-                    if (!hasA) {
-                        pool.load4(koB, gAv);
-                        vA = vB;
-                    }
-                    with_rows(vA, vB, [&](auto& evalg, auto&, auto& second) {
-                        uint32_t ko = ko0;
-                        int left = n;
-                        E gb[4];
-                        for (; left >= 2; left -= 2) {
-                            const bool s1 = ko == koSw;
-                            const uint32_t k1 = s1 ? koB : ko + 4u * ES;
-                            pool.load4(k1, gb);
-                            evalg(gAv);
-                            if (s1) second();
-                            const bool s2 = k1 == koSw;
-                            ko = s2 ? koB : k1 + 4u * ES;
-                            pool.load4(ko, gAv);
-                            evalg(gb);
-                            if (s2) second();
-                        }
-                        if (left) evalg(gAv);
-                    });
-                } else {
-                    if (hasA) run4(vA, gAv, kA, jA + 1 + 4 * min(g1, gA));
-                    if (hasB) {
-                        E vB = pool.load(eoff + (uint32_t)jB * ES), gBv[4];
-                        pool.load4(eoff + (uint32_t)kB * ES, gBv);
-                        run4(vB, gBv, kB, jB + 1 + 4 * (g1 - gA));
-                    }
+                // One loop over the part's groups, switching from row jA to
+                // row jB after A's last one (koSw), so that a wave's lanes
+                // run their A and B groups together instead of every A loop
+                // as long as the longest, then every B loop.  A run's last
+                // group may reach up to 3 entries past the list, into its pad
+                // entries, which every row rejects; the loads one group past
+                // the part (never evaluated) may read 4 entries further, into
+                // the next list or the pool slot's padding.
+                const int nA = hasA ? min(g1, gA) - g0 : 0;
+                const int n = g1 - g0;
+                if (n <= 0) continue;
+                const uint32_t koB = eoff + (uint32_t)kB * ES;
+                const uint32_t ko0 = hasA ? eoff + (uint32_t)kA * ES : koB;
+                const uint32_t koSw = hasA && hasB ? ko0 + (uint32_t)(nA - 1) * (4u * ES) : 0xffffffffu;
+                const E vB = hasB ? pool.load(eoff + (uint32_t)jB * ES) : E{};
+                if (!hasA) {
+                    pool.load4(koB, gAv);
+                    vA = vB;
                 }
+                with_rows(vA, vB, [&](auto& evalg, auto&, auto& second) {
+                    uint32_t ko = ko0;
+                    int left = n;
+                    E gb[4];
+                    for (; left >= 2; left -= 2) {
+                        const bool s1 = ko == koSw;
+                        const uint32_t k1 = s1 ? koB : ko + 4u * ES;
+                        pool.load4(k1, gb);
+                        evalg(gAv);
+                        if (s1) second();
+                        const bool s2 = k1 == koSw;
+                        ko = s2 ? koB : k1 + 4u * ES;
+                        pool.load4(ko, gAv);
+                        evalg(gb);
+                        if (s2) second();
+                    }
+                    if (left) evalg(gAv);
+                });
                 continue;
             }
             const int Lt = LA + LB;
