@@ -404,14 +404,20 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
         __syncthreads();
         const int T = st.pre[st.n];
         const bool staged = T <= kStageCap;
+        // stencil cell of candidate t: the last r < n with pre[r] <= t
         auto cell_of_t = [&](int t) {
             int r = 0;
             while (st.pre[r + 1] <= t) ++r;
             return r;
         };
         if (staged) {
+            const int n_st = st.n;
             for (int t = tid; t < T; t += kBuildThreads) {
-                const int r = cell_of_t(t);
+                // (the same, by binary search: pre is non-decreasing, n <= 27)
+                int r = 0;
+#pragma unroll
+                for (int step = 16; step >= 1; step >>= 1)
+                    if (r + step < n_st && st.pre[r + step] <= t) r += step;
                 const int j = st.start[r] + (t - st.pre[r]);
                 s_x[t] = X[j] + st.shx[r];
                 s_y[t] = Y[j] + st.shy[r];
