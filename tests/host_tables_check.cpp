@@ -4,6 +4,8 @@
 // thr[b] <= s:
 //   * the u8 table gives a lower bound, within one step when one_step is set;
 //   * the step table, when built, gives b(s) exactly.
+// Then the pad entries after each neighbour list: where the host lets the
+// triplet kernel read them, no row accepts them.
 // Exit status: the number of geometries with a failure.
 #include "../paper_1708_08619_amd/csrc/g3_host.cpp"
 
@@ -55,5 +57,43 @@ int main()
     }
     // the benchmark-like geometries must get the step table
     if (with_step < 8) ++failed;
+
+    // Pad entries (components -32768): where the host lets the triplet kernel
+    // read them, every row within the pair cutoff must reject them, in the
+    // kernel's arithmetic (saturated 16-bit differences, squares summed and
+    // clamped to 2^31 - 1).  Rows on a grid over [-(C-1), C-1]^3, extremes
+    // included.
+    struct Pad { double rmax; int nb, nb3; bool padded; } pads[] = {
+        {3.0 * 4096, 60, 60, true}, {15000.0, 12, 24, true}, {15100.0, 10, 20, true},
+        {16000.0, 10, 20, false}, {30000.0, 20, 20, false}, {39321.6, 60, 60, true}};
+    for (const Pad& c : pads) {
+        Geometry g;
+        g.nbins = c.nb;
+        g.nb3 = c.nb3;
+        g.C = (int)std::ceil(c.rmax);
+        plan_bins(g, c.rmax);
+        g.wide = g.C3 > 32767 ? 1 : 0;
+        const bool padded = pads_rejected(g);
+        uint64_t accepted = 0, rows = 0;
+        if (padded && !g.wide) {
+            auto sat = [](int64_t v) { return v < -32768 ? -32768 : (v > 32767 ? 32767 : v); };
+            const int K = 40;
+            for (int a = 0; a <= K; ++a)
+                for (int b = 0; b <= K; ++b)
+                    for (int e = 0; e <= K; ++e) {
+                        const int64_t m = g.C - 1;
+                        const int64_t jx = -m + 2 * m * a / K, jy = -m + 2 * m * b / K, jz = -m + 2 * m * e / K;
+                        if ((uint64_t)(jx * jx + jy * jy + jz * jz) >= g.R2) continue;   // not a row
+                        ++rows;
+                        const int64_t dx = sat(-32768 - jx), dy = sat(-32768 - jy), dz = sat(-32768 - jz);
+                        const int64_t s = std::min<int64_t>(dx * dx + dy * dy + dz * dz, 0x7fffffff);
+                        if ((uint64_t)s < g.R3) ++accepted;
+                    }
+        }
+        std::printf("pads: rmax %.1f nb3 %d wide %d padded %d (expected %d): %llu rows, %llu accept a pad\n",
+                    c.rmax, c.nb3, g.wide, padded ? 1 : 0, c.padded ? 1 : 0, (unsigned long long)rows,
+                    (unsigned long long)accepted);
+        if (padded != c.padded || accepted) ++failed;
+    }
     return failed;
 }

@@ -1,6 +1,8 @@
 """Bin lookup tables of the runtime, checked on the host for every value
-below the third-side cutoff (tests/host_tables_check.cpp, built from the
-runtime's own source with stub launchers)."""
+below the third-side cutoff, and the neighbour lists' pad entries, checked
+against a grid of rows where the runtime lets the triplet kernel read them
+(tests/host_tables_check.cpp, built from the runtime's own source with stub
+launchers)."""
 from __future__ import annotations
 
 import os
