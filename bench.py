@@ -74,7 +74,7 @@ def mark(msg: str):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(frames would shard across GPUs with one uint64 all-reduce of the "
               "histogram; see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
