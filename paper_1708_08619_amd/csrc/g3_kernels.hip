@@ -833,6 +833,7 @@ constexpr uint32_t kTlKeys = kTlMisc + 128;           // uint32 [256]: centres p
 constexpr uint32_t kTlHist = kTlKeys + 1024;          // uint32 hist[hb_max], then per item:
                                                       // src[cb], m[cb], roff[cb+1], chunk[kChunkCap]
 static_assert(kTlHist == kTripletLdsFixed, "triplet LDS map");
+static_assert(kTripletThreads / kWave * 64 <= 1024, "each wave's 64 mark bytes fit the sort buckets");
 
 // (LDS pointers are 32-bit on the device; the host pass sees 64-bit ones)
 #pragma clang diagnostic push
