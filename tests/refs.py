@@ -187,3 +187,54 @@ def lattice_full(vectors: np.ndarray, n_sites: int, rmax: float, nbins: int,
 def permutations_of(H: np.ndarray):
     for p in itertools.permutations(range(3)):
         yield p, np.transpose(H, p)
+
+
+def brute_half(frames, box, rmax: float, nbins: int, nbins_third: int | None = None) -> dict:
+    """Unordered triplets counted straight into the half layout: for every
+    centre i and every pair j < k (both != i) with |d_ij|, |d_ik| < rmax and
+    the third side d_ik - d_ij (no second minimum image) inside the
+    nbins_third bins, key (min(b_ij, b_ik), max(b_ij, b_ik), b_jk) gains 1.
+    No full histogram and no fold: a different route from the oracle's."""
+    nc = nbins_third or nbins
+    fr = np.asarray(frames, dtype=np.int64)
+    F, _, N = fr.shape
+    out: dict[tuple[int, int, int], int] = {}
+    cache: dict[int, int] = {}
+    cache3: dict[int, int] = {}
+
+    def b(s):
+        if s not in cache:
+            cache[s] = frac_bin(s, rmax, nbins)
+        return cache[s]
+
+    def b3(s):
+        if s not in cache3:
+            cache3[s] = frac_bin_n(s, rmax, nbins, nc)
+        return cache3[s]
+
+    for f in range(F):
+        P = [tuple(int(fr[f, d, a]) for d in range(3)) for a in range(N)]
+        for i in range(N):
+            near = []
+            for j in range(N):
+                if j == i:
+                    continue
+                d = [min_image(P[j][a] - P[i][a], box[a]) for a in range(3)]
+                bj = b(sum(x * x for x in d))
+                if bj >= 0:
+                    near.append((d, bj))
+            for x in range(len(near)):
+                for y in range(x + 1, len(near)):
+                    (dj, bj), (dk, bk) = near[x], near[y]
+                    c = b3(sum((dk[a] - dj[a]) ** 2 for a in range(3)))
+                    if c < 0:
+                        continue
+                    key = (min(bj, bk), max(bj, bk), c)
+                    out[key] = out.get(key, 0) + 1
+    return out
+
+
+def half_order(nbins: int, nc: int) -> list:
+    """The half layout's bins in storage order, listed one by one: rows
+    lo = 0.. with columns hi = lo..nbins-1, each with nc third-side bins."""
+    return [(lo, hi, c) for lo in range(nbins) for hi in range(lo, nbins) for c in range(nc)]

@@ -384,3 +384,64 @@ def test_third_axis_ideal_gas_g3_is_one(oracle_mod):
     assert live[:, :, nbins:].any()
     z = (m[live] - E1[live]) / np.maximum(sem[live], 1e-9)
     assert np.all(np.abs(z) < 5.0), z.max()
+
+
+# ---------------------------------------------------------------- half layout, longer third axis
+@pytest.mark.parametrize("seed", range(4))
+def test_half_fold_third_axis_brute_force(oracle_mod, seed):
+    """The half layout with nbins < nbins_third <= 2 nbins (the longer third
+    axis of Sec. 3.3's geometry), counted straight from unordered {j, k}
+    (serial g3 listing: pairs k > j per centre) with exact Fraction bins, and
+    laid out by enumerating the half bins in order -- neither the full
+    histogram nor the oracle's fold or index formula is involved."""
+    rng = np.random.default_rng(700 + seed)
+    box = [int(x) for x in rng.integers(300, 700, size=3)]
+    rmax = float(rng.uniform(min(box) / 4.5, min(box) / 4.0))
+    nbins = int(rng.integers(3, 7))
+    nc = 2 * nbins if seed % 2 == 0 else nbins + int(rng.integers(1, nbins))
+    fr = _random_system(rng, int(rng.integers(28, 36)), box)
+    counts = refs.brute_half(fr, box, rmax, nbins, nc)
+    order = refs.half_order(nbins, nc)
+    want = np.array([counts.get(k, 0) for k in order], dtype=np.uint64)
+    assert sum(counts.values()) == int(want.sum())      # every key is a valid half bin
+    got = oracle_mod.hist(fr, box, rmax, nbins, 0, nbins_third=nc)
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+    # third sides past rmax were met, and diagonal (lo == hi) bins too
+    beyond = sum(n for (lo, hi, c), n in counts.items() if c >= nbins)
+    diag = sum(n for (lo, hi, c), n in counts.items() if lo == hi)
+    assert beyond > 0 and diag > 0
+
+
+def test_ideal_gas_half_layout_g3_is_one(oracle_mod):
+    """Ideal gas in the half layout: the normalisation halves the expectation
+    on the diagonal lo == hi (one unordered pair per two ordered ones), so g3
+    -> 1 on every live bin, the diagonal included.  Per-bin means against
+    frame-to-frame standard errors (same rule as the full-layout test), the
+    diagonal's pooled ratio, and the total against its expectation."""
+    N, F, nbins = 128, 40, 4
+    L = 12000
+    rmax = 4000.0
+    w = synth.ideal_gas(N, [L, L, L], F, rmax, nbins, layout=0, seed=(synth.SEED_BASE, 17))
+    per = np.stack([oracle_mod.hist(w.frames[f:f + 1], w.box, rmax, nbins, 0).astype(np.float64)
+                    for f in range(F)])                         # [F, half bins]
+    g = oracle_mod.normalize(per.sum(0).astype(np.uint64), 0, nbins, rmax, F, N, w.box)
+    order = refs.half_order(nbins, nbins)
+    diag = np.array([lo == hi for lo, hi, _ in order])
+    m = per.mean(0)
+    sem = per.std(0, ddof=1) / math.sqrt(F)
+    live = m > 50
+    assert live[diag].sum() >= 3 and live[~diag].sum() >= 3
+    # g3 = 1 within 5 standard errors of the per-frame mean, bin by bin
+    z = (g[live] - 1.0) / np.maximum(sem[live] / m[live], 1e-12)
+    assert np.all(np.abs(z) < 5.0), np.abs(z).max()
+    # a missing (or doubled) factor 1/2 on the diagonal would put it at 2 (or 1/2)
+    pooled = per.sum(0)[diag & live].sum() / (per.sum(0)[diag & live] / g[diag & live]).sum()
+    assert abs(pooled - 1.0) < 0.05, pooled
+    # total: the expected number of unordered triplets is half the ordered
+    # one, F N(N-1)(N-2)/V^2 sum(W) / 2 with sum(W) = (4 pi R^3/3)^2 15/32
+    E_tot = N * (N - 1) * (N - 2) / float(L) ** 6 * (4 * math.pi * rmax ** 3 / 3) ** 2 * 15 / 32 / 2
+    tot = per.sum(1)
+    zt = (tot.mean() - E_tot) / (tot.std(ddof=1) / math.sqrt(F))
+    assert abs(zt) < 5.0
+    assert abs(tot.mean() / E_tot - 1) < 0.04      # about 1 % standard error here
