@@ -143,9 +143,14 @@ g3_status g3_accumulate_system(g3_plan p, const g3_system* system);
 /* Batched form: every frame of every system in ONE launch sequence (batched
  * cell and neighbour builds, one persistent triplet kernel pulling work items
  * from a device counter, one flush at the end), replayed as a hipGraph once
- * the same launch signature (shapes and tuning) repeats.  Systems may differ
- * in size, box, rmax, nbins and layout.  Several systems may not share one
- * hist. */
+ * the same launch signature (shapes and tuning) repeats.  This is the
+ * frame x atom flattening of Sec. 3.2's parallel P2 logic (all frames'
+ * atoms in one kernel launch instead of a launch per frame, which removes the
+ * time between kernel calls), applied to g3 and extended across systems.
+ * Systems may differ in size, box, rmax, nbins and layout.  Several systems
+ * may not share one hist.  Arguments are checked before anything is queued
+ * (G3_EINVAL: a system fails the conventions above, or two systems' hist or
+ * pair_hist arrays overlap). */
 g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_systems);
 
 /* Wait for the plan's queued work and report asynchronous errors:
@@ -158,6 +163,23 @@ g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_sys
  * recomputed here through the plain path (with 512-centre items) before
  * returning, so they are never lost or miscounted. */
 g3_status g3_sync(g3_plan p);
+
+/* Completion of one call without waiting for the rest of the stream (for
+ * serving loops that keep several calls in flight).  Every successful
+ * g3_accumulate, g3_accumulate_system and g3_accumulate_batch call gets a
+ * ticket, numbered 1, 2, ... per plan; g3_last_ticket returns the latest
+ * (0 before the first).  g3_ticket_query never blocks:
+ *   G3_EBUSY  the call's kernels are still running;
+ *   G3_OK     they have finished, and *final says whether every histogram the
+ *             call added into now holds its final counts (1), or whether
+ *             g3_sync must run first (0: a frame of the call is to be
+ *             recomputed, or an error is to be reported);
+ *   G3_EINVAL no such ticket.
+ * Every ticket issued before a g3_sync is final once it returns.  A copy of
+ * a histogram taken after a ticket reports final = 1 holds the call's
+ * counts; if g3_sync had to run, copy it again after g3_sync. */
+g3_status g3_last_ticket(g3_plan p, uint64_t* ticket);
+g3_status g3_ticket_query(g3_plan p, uint64_t ticket, int32_t* final);
 
 /* Non-blocking: G3_OK if all work queued on the plan's stream has finished
  * (g3_sync will then not wait), G3_EBUSY if some is still running. */

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <map>
 #include <vector>
@@ -328,6 +329,21 @@ struct g3_plan_s {
     std::string last_key[2];   // signature of the previous batched call
     bool lds_set = false;
 
+    // Completion tickets (one per accumulate call): the call's flag words are
+    // copied to pinned host memory behind its kernels and an event marks the
+    // copy, so one call's completion is seen without waiting for the stream.
+    struct Ticket {
+        uint64_t id;
+        hipEvent_t ev;
+        int off, n;          // the call's range of the flag log
+    };
+    uint32_t* flag_host = nullptr;        // pinned mirror of the flag log
+    std::deque<Ticket> tickets;
+    std::vector<hipEvent_t> ticket_ev_free;
+    uint64_t next_ticket = 1;
+    uint64_t final_upto = 0;              // tickets up to this one are final (synchronised)
+    int call_first = -1, call_end = 0;    // flag-log range reserved by the current call
+
     // kernel timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
@@ -639,6 +655,8 @@ g3_status reserve_flags(g3_plan p, int n, uint32_t** out, int* off)
     *off = p->flag_used;
     *out = p->flag_log + p->flag_used;
     p->flag_used += n;
+    if (p->call_first < 0) p->call_first = *off;
+    p->call_end = *off + n;
     launch_zero_u32(*out, (size_t)n, p->stream);
     return G3_OK;
 }
@@ -1043,6 +1061,12 @@ g3_status drain(g3_plan p)
 {
     G3_TRY_HIP(hipStreamSynchronize(p->stream));
     collect_timing(p);
+    // every call queued so far has finished; after the recomputation below
+    // its histograms are final
+    for (auto& t : p->tickets) p->ticket_ev_free.push_back(t.ev);
+    p->tickets.clear();
+    p->final_upto = p->next_ticket - 1;
+    p->call_first = -1;
     g3_status result = p->sticky;
     if (p->flag_used > 0) {
         std::vector<uint32_t> fl(p->flag_used);
@@ -1080,6 +1104,30 @@ g3_status drain(g3_plan p)
         }
     }
     return result;
+}
+
+// Ticket of a successful accumulate call: copy its flag words behind its
+// kernels and record an event after the copy.
+g3_status issue_ticket(g3_plan p)
+{
+    if (!p->flag_host)
+        G3_TRY_HIP(hipHostMalloc((void**)&p->flag_host, sizeof(uint32_t) * kFlagLogCap, hipHostMallocDefault));
+    hipEvent_t ev;
+    if (!p->ticket_ev_free.empty()) {
+        ev = p->ticket_ev_free.back();
+        p->ticket_ev_free.pop_back();
+    } else {
+        G3_TRY_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    const int off = p->call_first >= 0 ? p->call_first : 0;
+    const int n = p->call_first >= 0 ? p->call_end - p->call_first : 0;
+    p->call_first = -1;
+    p->tickets.push_back({p->next_ticket++, ev, off, n});
+    if (n > 0)
+        G3_TRY_HIP(hipMemcpyAsync(p->flag_host + off, p->flag_log + off, sizeof(uint32_t) * n,
+                                  hipMemcpyDeviceToHost, p->stream));
+    G3_TRY_HIP(hipEventRecord(ev, p->stream));
+    return G3_OK;
 }
 
 }  // namespace
@@ -1120,6 +1168,9 @@ void g3_plan_destroy(g3_plan p)
         if (p->stage_ev[b]) hipEventDestroy(p->stage_ev[b]);
     }
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    for (auto& t : p->tickets) hipEventDestroy(t.ev);
+    for (auto& e : p->ticket_ev_free) hipEventDestroy(e);
+    if (p->flag_host) hipHostFree(p->flag_host);
     delete p;
 }
 
@@ -1151,9 +1202,11 @@ static g3_status accumulate_one(g3_plan p, g3_system s)
     g3_status st = check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
     if (st) return st;
     if (s.n_frames < 0 || (s.n_frames > 0 && s.n_atoms > 0 && (!s.frames || !s.hist))) return G3_EINVAL;
-    if (s.n_frames == 0 || s.n_atoms < (s.pair_hist ? 2 : 3)) return G3_OK;
+    p->call_first = -1;
+    if (s.n_frames == 0 || s.n_atoms < (s.pair_hist ? 2 : 3)) return issue_ticket(p);
     if (s.pair_hist && overlaps(s, s)) return G3_EINVAL;
-    return run_plain(p, s, false);
+    st = run_plain(p, s, false);
+    return st ? st : issue_ticket(p);
 }
 
 g3_status g3_accumulate(g3_plan p, const int32_t* frames, int32_t n_frames, int32_t n_atoms,
@@ -1197,8 +1250,9 @@ g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_sys
         if (overlaps(s, s)) return G3_EINVAL;
         live.push_back(s);
     }
-    if (live.empty()) return G3_OK;
-    return run_batch(p, live.data(), (int)live.size());
+    p->call_first = -1;
+    g3_status st = live.empty() ? G3_OK : run_batch(p, live.data(), (int)live.size());
+    return st ? st : issue_ticket(p);
 }
 
 g3_status g3_query(g3_plan p)
@@ -1208,6 +1262,35 @@ g3_status g3_query(g3_plan p)
     if (e == hipErrorNotReady) return G3_EBUSY;
     if (e != hipSuccess) return fail(p, e);
     return G3_OK;
+}
+
+g3_status g3_last_ticket(g3_plan p, uint64_t* ticket)
+{
+    if (!p || !ticket) return G3_EINVAL;
+    *ticket = p->next_ticket - 1;
+    return G3_OK;
+}
+
+g3_status g3_ticket_query(g3_plan p, uint64_t ticket, int32_t* final)
+{
+    if (!p || !final || ticket == 0 || ticket >= p->next_ticket) return G3_EINVAL;
+    *final = 0;
+    if (ticket <= p->final_upto) {
+        *final = 1;
+        return G3_OK;
+    }
+    for (const auto& t : p->tickets) {
+        if (t.id != ticket) continue;
+        const hipError_t e = hipEventQuery(t.ev);
+        if (e == hipErrorNotReady) return G3_EBUSY;
+        if (e != hipSuccess) return fail(p, e);
+        int ok = p->sticky == G3_OK ? 1 : 0;
+        for (int i = 0; i < t.n && ok; ++i)
+            if (p->flag_host[t.off + i]) ok = 0;
+        *final = ok;
+        return G3_OK;
+    }
+    return G3_EINVAL;
 }
 
 g3_status g3_sync(g3_plan p)

@@ -77,6 +77,8 @@ def lib():
         "g3_normalize3": ([P, I32, I32, I32, D, I64, I32, P, P], I32),
         "g3_sync": ([P], I32),
         "g3_query": ([P], I32),
+        "g3_last_ticket": ([P, C.POINTER(C.c_uint64)], I32),
+        "g3_ticket_query": ([P, C.c_uint64, C.POINTER(I32)], I32),
         "g3_hist_len": ([I32, I32], C.c_size_t),
         "g3_check_args": ([I32, P, D, I32, I32], I32),
         "g3_thresholds": ([D, I32, P], I32),
@@ -295,6 +297,22 @@ class Plan:
             return False
         _check(st, "g3_query")
         return True
+
+    def last_ticket(self) -> int:
+        """Ticket of the latest accumulate call (g3_last_ticket)."""
+        t = C.c_uint64()
+        _check(lib().g3_last_ticket(self._h, C.byref(t)), "g3_last_ticket")
+        return int(t.value)
+
+    def ticket_query(self, ticket: int):
+        """None while the call runs; then True if its histograms are final,
+        False if g3_sync must run first (g3_ticket_query)."""
+        fin = C.c_int32()
+        st = int(lib().g3_ticket_query(self._h, C.c_uint64(int(ticket)), C.byref(fin)))
+        if st == EBUSY:
+            return None
+        _check(st, "g3_ticket_query")
+        return bool(fin.value)
 
     def sync_status(self) -> int:
         return int(lib().g3_sync(self._h))

@@ -11,7 +11,11 @@ its histogram and its share of the neighbour pool -- fits the HBM budget; a
 request that does not fit waits until finished requests free their memory.
 A request's frames and histogram stay resident on the device from admission
 to completion; completion is the moment its histogram is visible in host
-memory, and latency runs from its arrival to that moment.
+memory, and latency runs from its arrival to that moment.  Completion is
+seen per request, without draining the stream: the histogram is copied to the
+host behind the batch that finished it, and the batch's completion ticket
+(``g3_ticket_query``) says whether that copy is final; only a request one of
+whose frames the library must recompute (``g3_sync``) waits for the device.
 
 The scheduler talks to an executor: :class:`GpuExecutor` drives libg3
 through ``g3.Plan`` (all arithmetic runs in the HIP library); tests substitute
@@ -48,6 +52,9 @@ class Request:
     dev_hist: object = None
     next_frame: int = 0
     nbytes: int = 0
+    ticket: int = 0
+    fetch: object = None
+    fetch_ev: object = None
 
     @property
     def n_frames(self) -> int:
@@ -92,15 +99,21 @@ class GpuExecutor:
         t = self.torch
         host = t.from_numpy(np.ascontiguousarray(frames, dtype=np.int32)).pin_memory()
         dev = host.to(self.device, non_blocking=True)
-        self._host[id(dev)] = host           # keep the pinned source alive until synced
+        self._host[id(dev)] = host           # keep the pinned source alive until released
         return dev
 
     def new_hist(self, n: int):
         t = self.torch
         return t.zeros(n, dtype=t.uint64, device=self.device)
 
-    def accumulate_batch(self, systems: list[dict]):
+    def accumulate_batch(self, systems: list[dict]) -> int:
+        """Queue one batched call; returns its completion ticket."""
         self.plan.accumulate_batch(systems)
+        return self.plan.last_ticket()
+
+    def ticket_final(self, ticket: int):
+        """None while the call runs, then whether its histograms are final."""
+        return self.plan.ticket_query(ticket)
 
     def start_fetch(self, hist):
         t = self.torch
@@ -122,22 +135,32 @@ class GpuExecutor:
         ev.record()
         return ev
 
+    def device_used(self) -> int:
+        """Device memory in use on the whole device (bytes), measured."""
+        free, total = self.torch.cuda.mem_get_info(self.device)
+        return int(total - free)
+
 
 class Server:
     """Iteration-level continuous batching."""
 
     def __init__(self, hbm_budget_bytes: int = 8 << 30, frames_per_iter: int = 4,
-                 max_in_flight: int = 2, executor=None):
+                 max_in_flight: int = 2, executor=None, plan_reserve_bytes: int = 0):
         self.ex = executor if executor is not None else GpuExecutor()
         self.budget = int(hbm_budget_bytes)
+        # device memory the plan keeps besides the requests' shares (partial
+        # slots, tables, flag log), held back from the budget
+        self.reserve = int(plan_reserve_bytes)
         self.frames_per_iter = int(frames_per_iter)
         self.max_in_flight = int(max_in_flight)
         self.queue: collections.deque[Request] = collections.deque()
         self.active: list[Request] = []
         self.in_flight: collections.deque = collections.deque()
+        self.finishing: collections.deque[Request] = collections.deque()
         self.used = 0
         self.peak_used = 0
         self.iterations = 0
+        self.syncs = 0
         self.completed: list[Request] = []
         self._next_rid = 0
         self.t0 = time.perf_counter()
@@ -159,7 +182,7 @@ class Server:
         if fr.min() < 0 or np.any(fr >= lo):
             raise g3.G3Error(g3.EDOMAIN, f"request {req.rid}")
         req.nbytes = footprint_bytes(req, self.frames_per_iter)
-        if req.nbytes > self.budget:
+        if req.nbytes + self.reserve > self.budget:
             raise g3.G3Error(g3.ENOMEM, f"request {req.rid} exceeds the HBM budget")
         self.queue.append(req)
 
@@ -184,7 +207,7 @@ class Server:
         return req.result
 
     def _admit(self):
-        while self.queue and self.used + self.queue[0].nbytes <= self.budget:
+        while self.queue and self.reserve + self.used + self.queue[0].nbytes <= self.budget:
             req = self.queue.popleft()
             req.dev_frames = self.ex.upload(req.frames)
             req.dev_hist = self.ex.new_hist(g3.hist_len(req.nbins, req.layout))
@@ -197,7 +220,6 @@ class Server:
         self.used -= req.nbytes
         self.ex.release(req.dev_frames, req.dev_hist)
         req.dev_frames = req.dev_hist = None
-        self.active.remove(req)
         self.completed.append(req)
 
     # -- one iteration ---------------------------------------------------------
@@ -212,36 +234,68 @@ class Server:
             if b == req.n_frames:
                 done_now.append(req)
         try:
-            self.ex.accumulate_batch(systems)
+            ticket = self.ex.accumulate_batch(systems)
         except Exception:
             for req in list(self.active):     # nothing of this batch was queued
                 req.status = g3.EDEVICE
                 req.done = self.now()
+                self.active.remove(req)
                 self._release(req)
             raise
         self.iterations += 1
-        if not done_now:
-            self.in_flight.append(self.ex.record())
-            return
-        # A finished request's histogram is final only after g3_sync: a frame
-        # whose scratch overflowed is recomputed there from its device frames.
-        tokens = [self.ex.start_fetch(req.dev_hist) for req in done_now]
-        st = self.ex.sync()
-        self.in_flight.clear()
-        t = self.now()
-        for req, tok in zip(done_now, tokens):
+        # A finishing request's histogram is copied to the host behind this
+        # batch (stream order); it is final once the batch's ticket says so.
+        for req in done_now:
+            self.active.remove(req)
+            req.ticket = ticket
+            req.fetch = self.ex.start_fetch(req.dev_hist)
+            self.finishing.append(req)
+        ev = self.ex.record()
+        for req in done_now:
+            req.fetch_ev = ev
+        self.in_flight.append(ev)
+
+    def _complete(self) -> bool:
+        """Complete the finishing requests whose copies have landed, in
+        stream order; g3_sync runs only for a request with a flagged frame
+        (then every finishing copy is taken again after it)."""
+        did = False
+        while self.finishing and self.finishing[0].fetch_ev.query():
+            req = self.finishing[0]
+            fin = self.ex.ticket_final(req.ticket)
+            if fin is None:       # (its copy landed, so the batch has finished)
+                break
+            st = g3.OK
+            if not fin:
+                # a frame of this request is recomputed (or an error is
+                # reported) by g3_sync; copies taken before it are stale
+                st = self.ex.sync()
+                self.syncs += 1
+                self.in_flight.clear()
+                for r in self.finishing:
+                    r.fetch = self.ex.start_fetch(r.dev_hist)
+                ev = self.ex.record()
+                for r in self.finishing:
+                    r.fetch_ev = ev
+                ev.synchronize()
+            self.finishing.popleft()
             req.status = st
-            req.done = t
-            req.result = self.ex.finish_fetch(tok)
+            req.result = self.ex.finish_fetch(req.fetch)
+            req.fetch = None
+            req.done = self.now()
             self._release(req)
-        if st != g3.OK:
-            raise g3.G3Error(st, "serving batch")
+            did = True
+            if st != g3.OK:
+                raise g3.G3Error(st, f"request {req.rid}")
+        return did
 
     def step(self) -> bool:
-        """Admit what fits and enqueue one iteration if there is work and room
-        in flight.  Returns True if it did anything."""
+        """Complete what has landed, admit what fits and enqueue one
+        iteration if there is work and room in flight.  Returns True if it
+        did anything."""
         while self.in_flight and self.in_flight[0].query():
             self.in_flight.popleft()
+        did = self._complete()
         self._admit()
         if self.active and len(self.in_flight) < self.max_in_flight:
             self._iterate()
@@ -249,10 +303,13 @@ class Server:
         if self.in_flight:
             self.in_flight[0].synchronize()
             return True
-        return False
+        return did
+
+    def pending(self) -> bool:
+        return bool(self.queue or self.active or self.in_flight or self.finishing)
 
     def drain(self):
-        while self.queue or self.active or self.in_flight:
+        while self.pending():
             if not self.step():
                 break
         st = self.ex.sync()
@@ -260,25 +317,36 @@ class Server:
             raise g3.G3Error(st, "serving batch")
 
     # -- open-loop driver --------------------------------------------------------
-    def run_open_loop(self, requests: list[Request]) -> dict:
+    def run_open_loop(self, requests: list[Request], sample_device=False) -> dict:
         """Serve requests whose ``arrival`` times (seconds from start) form an
-        open-loop schedule.  Returns latency and throughput statistics."""
+        open-loop schedule.  Returns latency and throughput statistics (with
+        ``sample_device``, also the device memory in use, measured after each
+        iteration, above what was in use at the start)."""
         pending = sorted(requests, key=lambda r: r.arrival)
         self.t0 = time.perf_counter()
+        base = self.ex.device_used() if sample_device else 0
+        dev_peak = 0
         i = 0
-        while i < len(pending) or self.queue or self.active or self.in_flight:
+        while i < len(pending) or self.pending():
             now = self.now()
             while i < len(pending) and pending[i].arrival <= now:
                 self.submit(pending[i])
                 i += 1
+            it = self.iterations
             if self.step():
+                if sample_device and self.iterations != it:
+                    dev_peak = max(dev_peak, self.ex.device_used() - base)
                 continue
             if i < len(pending):
                 time.sleep(max(0.0, min(pending[i].arrival - self.now(), 0.001)))
         st = self.ex.sync()
         if st != g3.OK:
             raise g3.G3Error(st, "serving batch")
-        return summarize(requests, self.now(), self.iterations, self.peak_used)
+        out = summarize(requests, self.now(), self.iterations, self.peak_used)
+        out["syncs"] = self.syncs
+        if sample_device:
+            out["device_peak_bytes"] = int(dev_peak)
+        return out
 
 
 def summarize(requests: list[Request], wall: float, iterations: int, peak_used: int = 0) -> dict:

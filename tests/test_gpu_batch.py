@@ -1,0 +1,125 @@
+"""GPU: the batched form on the uneven-systems workload at its configured
+size against the oracle, the autotuner, and per-call completion tickets."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_1708_08619_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def g3mod():
+    from paper_1708_08619_amd import g3
+    g3.lib()
+    return g3
+
+
+def _dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+
+
+def _systems(g3, ws, dev):
+    return [dict(frames=_dev(w.frames, dev), box=w.box, rmax=w.rmax, nbins=w.nbins,
+                 layout=w.layout, hist=g3.new_hist(w.nbins, w.layout, dev)) for w in ws]
+
+
+def test_uneven_batch_full_size_matches_oracle(g3mod, torch_dev, oracle_mod):
+    """8 systems, N log-uniform in 512..32768, densities 0.7-0.9, 8 jittered
+    FCC frames each, rmax 2.5 sigma, 50 bins, full layout: one batched call
+    (the frame x atom flattening of Sec. 3.2 applied to g3), every system's
+    histogram equal to the oracle's, bin for bin."""
+    ws = synth.uneven_batch()
+    assert len(ws) == 8 and all(w.frames.shape[0] == 8 for w in ws)
+    with g3mod.Plan() as plan:
+        systems = _systems(g3mod, ws, torch_dev)
+        plan.accumulate_batch(systems)
+        plan.sync()
+        for w, s in zip(ws, systems):
+            got = s["hist"].cpu().numpy().astype(np.uint64)
+            want = oracle_mod.hist(w.frames, w.box, w.rmax, w.nbins, w.layout)
+            assert np.array_equal(got, want), w.name
+
+
+def test_autotune_picks_from_grid_and_stays_exact(g3mod, torch_dev, oracle_mod):
+    """The autotuner returns a tuning from its grid (workgroups per CU,
+    centres per item, all or 3/4 of the LDS histogram), never writes the
+    callers' histograms, and the chosen tuning reproduces the oracle."""
+    rng = np.random.default_rng(31)
+    ws = []
+    for s in range(4):
+        N = int(round(np.exp(rng.uniform(np.log(400), np.log(3000)))))
+        fr, box = synth.jittered_fcc(N, float(rng.uniform(0.7, 0.9)), 0.1, 2, [91, s])
+        ws.append(synth.Workload(f"t{s}", fr, box, 2.5 * 4096, 50, s % 2))
+    with g3mod.Plan() as plan:
+        systems = _systems(g3mod, ws, torch_dev)
+        best = plan.autotune(systems)
+        for s in systems:
+            assert int(s["hist"].count_nonzero().item()) == 0
+        assert best["wg_per_cu"] in (1, 2)
+        assert best["centres_per_item"] in (256, 512, 1024, 2048)
+        # the LDS sizes on the grid: all of what fits beside the item arrays, or 3/4
+        probe = g3mod.Plan()
+        probe.set_tuning(wg_per_cu=best["wg_per_cu"], centres_per_item=best["centres_per_item"])
+        full = probe.get_tuning()["lds_hist_bins"]
+        probe.close()
+        assert best["lds_hist_bins"] in (full, (full * 3 // 4) & ~63), (best, full)
+        assert plan.get_tuning()["lds_hist_bins"] == best["lds_hist_bins"]
+        # a second call with the same workload returns the cached tuning
+        assert plan.autotune(systems) == best
+        plan.accumulate_batch(systems)
+        plan.sync()
+        for w, s in zip(ws, systems):
+            got = s["hist"].cpu().numpy().astype(np.uint64)
+            assert np.array_equal(got, oracle_mod.hist(w.frames, w.box, w.rmax, w.nbins, w.layout))
+
+
+def test_tickets(g3mod, torch_dev, oracle_mod):
+    """g3_ticket_query: final once an ordinary call has run; not final for a
+    call with a frame to recompute until g3_sync has run; unknown tickets are
+    rejected."""
+    import torch
+    w = synth.lj_small("fcc", n_frames=2)
+    rng = np.random.default_rng(4)
+    box = [200000] * 3
+    pos = np.stack([rng.integers(0, L, size=1200) for L in box])
+    pos[:, :600] = (np.array(box) // 2)[:, None] + rng.integers(-900, 900, size=(3, 600))
+    dense = pos[None].astype(np.int32)
+    with g3mod.Plan() as plan:
+        assert plan.last_ticket() == 0
+        h = g3mod.new_hist(w.nbins, w.layout, torch_dev)
+        plan.accumulate_batch([dict(frames=_dev(w.frames, torch_dev), box=w.box, rmax=w.rmax,
+                                    nbins=w.nbins, layout=w.layout, hist=h)])
+        t1 = plan.last_ticket()
+        assert t1 == 1
+        torch.cuda.synchronize()
+        assert plan.ticket_query(t1) is True
+        assert np.array_equal(h.cpu().numpy().astype(np.uint64),
+                              oracle_mod.hist(w.frames, w.box, w.rmax, w.nbins, w.layout))
+        hd = g3mod.new_hist(20, 0, torch_dev)
+        plan.accumulate_batch([dict(frames=_dev(dense, torch_dev), box=box, rmax=2500.0, nbins=20,
+                                    layout=0, hist=hd)])
+        t2 = plan.last_ticket()
+        assert t2 == 2
+        torch.cuda.synchronize()
+        assert plan.ticket_query(t2) is False      # the frame awaits g3_sync's recomputation
+        assert plan.ticket_query(t1) is True
+        plan.sync()
+        assert plan.ticket_query(t2) is True
+        assert np.array_equal(hd.cpu().numpy().astype(np.uint64),
+                              oracle_mod.hist(dense, box, 2500.0, 20, 0))
+        with pytest.raises(g3mod.G3Error):
+            plan.ticket_query(3)
+        with pytest.raises(g3mod.G3Error):
+            plan.ticket_query(0)

@@ -19,13 +19,23 @@ class _Done:
 
 
 class OracleExecutor:
-    """Executes batches with the oracle; device buffers are numpy arrays."""
+    """Executes batches with the oracle; device buffers are numpy arrays.
 
-    def __init__(self, oracle_mod, fail_on_call=None):
+    ``late`` names frames counts (by request frames' identity, see
+    ``late_ids``) that a batch leaves out and ``sync`` adds afterwards, the
+    way the library recomputes a flagged frame in g3_sync: a batch holding
+    such a frame gets a ticket that is not final, and a histogram copied
+    before the sync misses those counts."""
+
+    def __init__(self, oracle_mod, fail_on_call=None, late_ids=()):
         self.o = oracle_mod
         self.calls = 0
         self.fail_on_call = fail_on_call
         self.live = 0
+        self.late_ids = set(late_ids)
+        self.withheld = []          # (hist, counts) added by the next sync
+        self.tickets = {}           # ticket -> final
+        self.syncs = 0
 
     def upload(self, frames):
         self.live += 1
@@ -38,8 +48,19 @@ class OracleExecutor:
         self.calls += 1
         if self.fail_on_call == self.calls:
             raise RuntimeError("injected executor failure")
+        final = True
         for s in systems:
-            s["hist"] += self.o.hist(s["frames"], s["box"], s["rmax"], s["nbins"], s["layout"])
+            h = self.o.hist(s["frames"], s["box"], s["rmax"], s["nbins"], s["layout"])
+            if s.get("tag") in self.late_ids:
+                self.withheld.append((s["hist"], h))
+                final = False
+            else:
+                s["hist"] += h
+        self.tickets[self.calls] = final
+        return self.calls
+
+    def ticket_final(self, ticket):
+        return self.tickets[ticket]
 
     def start_fetch(self, hist):
         return hist.copy()
@@ -51,6 +72,12 @@ class OracleExecutor:
         self.live -= 1
 
     def sync(self):
+        self.syncs += 1
+        for h, add in self.withheld:
+            h += add
+        self.withheld.clear()
+        for t in self.tickets:
+            self.tickets[t] = True
         return g3.OK
 
     def record(self):
@@ -136,3 +163,37 @@ def test_future_api(oracle_mod):
     ha = srv.result(fa)
     assert np.array_equal(ha, oracle_mod.hist(a_fr, a_box, 2.0 * 4096, 40, g3.HALF))
     assert fa.rid != fb.rid and srv.used == 0
+
+
+def test_recomputed_frames_are_in_the_result(oracle_mod, monkeypatch):
+    """A batch whose ticket is not final (a frame the library recomputes in
+    g3_sync) must not complete a request from a copy taken before the sync:
+    the server syncs, copies again, and every result equals the oracle."""
+    reqs = _requests(6, seed=11)
+    late = {reqs[2].rid, reqs[4].rid}
+    ex = OracleExecutor(oracle_mod, late_ids=late)
+    srv = serve.Server(1 << 30, frames_per_iter=2, executor=ex)
+    orig = srv._iterate
+
+    def tagged():
+        # tag each system with its request so the executor can hold it back
+        real = ex.accumulate_batch
+
+        def acc(systems):
+            for s, r in zip(systems, list(srv.active)):
+                s["tag"] = r.rid
+            return real(systems)
+        ex.accumulate_batch = acc
+        try:
+            orig()
+        finally:
+            ex.accumulate_batch = real
+    monkeypatch.setattr(srv, "_iterate", tagged)
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    assert ex.syncs >= 1 and srv.syncs >= 1
+    for r in reqs:
+        want = oracle_mod.hist(r.frames, r.box, r.rmax, r.nbins, r.layout)
+        assert np.array_equal(r.result, want), r.rid
+    assert srv.used == 0 and ex.live == 0
