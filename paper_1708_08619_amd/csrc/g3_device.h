@@ -26,8 +26,10 @@ static_assert((uint64_t)kSafeItemCentres * kListCap * (kListCap - 1) / 2 <= 0xFF
               "a safe pass keeps every uint32 LDS counter exact");
 constexpr int kTabBytes = 8192;        // LDS bytes of the bin lookup table
 constexpr int kWave = 64;
+constexpr int kNbinsMax = 160;         // G3_MAX_NBINS
 constexpr int kPoolPad = 8;          // entries after each frame's pool slot that unrolled reads may touch
 constexpr int kCursorStride = 32;   // uint32 words between per-frame pool cursors (one 128 B line each)
+constexpr int kOvfWord = 1;         // word of a frame's cursor line counting its overflow cells
 
 // Per-frame status bits (one uint32 per frame and system).
 constexpr uint32_t kFlagDomain = 1u;   // coordinate outside [0, L)
@@ -86,6 +88,11 @@ struct Sys {
     int64_t pool_cap;        // entries per frame slot (the slot stride is pool_cap + kPoolPad)
     int32_t per_frame;       // 1: every frame has its own scratch; 0: reused
     uint32_t* flags;         // [F] (always per frame)
+    // per-wave build: the stencil of every cell, relative to the cell's
+    // midpoint, fits int16 (pk_ok); cells it leaves to the general build are
+    // listed here ([ncell] per frame, count in the frame's cursor line)
+    int32_t pk_ok;
+    int32_t* ovf_cells;
 };
 
 struct Job {
@@ -157,14 +164,22 @@ void launch_cell_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, h
 void launch_cell_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s);
 void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
 size_t nbr_build_lds_bytes();
+// General build over every cell of every job, or (list) over the cells the
+// per-wave build left in each frame's overflow list.
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
-                      bool one_step, hipStream_t s);
+                      bool one_step, bool list, hipStream_t s);
+// Per-wave build (narrow entries): a wave stages one cell's stencil, at most
+// stage_cap atoms, as packed int16 coordinates and builds its centres' lists.
+constexpr int kWaveBuildWaves = 8;
+size_t nbr_wave_lds_bytes(int stage_cap);
+void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool one_step,
+                     int stage_cap, hipStream_t s);
 // Bin lookups of the triplet kernel: u8 table then threshold steps (loop or
 // one step), or the step table.
 enum Lookup : int { kLookupSteps = 0, kLookupOneStep = 1, kLookupStepTable = 2 };
 void launch_triplet(const TripletArgs& a, bool wide, int lookup, bool padded, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
 void launch_expand(const Sys* sys, int n_sys, int max_nbins, hipStream_t s);
-hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes);
+hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes, size_t wave_build_bytes);
 
 }  // namespace g3

@@ -26,6 +26,7 @@ using namespace g3;
 constexpr int kTabMax = kTabBytes;   // bytes of the bin lookup table in LDS
 constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
 constexpr size_t kLdsPerCU = 160 * 1024;
+constexpr int kWaveStageMax = 1024;    // largest stencil a wave of the per-wave build stages
 
 #define G3_TRY_HIP(expr)                         \
     do {                                         \
@@ -94,6 +95,7 @@ struct Geometry {
     std::vector<uint8_t> tab;
     std::vector<uint32_t> step;
     std::vector<int> slab_lo;  // n_slabs + 1 boundaries
+    int pk_ok = 0;             // the per-wave build applies (stencil fits int16)
 };
 
 g3_status check(int32_t n_atoms, const int32_t box[3], double rmax, int32_t nbins, int32_t layout)
@@ -407,6 +409,7 @@ struct Prepared {
     size_t off_cell_count, off_cell_start, off_atom_cell, off_atom_rank, off_sorted, off_nbr_off,
         off_nbr_cnt, off_cursor, off_slab_j, off_pool, off_thr, off_tab, off_step;
     size_t off_tri;          // triangle-once counts (half layout, uint64), if tri_once
+    size_t off_ovf;          // cells left to the general build, [F][ncell]
     bool tri_once;
     int64_t pool_cap;
     int per_frame;
@@ -430,6 +433,15 @@ g3_status prepare(const g3_system& s, int hb_max, Prepared& P)
     // 16-bit entries need every accepted third-side component in int16
     g.wide = g.C3 > 32767 ? 1 : 0;
     plan_cells(g);
+    // The per-wave build stages a stencil relative to the home cell's
+    // midpoint as int16: every atom of the 3 x 3 x 3 cells lies within 1.5
+    // cell widths (+ 1 unit of rounding) of it; the margin covers the
+    // midpoint's rounding.
+    g.pk_ok = !g.wide && g.C <= 32767;
+    for (int d = 0; d < 3; ++d) {
+        const double w = (double)g.box[d] / (double)g.nc[d];
+        if (g.nc[d] < 3 || !(1.5 * w + 8.0 <= 32767.0)) g.pk_ok = 0;
+    }
     if (!plan_slabs(g, hb_max)) return G3_EINVAL;
     P.in = s;
     return G3_OK;
@@ -464,6 +476,7 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         P.off_nbr_cnt = o;    o = align_up(o + F * N * 4, 256);
         P.off_cursor = o;     o = align_up(o + (size_t)std::max(P.in.n_frames, 1) * kCursorStride * 4, 256);
         P.off_slab_j = o;     o = align_up(o + F * N * (S + 1) * 2, 256);
+        P.off_ovf = o;        o = align_up(o + F * g.ncell * 4, 256);
         P.off_thr = o;        o = align_up(o + (g.nb3 + 1) * 4, 256);
         P.off_tab = o;        o = align_up(o + g.tab_len, 256);
         P.off_step = o;       o = align_up(o + g.step.size() * 4, 256);
@@ -588,7 +601,46 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
     s.pool_cap = P.pool_cap;
     s.per_frame = P.per_frame;
     s.flags = flags;
+    s.pk_ok = g.pk_ok;
+    s.ovf_cells = reinterpret_cast<int32_t*>(arena + P.off_ovf);
     return s;
+}
+
+// Neighbour build of a group: the per-wave build when some system qualifies
+// (then the general build over the cells it left), else the general build.
+// The wave's stage capacity covers the largest expected stencil with room
+// for fluctuations (a larger cell goes to the general build).
+struct BuildPlan {
+    bool wave = false;
+    int cap = 0;
+};
+
+BuildPlan plan_build(const std::vector<Prepared>& ps)
+{
+    BuildPlan b;
+    double t_max = 0;
+    for (const auto& P : ps) {
+        if (!P.g.pk_ok) continue;
+        b.wave = true;
+        const double per_cell = (double)P.g.N / (double)P.g.ncell;
+        t_max = std::max(t_max, per_cell * (P.tri_once ? 14.0 : 27.0));
+    }
+    if (b.wave) {
+        const int want = (int)std::ceil(1.3 * t_max + 64.0);
+        b.cap = std::min(kWaveStageMax, std::max(256, (want + 63) & ~63));
+    }
+    return b;
+}
+
+void launch_build(const Sys* dsys, const Job* djobs, int nj, int max_cells, bool wide, bool one_step,
+                  const BuildPlan& bp, hipStream_t sm)
+{
+    if (bp.wave) {
+        launch_nbr_wave(dsys, djobs, nj, max_cells, one_step, bp.cap, sm);
+        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, true, sm);
+    } else {
+        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, false, sm);
+    }
 }
 
 // Partial slots of one triplet launch.  A workgroup flushes its slab at
@@ -763,7 +815,7 @@ g3_status upload_geometry(g3_plan p, const std::vector<Prepared>& ps)
 g3_status set_lds_limits(g3_plan p)
 {
     if (p->lds_set) return G3_OK;
-    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_build_lds_bytes()));
+    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_build_lds_bytes(), nbr_wave_lds_bytes(kWaveStageMax)));
     p->lds_set = true;
     return G3_OK;
 }
@@ -794,6 +846,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     const Prepared& P = ps[0];
     const int F = s.n_frames;
     Sys sys = make_sys(P, (char*)p->arena, flags, tn.cb);
+    const BuildPlan bp = plan_build(ps);
     std::vector<Job> jobs(F);
     for (int f = 0; f < F; ++f) jobs[f] = {0, f};
     std::vector<Seg> segs;
@@ -845,7 +898,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
         launch_cell_count(dsys, j, 1, N, p->stream);
         launch_cell_scan(dsys, j, 1, p->stream);
         launch_cell_scatter(dsys, j, 1, N, p->stream);
-        launch_nbr_build(dsys, j, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, p->stream);
+        launch_build(dsys, j, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, bp, p->stream);
         launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
         if (tri.second > tri.first)
             launch_zero_u32((uint32_t*)((char*)p->arena + tri.first), (tri.second - tri.first) / 4, p->stream);
@@ -916,6 +969,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             padded = padded && pads_rejected(P.g);
         }
         const int lookup = step_ok ? kLookupStepTable : one_step ? kLookupOneStep : kLookupSteps;
+        const BuildPlan bp = plan_build(ps);
         const int n_wg = p->n_cu * tn.wg_per_cu;
         const int max_slots = slot_count(n_wg, (int)segs.size(), tn.hb_max, tn.slot_limit);
         const size_t o_sys = 0, o_jobs = align_up(sizeof(Sys) * sys.size(), 256),
@@ -943,6 +997,8 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         put(&one_step, sizeof(one_step));
         put(&lookup, sizeof(lookup));
         put(&padded, sizeof(padded));
+        put(&bp.wave, sizeof(bp.wave));
+        put(&bp.cap, sizeof(bp.cap));
         // tuning fields one by one (the struct's padding bytes are undefined)
         const int32_t tk[5] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0, tn.slot_limit};
         put(tk, sizeof(tk));
@@ -997,7 +1053,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_count(dsys, djobs, nj, max_n, sm);
             launch_cell_scan(dsys, djobs, nj, sm);
             launch_cell_scatter(dsys, djobs, nj, max_n, sm);
-            launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, sm);
+            launch_build(dsys, djobs, nj, max_cells, wide, one_step, bp, sm);
             launch_triplet(a, wide, lookup, padded, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
             if (any_tri) launch_expand(dsys, n_sys, max_nb, sm);
@@ -1009,7 +1065,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_count(dsys, djobs, nj, max_n, p->stream);
             launch_cell_scan(dsys, djobs, nj, p->stream);
             launch_cell_scatter(dsys, djobs, nj, max_n, p->stream);
-            launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, p->stream);
+            launch_build(dsys, djobs, nj, max_cells, wide, one_step, bp, p->stream);
             hipEvent_t e0;
             timing_begin(p, &e0);
             launch_triplet(a, wide, lookup, padded, n_wg, p->stream);

@@ -12,6 +12,8 @@
 // LDS counters uint32, output uint64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "g3_device.h"
 
 namespace g3 {
@@ -255,7 +257,7 @@ constexpr uint32_t kChunk = kBuildChunk;
 // CU: the build is latency-bound, and its few spills sit outside the pass-1 loop.
 template <bool WIDE, bool ONE_STEP>
 __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __restrict__ sys,
-                                                             const Job* __restrict__ jobs)
+                                                             const Job* __restrict__ jobs, int list)
 {
     using E = typename std::conditional<WIDE, int4, uint2>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -337,12 +339,17 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
     const int nst = (2 * rx + 1) * (2 * ry + 1) * (2 * rz + 1);
     const int home = nst / 2;   // (0,0,0) sits in the middle of the odd stencil grid
 
+    // The cells to build: all of the frame's, or (list) those the per-wave
+    // build left in the frame's overflow list.
+    const int n_items = list ? (int)gp(S.cursor)[(size_t)f * kCursorStride + kOvfWord] : ncell;
+    const gptr<const int32_t> items = gp(S.ovf_cells + fr_off(S, f, ncell));
     // A cell's atom range and, in wave 0 (lane e: stencil offset e), its
     // stencil cells' index, start, end and periodic shift are loaded one cell
     // ahead, while the previous cell is processed.
     int p_c0 = 0, p_c1 = 0, p_c = 0x7fffffff, p_a = 0, p_e = 0, p_sx = 0, p_sy = 0, p_sz = 0;
-    auto fetch_cell = [&](int cl) {
-        if (cl >= ncell) return;
+    auto fetch_cell = [&](int k) {
+        if (k >= n_items) return;
+        const int cl = list ? items[k] : k;
         p_c0 = cs[cl];
         p_c1 = cs[cl + 1];
         if (wave == 0) {
@@ -364,10 +371,10 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
     };
     fetch_cell(blockIdx.x);
 
-    for (int cell = blockIdx.x; cell < ncell; cell += gridDim.x) {
+    for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
         const int c0 = p_c0, c1 = p_c1;
         const int c = p_c, a = p_a, e_end = p_e, shx = p_sx, shy = p_sy, shz = p_sz;
-        fetch_cell(cell + gridDim.x);
+        fetch_cell(k + gridDim.x);
         if (c0 == c1) continue;   // uniform over the workgroup
         // stencil table: lane e of wave 0 takes stencil offset e; the home
         // cell goes to position 0, the kept others follow in lane order (the
@@ -699,6 +706,378 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
         __syncthreads();
         flush_g2();
     }
+}
+
+// ------------------------------------------------------------------ per-wave neighbours
+// For narrow entries on a grid of >= 3 cells per axis whose stencil, taken
+// relative to the home cell's midpoint, fits int16 (host: 1.5 cell widths
+// plus a margin below 32767 units on every axis).  Every wave builds its own
+// cells with its own stencil in LDS, so the main loop has no workgroup
+// barrier:
+//   the stencil (home cell first, then the kept neighbour cells, each atom
+//   with its cell's periodic shift and the midpoint subtracted) is staged as
+//   packed int16 coordinates (x | y << 16, z), followed by kStagePad
+//   sentinel atoms at -32768 on every axis;
+//   pass 1 tests 64 candidates per step: two saturating packed subtractions
+//   and two clamped dot products give s = |d|^2, where a component beyond
+//   int16 or a sum beyond int32 saturates to a value >= R2 (C <= 32767) and an
+//   accepted s is exact; the sentinels are rejected by every centre, so no
+//   bounds test is needed; the accepted staged indices are compacted
+//   (ballot + mbcnt) into an index list as long as the stencil;
+//   pass 2 forms the entries -- the packed difference IS the entry's first
+//   word -- with their pair bins and r12 slabs, and writes the list
+//   partitioned by slab exactly as the general build does.
+// A cell whose stencil exceeds the wave's stage capacity, and every cell of a
+// system without pk_ok, is appended to the frame's overflow list; the
+// general build then runs on those cells only.
+namespace {
+
+constexpr int kStagePad = 64;
+constexpr uint32_t kWaveShared = 4 * kThrMax + 8192 + 256;   // thr, bin table, bin -> slab
+
+struct WaveLds {   // byte offsets inside one wave's LDS region
+    uint32_t stage, idx, scnt, g2, pre, start, offx, offy, offz, size;
+};
+
+__host__ __device__ inline WaveLds wave_lds(int cap)
+{
+    WaveLds w;
+    uint32_t o = 0;
+    w.stage = o; o += (uint32_t)(cap + kStagePad) * 8u;
+    w.idx = o;   o += ((uint32_t)cap * 2u + 15u) & ~15u;
+    w.scnt = o;  o += 64u * 4u;
+    w.g2 = o;    o += (uint32_t)kNbinsMax * 4u;
+    w.pre = o;   o += 32u * 4u;
+    w.start = o; o += 32u * 4u;
+    w.offx = o;  o += 32u * 4u;
+    w.offy = o;  o += 32u * 4u;
+    w.offz = o;  o += 32u * 4u;
+    w.size = o;
+    return w;
+}
+
+typedef short short2p __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ short2p as_s2(uint32_t v) { return __builtin_bit_cast(short2p, v); }
+__device__ __forceinline__ uint32_t as_u32(short2p v) { return __builtin_bit_cast(uint32_t, v); }
+
+}  // namespace
+
+template <bool ONE_STEP>
+__global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys* __restrict__ sys,
+                                                                   const Job* __restrict__ jobs,
+                                                                   int cap)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                    // [kThrMax]
+    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + kThrMax);           // [8192]
+    uint8_t* s_slab = s_tab + 8192;                                          // [256] bin -> slab
+    const WaveLds WL = wave_lds(cap);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    unsigned char* wb = smem + kWaveShared + (size_t)wave * WL.size;
+    uint2* stage = reinterpret_cast<uint2*>(wb + WL.stage);
+    uint16_t* idx = reinterpret_cast<uint16_t*>(wb + WL.idx);
+    uint32_t* scnt = reinterpret_cast<uint32_t*>(wb + WL.scnt);
+    uint32_t* g2w = reinterpret_cast<uint32_t*>(wb + WL.g2);
+    int32_t* st_pre = reinterpret_cast<int32_t*>(wb + WL.pre);
+    int32_t* st_start = reinterpret_cast<int32_t*>(wb + WL.start);
+    int32_t* st_ox = reinterpret_cast<int32_t*>(wb + WL.offx);
+    int32_t* st_oy = reinterpret_cast<int32_t*>(wb + WL.offy);
+    int32_t* st_oz = reinterpret_cast<int32_t*>(wb + WL.offz);
+
+    const Job jb = jobs[blockIdx.y];
+    const Sys& S = sys[jb.sys];
+    const int f = jb.frame, N = S.N;
+    if (gp(S.flags)[f] & kFlagDomain) return;   // uniform over the workgroup
+    const int ncx = S.nc[0], ncy = S.nc[1], ncz = S.nc[2], ncell = S.ncell;
+    const int Lx = S.box[0], Ly = S.box[1], Lz = S.box[2];
+    const gptr<const int32_t> cs = gp(S.cell_start + fr_off(S, f, ncell + 1));
+    const gptr<const int32_t> X = gp(S.sorted + fr_off(S, f, (size_t)3 * N));
+    const gptr<const int32_t> Y = X + N;
+    const gptr<const int32_t> Z = Y + N;
+    const uint32_t R2 = S.R2;
+    const int sh = S.sh, nb = S.nbins, n_slabs = S.n_slabs, nb3 = S.nb3;
+    const int tbits = S.tab_bits;
+    const int64_t pool_cap = S.pool_cap;
+    const gptr<uint32_t> flags = gp(S.flags + f);
+    const gptr<uint32_t> cursor = gp(S.cursor + (size_t)f * kCursorStride);
+    const gptr<int32_t> ovf = gp(S.ovf_cells + fr_off(S, f, ncell));
+    const gptr<uint32_t> nbr_off = gp(S.nbr_off + fr_off(S, f, N));
+    const gptr<uint32_t> nbr_cnt = gp(S.nbr_cnt + fr_off(S, f, N));
+    const gptr<uint16_t> slab_j = gp(S.slab_j + fr_off(S, f, (size_t)N * (n_slabs + 1)));
+    const size_t pbase = S.per_frame ? (size_t)f * (size_t)(pool_cap + kPoolPad) : 0;
+    const gptr<uint2> pool = gp(reinterpret_cast<uint2*>(S.pool) + pbase);
+    uint64_t* const pair_hist = S.pair_hist;
+    const bool tri_once = S.tri != nullptr;
+    const uint32_t pair_inc = tri_once ? 2u : 1u;
+
+    // bin tables and the bin -> slab map, once per workgroup
+    for (int x = tid; x <= nb3; x += kWaveBuildWaves * 64) s_thr[x] = gp(S.thr)[x];
+    {
+        const int n4 = (S.tab_len + 3) / 4;
+        const gptr<const uint32_t> src = gp(reinterpret_cast<const uint32_t*>(S.tab));
+        for (int x = tid; x < n4; x += kWaveBuildWaves * 64) reinterpret_cast<uint32_t*>(s_tab)[x] = src[x];
+    }
+    for (int b = tid; b < 256; b += kWaveBuildWaves * 64) {
+        int q = 0;
+        while (q + 1 < n_slabs && S.slab_lo[q + 1] <= b) ++q;
+        s_slab[b] = (uint8_t)q;
+    }
+    for (int b = lane; b < kNbinsMax; b += 64) g2w[b] = 0u;
+    __syncthreads();   // the only workgroup barrier: waves work alone from here
+
+    uint32_t g2_pending = 0;   // increments held in this wave's pair counters
+    auto flush_g2 = [&]() {
+        wave_sync();
+        for (int b = lane; b < nb; b += 64) {
+            const uint32_t v = g2w[b];
+            if (v) {
+                __hip_atomic_fetch_add(gp(reinterpret_cast<unsigned long long*>(pair_hist + b)),
+                                       (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                g2w[b] = 0u;
+            }
+        }
+        wave_sync();
+        g2_pending = 0;
+    };
+    auto push_ovf = [&](int cell) {
+        if (lane == 0) {
+            const uint32_t k = __hip_atomic_fetch_add(cursor + kOvfWord, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            ovf[k] = cell;   // each cell is listed at most once: k < ncell
+        }
+    };
+    auto bin_of = [&](uint32_t s) -> int {
+        int b;
+        if constexpr (ONE_STEP) {
+            b = s_tab[__builtin_amdgcn_ubfe(s, (uint32_t)sh, (uint32_t)tbits)];
+            b += (s >= s_thr[b + 1]) ? 1 : 0;
+        } else {
+            b = s_tab[s >> sh];
+            while (s >= s_thr[b + 1]) ++b;
+        }
+        return b;
+    };
+    const uint2 pad_e = make_uint2(0x80008000u, 0x00008000u);   // pad entry after every list
+    uint32_t chunk_base = 0, chunk_left = 0;   // this wave's slice of the frame's pool
+
+    for (int cell = blockIdx.x * kWaveBuildWaves + wave; cell < ncell;
+         cell += gridDim.x * kWaveBuildWaves) {
+        const int c0 = __builtin_amdgcn_readfirstlane(cs[cell]);
+        const int c1 = __builtin_amdgcn_readfirstlane(cs[cell + 1]);
+        if (c0 == c1) continue;
+        if (!S.pk_ok) {
+            push_ovf(cell);
+            continue;
+        }
+        // stencil: lane e < 27 takes offset e; the home cell (e = 13) goes to
+        // position 0, the kept others follow in lane order
+        const int kx = cell % ncx, ky = (cell / ncx) % ncy, kz = cell / (ncx * ncy);
+        // the home cell's midpoint (any point within a unit or two will do:
+        // the host bound leaves a margin)
+        const int refx = (int)((double)(2 * kx + 1) * (double)Lx / (double)(2 * ncx));
+        const int refy = (int)((double)(2 * ky + 1) * (double)Ly / (double)(2 * ncy));
+        const int refz = (int)((double)(2 * kz + 1) * (double)Lz / (double)(2 * ncz));
+        int ce = 0x7fffffff, ae = 0, ne = 0, ox = 0, oy = 0, oz = 0;
+        if (lane < 27) {
+            int x = kx + lane % 3 - 1, y = ky + (lane / 3) % 3 - 1, z = kz + lane / 9 - 1;
+            int sx = 0, sy = 0, sz = 0;
+            if (x < 0) { x += ncx; sx = -Lx; } else if (x >= ncx) { x -= ncx; sx = Lx; }
+            if (y < 0) { y += ncy; sy = -Ly; } else if (y >= ncy) { y -= ncy; sy = Ly; }
+            if (z < 0) { z += ncz; sz = -Lz; } else if (z >= ncz) { z -= ncz; sz = Lz; }
+            ce = (z * ncy + y) * ncx + x;
+            ae = cs[ce];
+            ne = cs[ce + 1] - ae;
+            ox = sx - refx; oy = sy - refy; oz = sz - refz;
+        }
+        const bool other = lane < 27 && lane != 13 && (!tri_once || ce > cell);
+        const uint64_t om = __ballot(other);
+        const int n_keep = 1 + (int)__popcll(om);
+        int pos = -1;
+        if (lane == 13) pos = 0;
+        if (other) pos = 1 + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32),
+                                 __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
+        if (pos >= 0) {
+            st_start[pos] = ae;
+            st_ox[pos] = ox; st_oy[pos] = oy; st_oz[pos] = oz;
+            st_pre[pos] = ne;
+        }
+        wave_sync();
+        const int v = lane < n_keep ? st_pre[lane] : 0;
+        wave_sync();
+        int incl = v;
+#pragma unroll
+        for (int d = 1; d < 32; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        if (lane < n_keep) st_pre[lane] = incl - v;
+        const int T = __builtin_amdgcn_readfirstlane(__shfl(incl, n_keep - 1, 64));
+        if (T > cap) {          // stencil too large for this wave: general build
+            push_ovf(cell);
+            continue;
+        }
+        wave_sync();
+        for (int t = lane; t < T + kStagePad; t += 64) {
+            uint2 e = pad_e;      // sentinel: -32768 on every axis
+            if (t < T) {
+                int r = 0;
+#pragma unroll
+                for (int step = 16; step >= 1; step >>= 1)
+                    if (r + step < n_keep && st_pre[r + step] <= t) r += step;
+                const int j = st_start[r] + (t - st_pre[r]);
+                const int x = X[j] + st_ox[r], y = Y[j] + st_oy[r], z = Z[j] + st_oz[r];
+                e = make_uint2(((uint32_t)x & 0xffffu) | ((uint32_t)y << 16), (uint32_t)z & 0xffffu);
+            }
+            stage[t] = e;
+        }
+        wave_sync();
+
+        const int Tu = T;
+        for (int ci = c0; ci < c1; ++ci) {
+            const int tself = ci - c0;      // the home cell is staged first, in cell order
+            const uint2 cc = stage[tself];
+            const short2p cxy = as_s2(cc.x), cz = as_s2(cc.y);
+            // |d|^2 of staged atom t from the centre, saturated; the packed
+            // differences are returned for the entry
+            auto dist = [&](const uint2 e, short2p& dxy, short2p& dz) -> uint32_t {
+                dxy = __builtin_elementwise_sub_sat(as_s2(e.x), cxy);
+                dz = __builtin_elementwise_sub_sat(as_s2(e.y), cz);
+                return (uint32_t)__builtin_amdgcn_sdot2(dz, dz, __builtin_amdgcn_sdot2(dxy, dxy, 0, true), true);
+            };
+            // Pass 1: test and compact the accepted staged indices (with
+            // the triangle-once lists every candidate ranks above the centre;
+            // otherwise the centre itself is excluded)
+            uint32_t n = 0;
+            auto pass1 = [&](auto TRI) {
+                auto accept = [&](int t) -> bool {
+                    short2p dxy, dz;
+                    const bool ok = dist(stage[t], dxy, dz) < R2;
+                    if constexpr (decltype(TRI)::value) return ok;
+                    else return ok && t != tself;
+                };
+                auto push = [&](bool ok, int t) {
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(ok);
+                    const uint32_t p = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, n));
+                    if (ok) idx[p] = (uint16_t)t;
+                    n += (uint32_t)__popcll(m);
+                };
+                int t0 = decltype(TRI)::value ? tself + 1 : 0;
+                for (; t0 + 64 < Tu; t0 += 128) {
+                    const bool oa = accept(t0 + lane);
+                    const bool ob = accept(t0 + 64 + lane);
+                    push(oa, t0 + lane);
+                    push(ob, t0 + 64 + lane);
+                }
+                if (t0 < Tu) push(accept(t0 + lane), t0 + lane);
+            };
+            if (tri_once) pass1(std::true_type{});
+            else pass1(std::false_type{});
+            wave_sync();
+            // entry, pair bin and slab of accepted index e (slab via q)
+            auto entry = [&](uint32_t e, int& b) -> uint2 {
+                short2p dxy, dz;
+                const uint32_t s = dist(stage[idx[e]], dxy, dz);
+                b = bin_of(s);
+                return make_uint2(as_u32(dxy), (as_u32(dz) & 0xffffu) | ((uint32_t)__mul24(b, nb3) << 16));
+            };
+            if (n > (uint32_t)S.m_safe && lane == 0)
+                __hip_atomic_fetch_or(flags, kFlagDense, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (pair_hist) {
+                if (g2_pending + n * pair_inc > 0x7fff0000u) flush_g2();
+                g2_pending += n * pair_inc;
+            }
+            // bump-allocate the list and its pad entries from the wave's chunk
+            const uint32_t nres = n ? n + (uint32_t)kListPad : 0u;
+            if (nres > chunk_left) {
+                const uint32_t want = nres > kChunk ? nres : kChunk;
+                uint32_t got = 0;
+                if (lane == 0) got = __hip_atomic_fetch_add(cursor, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                chunk_base = __shfl(got, 0, 64);
+                chunk_left = want;
+            }
+            const uint32_t base = chunk_base;
+            chunk_base += nres;
+            chunk_left -= nres;
+            const bool fits = (int64_t)base + nres <= pool_cap;
+            if (!fits && lane == 0)
+                __hip_atomic_fetch_or(flags, kFlagPool, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (n <= 64u && n_slabs <= kSplitSlabs) {
+                // one sweep in registers: a ballot per slab gives every entry
+                // its slab-partitioned position and lane q the boundary J_q
+                const bool act = (uint32_t)lane < n;
+                uint32_t q = 0xffu;
+                uint2 ent = pad_e;
+                if (act) {
+                    int b;
+                    ent = entry((uint32_t)lane, b);
+                    q = s_slab[b];
+                    if (pair_hist) atomicAdd(&g2w[b], pair_inc);
+                }
+                if (!fits) continue;
+                uint32_t J = 0, epos = 0, jlane = 0;
+                for (int qq = 0; qq < n_slabs; ++qq) {
+                    const bool mine = q == (uint32_t)qq;
+                    const uint64_t mk = __ballot(mine);
+                    if (lane == qq) jlane = J;
+                    if (mine) epos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mk, J));
+                    J += (uint32_t)__popcll(mk);
+                }
+                if (lane == n_slabs) jlane = J;   // = n
+                if (lane <= n_slabs) slab_j[(size_t)ci * (n_slabs + 1) + lane] = (uint16_t)jlane;
+                if (n && (uint32_t)lane < n + (uint32_t)kListPad)
+                    gstore(pool + (base + (act ? epos : (uint32_t)lane)), act ? ent : pad_e);
+                if (n + (uint32_t)kListPad > 64u && (uint32_t)lane < n + (uint32_t)kListPad - 64u)
+                    gstore(pool + (base + 64u + lane), pad_e);
+                if (lane == 0) {
+                    nbr_off[ci] = base;
+                    nbr_cnt[ci] = n;
+                }
+                continue;
+            }
+            // longer list (or many slabs): count the slabs in LDS, scan, then
+            // form the entries again and write each at its slab's cursor
+            scnt[lane] = 0u;
+            wave_sync();
+            for (uint32_t e = lane; e < n; e += 64) {
+                int b;
+                (void)entry(e, b);
+                atomicAdd(&scnt[s_slab[b]], 1u);
+                if (pair_hist) atomicAdd(&g2w[b], pair_inc);
+            }
+            wave_sync();
+            if (!fits) continue;
+            {
+                const uint32_t v = lane < n_slabs ? scnt[lane] : 0u;
+                uint32_t x = v;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t y = __shfl_up(x, d, 64);
+                    if (lane >= d) x += y;
+                }
+                const uint32_t J = x - v;       // lane n_slabs gets the total n
+                if (lane <= n_slabs) slab_j[(size_t)ci * (n_slabs + 1) + lane] = (uint16_t)J;
+                wave_sync();
+                if (lane < n_slabs) scnt[lane] = J;
+                wave_sync();
+            }
+            const gptr<uint2> P = pool + base;
+            if (n && lane < kListPad) gstore(P + (n + lane), pad_e);
+            for (uint32_t e = lane; e < n; e += 64) {
+                int b;
+                const uint2 ent = entry(e, b);
+                gstore(P + atomicAdd(&scnt[s_slab[b]], 1u), ent);
+            }
+            if (lane == 0) {
+                nbr_off[ci] = base;
+                nbr_cnt[ci] = n;
+            }
+            wave_sync();
+        }
+    }
+    if (pair_hist && g2_pending) flush_g2();
 }
 
 // ------------------------------------------------------------------ triplets
@@ -1508,22 +1887,43 @@ size_t nbr_build_lds_bytes()
 }
 
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
-                      bool one_step, hipStream_t s)
+                      bool one_step, bool list, hipStream_t s)
 {
     // enough workgroups per frame to fill the chip, each looping over cells
-    const int per_job = build_wgs_per_job(n_jobs, max_cells);
+    // (over the overflow list: a few per frame, most of which find it empty)
+    const int per_job = list ? std::max(1, std::min(8, 2048 / std::max(n_jobs, 1)))
+                             : build_wgs_per_job(n_jobs, max_cells);
     const size_t lds = nbr_build_lds_bytes();
     const dim3 g(per_job, n_jobs), b(kBuildThreads);
+    const int lm = list ? 1 : 0;
     if (wide) {
-        if (one_step) hipLaunchKernelGGL((k_nbr_build<true, true>), g, b, lds, s, sys, jobs);
-        else hipLaunchKernelGGL((k_nbr_build<true, false>), g, b, lds, s, sys, jobs);
+        if (one_step) hipLaunchKernelGGL((k_nbr_build<true, true>), g, b, lds, s, sys, jobs, lm);
+        else hipLaunchKernelGGL((k_nbr_build<true, false>), g, b, lds, s, sys, jobs, lm);
     } else {
-        if (one_step) hipLaunchKernelGGL((k_nbr_build<false, true>), g, b, lds, s, sys, jobs);
-        else hipLaunchKernelGGL((k_nbr_build<false, false>), g, b, lds, s, sys, jobs);
+        if (one_step) hipLaunchKernelGGL((k_nbr_build<false, true>), g, b, lds, s, sys, jobs, lm);
+        else hipLaunchKernelGGL((k_nbr_build<false, false>), g, b, lds, s, sys, jobs, lm);
     }
 }
 
-hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
+size_t nbr_wave_lds_bytes(int stage_cap)
+{
+    return kWaveShared + (size_t)kWaveBuildWaves * wave_lds(stage_cap).size;
+}
+
+void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool one_step,
+                     int stage_cap, hipStream_t s)
+{
+    // about two rounds of resident workgroups over the whole batch; a wave
+    // takes cells blockIdx.x * 8 + wave + k * gridDim.x * 8
+    const int cells_wg = (max_cells + kWaveBuildWaves - 1) / kWaveBuildWaves;
+    const int per_job = std::max(1, std::min(cells_wg, 1024 / std::max(n_jobs, 1)));
+    const size_t lds = nbr_wave_lds_bytes(stage_cap);
+    const dim3 g(per_job, n_jobs), b(kWaveBuildWaves * 64);
+    if (one_step) hipLaunchKernelGGL((k_nbr_wave<true>), g, b, lds, s, sys, jobs, stage_cap);
+    else hipLaunchKernelGGL((k_nbr_wave<false>), g, b, lds, s, sys, jobs, stage_cap);
+}
+
+hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes, size_t wave_build_bytes)
 {
     const void* trip[9] = {
         (const void*)k_triplet<false, 0, false>, (const void*)k_triplet<false, 1, false>,
@@ -1544,6 +1944,10 @@ hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes)
                             (const void*)k_nbr_build<true, false>, (const void*)k_nbr_build<true, true>};
     for (const void* k : build)
         if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)build_bytes)))
+            return e;
+    const void* wave[2] = {(const void*)k_nbr_wave<false>, (const void*)k_nbr_wave<true>};
+    for (const void* k : wave)
+        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wave_build_bytes)))
             return e;
     return hipSuccess;
 }

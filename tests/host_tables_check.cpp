@@ -5,7 +5,10 @@
 //   * the u8 table gives a lower bound, within one step when one_step is set;
 //   * the step table, when built, gives b(s) exactly.
 // Then the pad entries after each neighbour list: where the host lets the
-// triplet kernel read them, no row accepts them.
+// triplet kernel read them, no row accepts them.  Then the per-wave build's
+// int16 staging: wherever the host sets pk_ok, every coordinate of a cell's
+// 3 x 3 x 3 stencil (periodic shift applied) minus the kernel's midpoint
+// reference fits int16, and the sentinel atoms are rejected by every centre.
 // Exit status: the number of geometries with a failure.
 #include "../paper_1708_08619_amd/csrc/g3_host.cpp"
 
@@ -15,11 +18,13 @@ void launch_cell_count(const Sys*, const Job*, int, int, hipStream_t) {}
 void launch_cell_scan(const Sys*, const Job*, int, hipStream_t) {}
 void launch_cell_scatter(const Sys*, const Job*, int, int, hipStream_t) {}
 size_t nbr_build_lds_bytes() { return 0; }
-void launch_nbr_build(const Sys*, const Job*, int, int, bool, bool, hipStream_t) {}
+void launch_nbr_build(const Sys*, const Job*, int, int, bool, bool, bool, hipStream_t) {}
+size_t nbr_wave_lds_bytes(int) { return 0; }
+void launch_nbr_wave(const Sys*, const Job*, int, int, bool, int, hipStream_t) {}
 void launch_triplet(const TripletArgs&, bool, int, bool, int, hipStream_t) {}
 void launch_reduce(const TripletArgs&, int, int, hipStream_t) {}
 void launch_expand(const Sys*, int, int, hipStream_t) {}
-hipError_t set_kernel_lds_limits(size_t, size_t) { return hipSuccess; }
+hipError_t set_kernel_lds_limits(size_t, size_t, size_t) { return hipSuccess; }
 }  // namespace g3
 
 int main()
@@ -95,5 +100,61 @@ int main()
                     (unsigned long long)accepted);
         if (padded != c.padded || accepted) ++failed;
     }
+
+    // Per-wave build: for boxes and cutoffs around the bound, every cell k of
+    // an axis with cells k-1, k, k+1 (wrapped, shifted by the box) staged
+    // relative to the reference the kernel uses.  A cell k' holds the
+    // integers x with floor(x nc / L) = k'.
+    struct Ax { int L; double rmax; } axes[] = {
+        {174356, 12288.0}, {28016, 10240.0}, {65600, 21000.0}, {65536, 21844.0}, {70000, 23000.0},
+        {100003, 20000.0}, {43000, 14300.0}, {2000000, 21840.0}, {1000, 300.0}, {90, 29.0},
+        {65490, 21800.0}, {65520, 21800.0}};
+    int staged_ok = 0;
+    for (const Ax& a : axes) {
+        Geometry g;
+        g.N = 1 << 20;
+        g.nbins = 10;
+        g.nb3 = 10;
+        g.box[0] = g.box[1] = g.box[2] = a.L;
+        g.C = (int)std::ceil(a.rmax);
+        plan_bins(g, a.rmax);
+        g.wide = g.C3 > 32767 ? 1 : 0;
+        plan_cells(g);
+        g.pk_ok = !g.wide && g.C <= 32767;
+        for (int d = 0; d < 3; ++d) {
+            const double w = (double)g.box[d] / (double)g.nc[d];
+            if (g.nc[d] < 3 || !(1.5 * w + 8.0 <= 32767.0)) g.pk_ok = 0;
+        }
+        const int nc = g.nc[0], L = a.L;
+        int64_t worst = 0, home = 0;
+        bool bad = false;
+        if (g.pk_ok) {
+            auto lo_of = [&](int64_t k) { return (k * L + nc - 1) / nc; };   // least x in cell k
+            for (int k = 0; k < nc; ++k) {
+                const int ref = (int)((double)(2 * k + 1) * (double)L / (double)(2 * nc));
+                for (int o = -1; o <= 1; ++o) {
+                    int kk = k + o, shift = 0;
+                    if (kk < 0) { kk += nc; shift = -L; } else if (kk >= nc) { kk -= nc; shift = L; }
+                    const int64_t x0 = lo_of(kk), x1 = lo_of(kk + 1) - 1;
+                    for (int64_t x : {x0, x1}) {
+                        if ((x * nc) / L != kk) bad = true;     // the cell bounds themselves
+                        const int64_t rel = x + shift - ref;
+                        worst = std::max<int64_t>(worst, rel < 0 ? -rel : rel);
+                        if (o == 0) home = std::max<int64_t>(home, rel < 0 ? -rel : rel);
+                    }
+                }
+            }
+            // sentinel -32768 against any centre of the home cell: at least
+            // 32768 - |c| per component (saturation only raises it)
+            const int64_t dmin = 32768 - std::min<int64_t>(home, 32767);
+            const int64_t s = std::min<int64_t>(3 * dmin * dmin, 0x7fffffff);
+            if (worst > 32767 || (uint64_t)s < g.R2) bad = true;
+            staged_ok += 1;
+        }
+        std::printf("stage: L %d rmax %.1f cells %d pk_ok %d worst |rel| %lld (home %lld) %s\n", L, a.rmax, nc,
+                    g.pk_ok, (long long)worst, (long long)home, bad ? "FAIL" : "ok");
+        if (bad) ++failed;
+    }
+    if (staged_ok < 6) ++failed;     // the benchmark-like axes must qualify
     return failed;
 }
