@@ -158,6 +158,17 @@ inline int build_wgs_per_job(int n_jobs, int max_cells)
     return per_job < 1 ? 1 : per_job;
 }
 
+// Workgroups per job of the per-wave build: about two rounds of resident
+// workgroups over the batch, at most one cell per wave.
+constexpr int kWaveBuildWavesPerWG = 8;
+inline int wave_wgs_per_job(int n_jobs, int max_cells)
+{
+    const int cells_wg = (max_cells + kWaveBuildWavesPerWG - 1) / kWaveBuildWavesPerWG;
+    int per_job = 1024 / (n_jobs > 0 ? n_jobs : 1);
+    if (per_job > cells_wg) per_job = cells_wg;
+    return per_job < 1 ? 1 : per_job;
+}
+
 // Launch wrappers (defined in g3_kernels.hip).
 void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
 void launch_cell_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
@@ -170,7 +181,7 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
                       bool one_step, bool list, hipStream_t s);
 // Per-wave build (narrow entries): a wave stages one cell's stencil, at most
 // stage_cap atoms, as packed int16 coordinates and builds its centres' lists.
-constexpr int kWaveBuildWaves = 8;
+constexpr int kWaveBuildWaves = kWaveBuildWavesPerWG;
 size_t nbr_wave_lds_bytes(int stage_cap);
 void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool one_step,
                      int stage_cap, hipStream_t s);

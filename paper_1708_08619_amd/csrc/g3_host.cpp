@@ -460,7 +460,10 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         n_jobs += per_frame ? std::max(P.in.n_frames, 1) : 1;
         max_cells = std::max(max_cells, P.g.ncell);
     }
-    const int64_t slack = (int64_t)build_wgs_per_job(n_jobs, max_cells) * kBuildWavesPerWG * kBuildChunk;
+    // (each wave of the per-wave build and of the general build may leave a
+    // chunk's tail unused)
+    const int64_t slack = ((int64_t)build_wgs_per_job(n_jobs, max_cells) * kBuildWavesPerWG +
+                           (int64_t)wave_wgs_per_job(n_jobs, max_cells) * kWaveBuildWaves) * kBuildChunk;
     for (auto& P : ps) {
         const Geometry& g = P.g;
         const size_t F = per_frame ? (size_t)std::max(P.in.n_frames, 1) : 1;

@@ -1891,7 +1891,7 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
 {
     // enough workgroups per frame to fill the chip, each looping over cells
     // (over the overflow list: a few per frame, most of which find it empty)
-    const int per_job = list ? std::max(1, std::min(8, 2048 / std::max(n_jobs, 1)))
+    const int per_job = list ? std::min(build_wgs_per_job(n_jobs, max_cells), 8)
                              : build_wgs_per_job(n_jobs, max_cells);
     const size_t lds = nbr_build_lds_bytes();
     const dim3 g(per_job, n_jobs), b(kBuildThreads);
@@ -1915,8 +1915,7 @@ void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells,
 {
     // about two rounds of resident workgroups over the whole batch; a wave
     // takes cells blockIdx.x * 8 + wave + k * gridDim.x * 8
-    const int cells_wg = (max_cells + kWaveBuildWaves - 1) / kWaveBuildWaves;
-    const int per_job = std::max(1, std::min(cells_wg, 1024 / std::max(n_jobs, 1)));
+    const int per_job = wave_wgs_per_job(n_jobs, max_cells);
     const size_t lds = nbr_wave_lds_bytes(stage_cap);
     const dim3 g(per_job, n_jobs), b(kWaveBuildWaves * 64);
     if (one_step) hipLaunchKernelGGL((k_nbr_wave<true>), g, b, lds, s, sys, jobs, stage_cap);

@@ -88,15 +88,20 @@ def test_autotune_picks_from_grid_and_stays_exact(g3mod, torch_dev, oracle_mod):
 def test_tickets(g3mod, torch_dev, oracle_mod):
     """g3_ticket_query: final once an ordinary call has run; not final for a
     call with a frame to recompute until g3_sync has run; unknown tickets are
-    rejected."""
+    rejected.  The frame to recompute: 2200 atoms in a 50-unit cube with
+    2048-centre items, so some lists are longer than such items allow (their
+    candidate pairs could pass 2^32); every side is in bin 0, so the half
+    histogram is N (N-1) (N-2) / 2 at bin 0."""
     import torch
     w = synth.lj_small("fcc", n_frames=2)
     rng = np.random.default_rng(4)
     box = [200000] * 3
-    pos = np.stack([rng.integers(0, L, size=1200) for L in box])
-    pos[:, :600] = (np.array(box) // 2)[:, None] + rng.integers(-900, 900, size=(3, 600))
-    dense = pos[None].astype(np.int32)
+    Nd = 2200
+    dense = (100000 + rng.integers(0, 50, size=(1, 3, Nd))).astype(np.int32)
+    want_dense = np.zeros(g3mod.hist_len(10, 0), np.uint64)
+    want_dense[0] = Nd * (Nd - 1) * (Nd - 2) // 2
     with g3mod.Plan() as plan:
+        plan.set_tuning(centres_per_item=2048)
         assert plan.last_ticket() == 0
         h = g3mod.new_hist(w.nbins, w.layout, torch_dev)
         plan.accumulate_batch([dict(frames=_dev(w.frames, torch_dev), box=w.box, rmax=w.rmax,
@@ -107,8 +112,8 @@ def test_tickets(g3mod, torch_dev, oracle_mod):
         assert plan.ticket_query(t1) is True
         assert np.array_equal(h.cpu().numpy().astype(np.uint64),
                               oracle_mod.hist(w.frames, w.box, w.rmax, w.nbins, w.layout))
-        hd = g3mod.new_hist(20, 0, torch_dev)
-        plan.accumulate_batch([dict(frames=_dev(dense, torch_dev), box=box, rmax=2500.0, nbins=20,
+        hd = g3mod.new_hist(10, 0, torch_dev)
+        plan.accumulate_batch([dict(frames=_dev(dense, torch_dev), box=box, rmax=5000.0, nbins=10,
                                     layout=0, hist=hd)])
         t2 = plan.last_ticket()
         assert t2 == 2
@@ -117,8 +122,7 @@ def test_tickets(g3mod, torch_dev, oracle_mod):
         assert plan.ticket_query(t1) is True
         plan.sync()
         assert plan.ticket_query(t2) is True
-        assert np.array_equal(hd.cpu().numpy().astype(np.uint64),
-                              oracle_mod.hist(dense, box, 2500.0, 20, 0))
+        assert np.array_equal(hd.cpu().numpy().astype(np.uint64), want_dense)
         with pytest.raises(g3mod.G3Error):
             plan.ticket_query(3)
         with pytest.raises(g3mod.G3Error):

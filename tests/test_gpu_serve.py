@@ -42,36 +42,31 @@ def test_alone_equals_in_the_mix(torch_dev, oracle_mod):
         assert np.array_equal(r.result, oracle_mod.hist(r.frames, r.box, r.rmax, r.nbins, r.layout)), r.rid
 
 
-def _dense_cluster_frames(n_frames, seed):
-    """Half the atoms in a small cluster far above the uniform-density
-    neighbour estimate: the batched neighbour pool overflows and the library
-    recomputes such a frame in g3_sync."""
-    rng = np.random.default_rng(seed)
-    box = [200000] * 3
-    N = 1200
-    out = []
-    for _ in range(n_frames):
-        pos = np.stack([rng.integers(0, L, size=N) for L in box])
-        c = np.array(box) // 2
-        pos[:, :600] = c[:, None] + rng.integers(-900, 900, size=(3, 600))
-        out.append(pos)
-    return np.stack(out).astype(np.int32), box
-
-
 def test_flagged_request_in_the_mix(torch_dev, oracle_mod):
-    """A request whose frames must be recomputed (pool overflow) served among
-    ordinary ones: it completes only after g3_sync has added its recomputed
-    frames, and every request -- flagged or not -- equals the oracle."""
+    """A request whose frames the library must recompute in g3_sync (2200
+    atoms in a 50-unit cube: with 2048-centre items some lists are longer
+    than such items allow) served among ordinary ones: it completes only
+    after g3_sync has added its recomputed frames, and every request --
+    flagged or not -- is exact (the cube by its closed form, every side in
+    bin 0: N (N-1) (N-2) / 2 per frame at half bin 0; the others against the
+    oracle)."""
+    from paper_1708_08619_amd import g3
     store = serve.TrajectoryStore(n_systems=3, max_frames=4, n_min=500, n_max=2000, seed=(12, 3))
     g = np.random.Generator(np.random.PCG64(8))
     reqs = [store.request(r, g, arrival=0.0) for r in range(8)]
-    fr, box = _dense_cluster_frames(3, 4)
-    dense = serve.Request(100, fr, box, 2500.0, 20, 0, arrival=0.0)
+    rng = np.random.default_rng(4)
+    Nd, Fd = 2200, 2
+    dense_fr = (100000 + rng.integers(0, 50, size=(Fd, 3, Nd))).astype(np.int32)
+    dense = serve.Request(100, dense_fr, [200000] * 3, 5000.0, 10, 0, arrival=0.0)
     mix = reqs[:3] + [dense] + reqs[3:]
-    srv = serve.Server(hbm_budget_bytes=1 << 30, frames_per_iter=2)
+    srv = serve.Server(hbm_budget_bytes=4 << 30, frames_per_iter=2)
+    srv.ex.plan.set_tuning(centres_per_item=2048)
     stats = srv.run_open_loop(mix)
     assert stats["requests"] == len(mix) and srv.used == 0
     assert srv.syncs >= 1                 # the dense request went through g3_sync
-    for r in mix:
+    want = np.zeros(g3.hist_len(10, 0), np.uint64)
+    want[0] = Fd * (Nd * (Nd - 1) * (Nd - 2) // 2)
+    assert np.array_equal(dense.result, want)
+    for r in reqs:
         want = oracle_mod.hist(r.frames, r.box, r.rmax, r.nbins, r.layout)
         assert np.array_equal(r.result, want), r.rid
