@@ -7,8 +7,11 @@ pass of the whole hot path (cell build, neighbour lists, triplet binning,
 flush) over all 50 frames.
 
 Reported: the batched form (one hipGraph launch per step) as the headline,
-the plain per-frame form beside it, the triplet kernel's HIP-event duration
-against the int32 VALU roofline, and the CPU oracle on a bounded sample.
+the plain per-frame form beside it, the triplet kernel's and the neighbour
+build's HIP-event durations against the int32 VALU roofline (and the triplet
+kernel against the measured LDS ceilings), the uneven-systems batch, the
+served form (open-loop latency, and closed-loop throughput against plain
+per-request launches), and the CPU oracle on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
 """
@@ -36,6 +39,11 @@ sys.path.insert(0, ROOT)
 # (three triplets binned, added by the expansion).
 OPS_PER_CANDIDATE = 9
 OPS_PER_BINNED = 4
+# Neighbour build: per (centre, stencil atom) pair tested, the same 9 (3 sub,
+# 3 mul, 2 add, 1 compare); per neighbour written: its bin (table + compare:
+# 2), its r12 slab (1) and its list position (1)
+BUILD_OPS_PER_CANDIDATE = 9
+BUILD_OPS_PER_NEIGHBOUR = 4
 # int32 VALU peak of MI355X: 256 CUs x 64 lanes/clk x 2.4 GHz
 INT32_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -63,6 +71,12 @@ def parse():
                     help="skip the replay of the paper's g3 runs (Table 2 shapes)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-systems batch")
+    ap.add_argument("--no-lds", action="store_true", help="skip the LDS rate probe")
+    ap.add_argument("--saturated-requests", type=int, default=300,
+                    help="requests of the closed-loop served run (0 skips it)")
+    ap.add_argument("--cpu1-centres", type=int, default=4096,
+                    help="centres of one frame the single-thread oracle run takes")
     return ap.parse_args()
 
 
@@ -136,7 +150,12 @@ def main():
     plan.kernel_time_reset(True)
     timed(lambda: plan.accumulate_batch([system]), max(3, args.steps // 2), 0)
     kern_ms, kern_n = plan.kernel_time()
+    build_ms, build_n = plan.stage_time(g3.STAGE_NEIGHBOURS)
+    cells_ms, _ = plan.stage_time(g3.STAGE_CELLS)
     cand = plan.candidates() // max(kern_n, 1)
+    b_cand, b_nbrs = plan.build_counts()
+    b_cand //= max(build_n, 1)
+    b_nbrs //= max(build_n, 1)
     plan.kernel_time_reset(False)
 
     plain = None
@@ -159,7 +178,24 @@ def main():
                 "unit": "Tops/s (int32)", "frac": achieved / INT32_VALU_PEAK_TOPS if achieved else None,
                 "traffic": traffic_per_launch(), "traffic_unit": "bytes per launch",
                 "kernel": "k_triplet", "kernel_ms": kern_ms,
-                "candidates_per_launch": cand, "increments_per_launch": increments}
+                "candidates_per_launch": cand, "increments_per_launch": increments,
+                "ops_per_candidate": OPS_PER_CANDIDATE, "ops_per_increment": OPS_PER_BINNED}
+    if not args.no_lds:
+        mark("LDS rate probe")
+        roofline["lds"] = lds_ceiling(g3, cand, increments, kern_ms, tuning["lds_hist_bins"])
+        roofline["valu_ceiling_ms"] = ops / (INT32_VALU_PEAK_TOPS * 1e12) * 1e3
+        lds_ms = roofline["lds"]["ceiling_ms"]
+        roofline["binding"] = "lds" if lds_ms > roofline["valu_ceiling_ms"] else "valu"
+        roofline["frac_of_binding"] = max(lds_ms, roofline["valu_ceiling_ms"]) / kern_ms
+    b_ops = BUILD_OPS_PER_CANDIDATE * b_cand + BUILD_OPS_PER_NEIGHBOUR * b_nbrs
+    b_ach = b_ops / (build_ms * 1e-3) / 1e12 if build_ms > 0 else None
+    roofline_build = {"bound": "alu", "achieved": b_ach, "peak": INT32_VALU_PEAK_TOPS,
+                      "unit": "Tops/s (int32)", "frac": b_ach / INT32_VALU_PEAK_TOPS if b_ach else None,
+                      "kernel": "neighbour build (k_nbr_wave + k_nbr_build over its overflow cells)",
+                      "kernel_ms": build_ms, "candidates_per_launch": b_cand,
+                      "neighbours_per_launch": b_nbrs,
+                      "ops_per_candidate": BUILD_OPS_PER_CANDIDATE,
+                      "ops_per_neighbour": BUILD_OPS_PER_NEIGHBOUR, "cell_build_ms": cells_ms}
 
     # the paper's enumeration (every centre's unordered pairs) for comparison
     per_centre = None
@@ -182,15 +218,24 @@ def main():
         mark("paper-shape replay: water N = 6720, 13440, 26880, 10 frames, rmax = L/4")
         paper_shapes = paper_shape_replay(torch, dev)
 
+    uneven = None
+    if not args.no_uneven:
+        mark("uneven-systems batch: 8 systems, N log-uniform 512..32768, 8 frames each")
+        uneven = uneven_bench(torch, dev, args.steps)
+
     served = None
     if args.serve_requests > 0:
         mark(f"served: {args.serve_requests} requests at {args.serve_rate}/s, two budgets")
         served = serve_bench(args.serve_requests, args.serve_rate)
+    if args.saturated_requests > 0:
+        mark(f"served, closed loop: {args.saturated_requests} requests against plain launches")
+        served = served or {}
+        served["saturated"] = saturated_bench(torch, dev, args.saturated_requests)
 
     cpu = None
     if not args.no_cpu:
         mark("cpu baseline (oracle)")
-        cpu = cpu_baseline(w, args.cpu_frames)
+        cpu = cpu_baseline(w, args.cpu_frames, args.cpu1_centres)
 
     line = {
         "metric": "G triplets binned/s at N=65536 (plain vs batched); p50/p99 served latency",
@@ -211,16 +256,30 @@ def main():
         "per_centre_enumeration": per_centre,
         "served": served,
         "paper_shapes": paper_shapes,
+        "uneven_batch": uneven,
         "roofline": roofline,
+        "roofline_neighbour_build": roofline_build,
         "cpu_baseline": cpu,
     }
     plan.close()
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(w, n_frames: int):
-    """The oracle (plain C, OpenMP over centres, untuned) on a bounded
-    sample of the same workload: its first ``n_frames`` frames, all centres."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, n_frames: int, centres_1t: int):
+    """The oracle (plain C, OpenMP over centres, untuned) on bounded samples
+    of the same workload: its first ``n_frames`` frames with every centre on
+    all host threads, and the first ``centres_1t`` centres of frame 0 on one
+    thread.  Triplets binned of a centre sample = its unordered pairs."""
     import oracle
     oracle.lib()
     nt = oracle.max_threads()
@@ -229,10 +288,130 @@ def cpu_baseline(w, n_frames: int):
     H = oracle.hist_full(w.frames[:n_frames], w.box, w.rmax, w.nbins, n_threads=nt)
     dt = time.perf_counter() - t0
     binned = int(H.sum()) // 2                  # unordered pairs = half-layout total
+    c1 = max(1, min(centres_1t, w.n_atoms))
+    t0 = time.perf_counter()
+    H1 = oracle.hist_full(w.frames[:1], w.box, w.rmax, w.nbins, n_threads=1,
+                          centres=np.arange(c1, dtype=np.int32))
+    dt1 = time.perf_counter() - t0
+    binned1 = int(H1.sum()) // 2
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
     return {"value": binned / dt / 1e9, "unit": "G triplets binned/s", "cores": nt,
-            "kind": "oracle", "seconds": dt,
+            "kind": "oracle", "seconds": dt, "cpu_model": cpu_model(), "cpus_available": avail,
             "sample": f"frames 0..{n_frames - 1} of {w.n_frames}, all {w.n_atoms} centres "
-                      f"({binned} triplets binned)"}
+                      f"({binned} triplets binned), {nt} threads",
+            "single_thread": {"value": binned1 / dt1 / 1e9, "unit": "G triplets binned/s",
+                              "cores": 1, "seconds": dt1,
+                              "sample": f"frame 0, centres 0..{c1 - 1} ({binned1} triplets binned)"}}
+
+
+def lds_ceiling(g3, candidates: int, increments: int, kern_ms: float, slab_words: int):
+    """LDS time the triplet kernel cannot go below: per candidate one random
+    bin-table read (the step table, 2048 words) and one increment -- at a
+    random slab word if the candidate is accepted, at the lane's own trash
+    word if not -- priced at the measured rates of each pattern."""
+    table_words = 2048
+    r = {"add_lane": g3.lds_rate(g3.LDS_ADD_LANE, 16 * 64),
+         "add_random": g3.lds_rate(g3.LDS_ADD_RANDOM, slab_words),
+         "read_random": g3.lds_rate(g3.LDS_READ_RANDOM, table_words),
+         "read_add_random": g3.lds_rate(g3.LDS_READ_ADD, slab_words)}
+    rejected = max(candidates - increments, 0)
+    t = candidates / r["read_random"] + increments / r["add_random"] + rejected / r["add_lane"]
+    return {"rates_lane_ops_per_s": r, "slab_words": slab_words, "table_words": table_words,
+            "ceiling_ms": t * 1e3, "frac": t * 1e3 / kern_ms if kern_ms > 0 else None,
+            "model": "candidates/read_random + increments/add_random + rejected/add_lane"}
+
+
+def uneven_bench(torch, dev, steps: int):
+    """The batched-systems workload: 8 systems (N log-uniform 512..32768,
+    densities 0.7-0.9, jittered FCC, 8 frames each, rmax 2.5 sigma, 50 bins,
+    full layout) in one batched call (graph replays) against the plain form
+    (per system, per-frame launches), frames resident in HBM."""
+    from paper_1708_08619_amd import g3, synth
+    ws = synth.uneven_batch()
+    systems = [dict(frames=torch.from_numpy(w.frames).to(dev), box=w.box, rmax=w.rmax,
+                    nbins=w.nbins, layout=w.layout, hist=g3.new_hist(w.nbins, w.layout, dev))
+               for w in ws]
+    with g3.Plan() as plan:
+        plan.autotune(systems)
+        plan.accumulate_batch(systems)
+        plan.sync()
+        binned = sum(int(s["hist"].sum().item()) // 2 for s in systems)   # full layout: ordered
+
+        def run(fn, reps):
+            fn()
+            plan.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            plan.sync()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        reps = max(5, steps)
+        tb = run(lambda: plan.accumulate_batch(systems), reps)
+
+        def plain():
+            for s in systems:
+                plan.accumulate(s["frames"], s["box"], s["rmax"], s["nbins"], s["layout"], s["hist"])
+        tp = run(plain, max(3, reps // 2))
+        tuning = plan.get_tuning()
+    return {"systems": [int(w.n_atoms) for w in ws], "frames_per_system": 8,
+            "triplets_binned": binned, "batched": {"value": binned / tb / 1e9, "ms": tb * 1e3},
+            "plain": {"value": binned / tp / 1e9, "ms": tp * 1e3}, "unit": "G triplets binned/s",
+            "tuning": tuning}
+
+
+def saturated_bench(torch, dev, n_requests: int):
+    """Served throughput with the server saturated (every request arrives at
+    t = 0) against plain per-request launches (g3_accumulate per request, one
+    after another on one stream), on the same requests; both take each
+    request's frames from pinned host memory and return its histogram to host
+    memory."""
+    from paper_1708_08619_amd import g3, serve
+    store = serve.TrajectoryStore(n_systems=16, max_frames=20, n_min=1024, n_max=65536)
+    reqs0 = serve.poisson_requests(store, n_requests, 1e9)
+    out = {"requests": n_requests, "workload": "frames U{1..20}, N log-uniform 1024..65536, "
+           "rmax in {2.0, 2.5, 3.0} sigma, dr 0.05 sigma, jittered FCC rho U(0.7,0.9), all at t=0"}
+    binned = None
+    for fpi in (4, 8):
+        reqs = serve.poisson_requests(store, n_requests, 1e9)
+        for r in reqs:
+            r.arrival = 0.0
+        srv = serve.Server(hbm_budget_bytes=16 << 30, frames_per_iter=fpi, max_in_flight=3)
+        srv.run_open_loop(serve.poisson_requests(store, 8, 1e9, seed=(1, 2)))   # warm-up
+        srv.iterations, srv.peak_used, srv.syncs = 0, 0, 0
+        st = srv.run_open_loop(reqs, sample_device=True)
+        binned = st["triplets_binned"]
+        out[f"served_fpi{fpi}"] = {k: st[k] for k in ("throughput_G_per_s", "requests_per_s", "p50_ms",
+                                                      "p99_ms", "iterations", "syncs",
+                                                      "device_peak_bytes", "peak_hbm_bytes")}
+        del srv
+    # plain: per request H2D, g3_accumulate (per-frame launches), D2H
+    with g3.Plan() as plan:
+        def plain_all():
+            res = []
+            for r in reqs0:
+                host = torch.from_numpy(np.ascontiguousarray(r.frames)).pin_memory()
+                fr = host.to(dev, non_blocking=True)
+                h = g3.new_hist(r.nbins, r.layout, dev)
+                plan.accumulate(fr, r.box, r.rmax, r.nbins, r.layout, h)
+                res.append(h.to("cpu", non_blocking=True))
+            plan.sync()
+            torch.cuda.synchronize()
+            return res
+        plain_all()                              # warm-up (scratch, allocator)
+        t0 = time.perf_counter()
+        res = plain_all()
+        tp = time.perf_counter() - t0
+        pb = sum(int(h.sum().item()) // (2 if r.layout == g3.FULL else 1) for h, r in zip(res, reqs0))
+    out["plain_per_request"] = {"throughput_G_per_s": pb / tp / 1e9, "seconds": tp,
+                                "triplets_binned": pb}
+    out["served_triplets_binned"] = binned
+    return out
 
 
 # The paper's Table 2 (g3, 10 frames, times in seconds including file reading):
@@ -279,7 +458,11 @@ def paper_shape_replay(torch, dev):
 
 def serve_bench(n_requests: int, rate_hz: float):
     """Open-loop Poisson request stream served by continuous batching; p50/p99
-    latency (arrival -> histogram in host memory) at two HBM budgets."""
+    latency (arrival -> histogram in host memory) at two HBM budgets.  The
+    budget holds the requests' frames, histograms and neighbour-pool shares
+    plus a reserve for the plan's own scratch (partial slots capped to fit
+    it, tables, flag log); the device memory actually in use above the
+    start is measured after every iteration."""
     from paper_1708_08619_amd import serve
     store = serve.TrajectoryStore(n_systems=16, max_frames=20, n_min=1024, n_max=65536)
     out = {"rate_hz": rate_hz, "workload": "frames U{1..20}, N log-uniform 1024..65536, "
@@ -287,14 +470,20 @@ def serve_bench(n_requests: int, rate_hz: float):
     for name, budget, fpi in (("budget_8GiB", 8 << 30, 2), ("budget_256MiB", 256 << 20, 2)):
         reqs = serve.poisson_requests(store, n_requests, rate_hz)
         warm = serve.poisson_requests(store, 8, 1e6, seed=(1, 2))
-        srv = serve.Server(hbm_budget_bytes=budget, frames_per_iter=fpi)
+        reserve = min(48 << 20, budget // 4)
+        srv = serve.Server(hbm_budget_bytes=budget, frames_per_iter=fpi, plan_reserve_bytes=reserve)
+        # partial slots: at most 2/3 of the reserve (the rest: tables, flags)
+        slot_bytes = 4 * srv.ex.plan.get_tuning()["lds_hist_bins"]
+        srv.ex.plan.set_tuning(slot_limit=max(64, (reserve * 2 // 3) // slot_bytes))
         srv.run_open_loop(warm)                 # library scratch and allocator warm-up
-        srv.iterations, srv.peak_used = 0, 0
-        st = srv.run_open_loop(reqs)
+        srv.iterations, srv.peak_used, srv.syncs = 0, 0, 0
+        st = srv.run_open_loop(reqs, sample_device=True)
         out[name] = {k: st[k] for k in ("requests", "p50_ms", "p99_ms", "mean_ms", "max_ms",
                                         "throughput_G_per_s", "requests_per_s", "iterations",
-                                        "peak_hbm_bytes")}
+                                        "peak_hbm_bytes", "device_peak_bytes", "syncs")}
         out[name]["frames_per_iter"] = fpi
+        out[name]["plan_reserve_bytes"] = reserve
+        del srv
     return out
 
 

@@ -261,17 +261,48 @@ g3_status g3_get_tuning(g3_plan p, g3_tuning* t);
 g3_status g3_autotune(g3_plan p, const g3_system* systems, int32_t n_systems,
                       g3_tuning* best);
 
-/* Timing of the most recent triplet-kernel launches on the plan's stream,
- * measured with HIP events (milliseconds per launch, averaged since the last
- * reset) and the number of launches. */
+/* Timing of the triplet-kernel launches on the plan's stream since the last
+ * g3_kernel_time_reset(p, 1), measured with HIP events (milliseconds per
+ * launch, averaged) and the number of launches.  While timing is enabled the
+ * batched form launches its kernels directly (no graph replay), so that the
+ * events bracket them. */
 g3_status g3_kernel_time(g3_plan p, double* avg_ms, int64_t* n_launches);
 g3_status g3_kernel_time_reset(g3_plan p, int32_t enable);
+
+/* The same for one stage of the path: G3_STAGE_TRIPLET (triplet binning,
+ * = g3_kernel_time), G3_STAGE_NEIGHBOURS (the neighbour build: the per-wave
+ * build and the general build over the cells it leaves, one interval),
+ * G3_STAGE_CELLS (counting sort into cells). */
+enum { G3_STAGE_TRIPLET = 0, G3_STAGE_NEIGHBOURS = 1, G3_STAGE_CELLS = 2 };
+g3_status g3_stage_time(g3_plan p, int32_t stage, double* avg_ms, int64_t* n_launches);
+
+/* Work of the neighbour builds since the last g3_kernel_time_reset:
+ * candidates = (centre, stencil atom) pairs whose distance was tested (the
+ * triangle-once lists test only atoms ranked above the centre), neighbours =
+ * entries written to the lists (pairs closer than rmax).  Synchronises the
+ * plan's stream. */
+g3_status g3_build_counts(g3_plan p, uint64_t* candidates, uint64_t* neighbours);
 
 /* Candidate pairs evaluated by the triplet kernel since the last
  * g3_kernel_time_reset: one per (centre i, unordered {j,k}) with both j and k
  * within rmax of i -- the pairs whose third side the method must test.
  * Synchronises the plan's stream. */
 g3_status g3_candidates(g3_plan p, uint64_t* n);
+
+/* Measured LDS rates of the current device, the ceilings behind the triplet
+ * kernel's roofline (its LDS work per candidate pair is one bin-table read
+ * and one histogram increment).  One 1024-thread workgroup per compute unit,
+ * each lane cycling through 16 word addresses in a table of `words` uint32
+ * words of LDS (1..36864; at least 1024 for pattern 0):
+ *   0  ds_add_u32 on the lane's own word (no bank conflict: the trash words
+ *      rejected candidates add to);
+ *   1  ds_add_u32 at uniformly random words (histogram increments);
+ *   2  ds_read_b32 at uniformly random words (bin-table reads);
+ *   3  one random read and one random add per step (counted as 2 operations).
+ * *lane_ops_per_s = lane operations per second over the whole device, the
+ * best of three timed launches after one warm-up.  Synchronous; allocates
+ * and frees a small device buffer. */
+g3_status g3_lds_rate(int32_t pattern, int32_t words, double* lane_ops_per_s);
 
 const char* g3_strerror(g3_status s);
 

@@ -178,13 +178,13 @@ size_t nbr_build_lds_bytes();
 // General build over every cell of every job, or (list) over the cells the
 // per-wave build left in each frame's overflow list.
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
-                      bool one_step, bool list, hipStream_t s);
+                      bool one_step, bool list, unsigned long long* cnt, hipStream_t s);
 // Per-wave build (narrow entries): a wave stages one cell's stencil, at most
 // stage_cap atoms, as packed int16 coordinates and builds its centres' lists.
 constexpr int kWaveBuildWaves = kWaveBuildWavesPerWG;
 size_t nbr_wave_lds_bytes(int stage_cap);
 void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool one_step,
-                     int stage_cap, hipStream_t s);
+                     int stage_cap, unsigned long long* cnt, hipStream_t s);
 // Bin lookups of the triplet kernel: u8 table then threshold steps (loop or
 // one step), or the step table.
 enum Lookup : int { kLookupSteps = 0, kLookupOneStep = 1, kLookupStepTable = 2 };

@@ -348,9 +348,15 @@ struct g3_plan_s {
 
     // kernel timing
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
-    double t_acc_ms = 0;
-    int64_t t_n = 0;
+    struct Timed {
+        hipEvent_t e0, e1;
+        int stage;               // G3_STAGE_*
+    };
+    std::vector<Timed> ev_pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+    double t_acc_ms[3] = {0, 0, 0};
+    int64_t t_n[3] = {0, 0, 0};
+    unsigned long long* build_cnt = nullptr;   // [2]: candidates tested, neighbours accepted
 };
 
 namespace {
@@ -636,13 +642,13 @@ BuildPlan plan_build(const std::vector<Prepared>& ps)
 }
 
 void launch_build(const Sys* dsys, const Job* djobs, int nj, int max_cells, bool wide, bool one_step,
-                  const BuildPlan& bp, hipStream_t sm)
+                  const BuildPlan& bp, unsigned long long* cnt, hipStream_t sm)
 {
     if (bp.wave) {
-        launch_nbr_wave(dsys, djobs, nj, max_cells, one_step, bp.cap, sm);
-        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, true, sm);
+        launch_nbr_wave(dsys, djobs, nj, max_cells, one_step, bp.cap, cnt, sm);
+        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, true, cnt, sm);
     } else {
-        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, false, sm);
+        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, false, cnt, sm);
     }
 }
 
@@ -690,6 +696,10 @@ g3_status ensure_common(g3_plan p)
         G3_TRY_HIP(hipMalloc((void**)&p->cand, sizeof(unsigned long long)));
         G3_TRY_HIP(hipMemsetAsync(p->cand, 0, sizeof(unsigned long long), p->stream));
     }
+    if (!p->build_cnt) {
+        G3_TRY_HIP(hipMalloc((void**)&p->build_cnt, 2 * sizeof(unsigned long long)));
+        G3_TRY_HIP(hipMemsetAsync(p->build_cnt, 0, 2 * sizeof(unsigned long long), p->stream));
+    }
     if (!p->flag_log) {
         G3_TRY_HIP(hipMalloc((void**)&p->flag_log, sizeof(uint32_t) * kFlagLogCap));
         p->flag_used = 0;
@@ -716,7 +726,9 @@ g3_status reserve_flags(g3_plan p, int n, uint32_t** out, int* off)
     return G3_OK;
 }
 
-void timing_begin(g3_plan p, hipEvent_t* e0)
+// Timed launches (g3_kernel_time_reset enables them): HIP events on the
+// plan's stream around one stage's kernels.
+void timing_begin(g3_plan p, hipEvent_t* e0, int stage = G3_STAGE_TRIPLET)
 {
     *e0 = nullptr;
     if (!p->timing) return;
@@ -724,25 +736,25 @@ void timing_begin(g3_plan p, hipEvent_t* e0)
     if (!p->ev_free.empty()) { ev = p->ev_free.back(); p->ev_free.pop_back(); }
     else { hipEventCreate(&ev.first); hipEventCreate(&ev.second); }
     hipEventRecord(ev.first, p->stream);
-    p->ev_pending.push_back(ev);
+    p->ev_pending.push_back({ev.first, ev.second, stage});
     *e0 = ev.first;
 }
 
 void timing_end(g3_plan p, hipEvent_t e0)
 {
     if (!e0) return;
-    hipEventRecord(p->ev_pending.back().second, p->stream);
+    hipEventRecord(p->ev_pending.back().e1, p->stream);
 }
 
 void collect_timing(g3_plan p)
 {
     for (auto& ev : p->ev_pending) {
         float ms = 0;
-        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
-            p->t_acc_ms += ms;
-            p->t_n += 1;
+        if (hipEventElapsedTime(&ms, ev.e0, ev.e1) == hipSuccess) {
+            p->t_acc_ms[ev.stage] += ms;
+            p->t_n[ev.stage] += 1;
         }
-        p->ev_free.push_back(ev);
+        p->ev_free.push_back({ev.e0, ev.e1});
     }
     p->ev_pending.clear();
 }
@@ -898,10 +910,15 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     for (int f = 0; f < F; ++f) {
         const Job* j = djobs + f;
         launch_zero_u32((uint32_t*)((char*)p->arena + P.off_cell_count), (size_t)P.g.ncell, p->stream);
+        hipEvent_t ec, eb;
+        timing_begin(p, &ec, G3_STAGE_CELLS);
         launch_cell_count(dsys, j, 1, N, p->stream);
         launch_cell_scan(dsys, j, 1, p->stream);
         launch_cell_scatter(dsys, j, 1, N, p->stream);
-        launch_build(dsys, j, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, bp, p->stream);
+        timing_end(p, ec);
+        timing_begin(p, &eb, G3_STAGE_NEIGHBOURS);
+        launch_build(dsys, j, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, bp, p->build_cnt, p->stream);
+        timing_end(p, eb);
         launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
         if (tri.second > tri.first)
             launch_zero_u32((uint32_t*)((char*)p->arena + tri.first), (tri.second - tri.first) / 4, p->stream);
@@ -1056,7 +1073,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_count(dsys, djobs, nj, max_n, sm);
             launch_cell_scan(dsys, djobs, nj, sm);
             launch_cell_scatter(dsys, djobs, nj, max_n, sm);
-            launch_build(dsys, djobs, nj, max_cells, wide, one_step, bp, sm);
+            launch_build(dsys, djobs, nj, max_cells, wide, one_step, bp, p->build_cnt, sm);
             launch_triplet(a, wide, lookup, padded, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
             if (any_tri) launch_expand(dsys, n_sys, max_nb, sm);
@@ -1065,10 +1082,15 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             // timed runs launch directly so that events bracket the kernel
             for (auto& z : zero) launch_zero_u32(z.first, z.second, p->stream);
             launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
+            hipEvent_t ec, eb;
+            timing_begin(p, &ec, G3_STAGE_CELLS);
             launch_cell_count(dsys, djobs, nj, max_n, p->stream);
             launch_cell_scan(dsys, djobs, nj, p->stream);
             launch_cell_scatter(dsys, djobs, nj, max_n, p->stream);
-            launch_build(dsys, djobs, nj, max_cells, wide, one_step, bp, p->stream);
+            timing_end(p, ec);
+            timing_begin(p, &eb, G3_STAGE_NEIGHBOURS);
+            launch_build(dsys, djobs, nj, max_cells, wide, one_step, bp, p->build_cnt, p->stream);
+            timing_end(p, eb);
             hipEvent_t e0;
             timing_begin(p, &e0);
             launch_triplet(a, wide, lookup, padded, n_wg, p->stream);
@@ -1214,13 +1236,14 @@ void g3_plan_destroy(g3_plan p)
     if (!p) return;
     hipStreamSynchronize(p->stream);
     for (auto& g : p->gexec) if (g) hipGraphExecDestroy(g);
-    for (auto& e : p->ev_pending) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    for (auto& e : p->ev_pending) { hipEventDestroy(e.e0); hipEventDestroy(e.e1); }
     for (auto& e : p->ev_free) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
     if (p->arena) hipFree(p->arena);
     if (p->tables) hipFree(p->tables);
     if (p->slots) hipFree(p->slots);
     if (p->ctl) hipFree(p->ctl);
     if (p->cand) hipFree(p->cand);
+    if (p->build_cnt) hipFree(p->build_cnt);
     if (p->flag_log) hipFree(p->flag_log);
     for (int b = 0; b < 2; ++b) {
         if (p->stage[b]) hipHostFree(p->stage[b]);
@@ -1512,9 +1535,27 @@ g3_status g3_get_tuning(g3_plan p, g3_tuning* t)
 
 g3_status g3_kernel_time(g3_plan p, double* avg_ms, int64_t* n)
 {
-    if (!p) return G3_EINVAL;
-    if (avg_ms) *avg_ms = p->t_n ? p->t_acc_ms / (double)p->t_n : 0.0;
-    if (n) *n = p->t_n;
+    return g3_stage_time(p, G3_STAGE_TRIPLET, avg_ms, n);
+}
+
+g3_status g3_stage_time(g3_plan p, int32_t stage, double* avg_ms, int64_t* n)
+{
+    if (!p || stage < 0 || stage > 2) return G3_EINVAL;
+    if (avg_ms) *avg_ms = p->t_n[stage] ? p->t_acc_ms[stage] / (double)p->t_n[stage] : 0.0;
+    if (n) *n = p->t_n[stage];
+    return G3_OK;
+}
+
+g3_status g3_build_counts(g3_plan p, uint64_t* candidates, uint64_t* neighbours)
+{
+    if (!p || !candidates || !neighbours) return G3_EINVAL;
+    *candidates = *neighbours = 0;
+    if (!p->build_cnt) return G3_OK;
+    unsigned long long v[2] = {0, 0};
+    G3_TRY_HIP(hipStreamSynchronize(p->stream));
+    G3_TRY_HIP(hipMemcpy(v, p->build_cnt, sizeof(v), hipMemcpyDeviceToHost));
+    *candidates = v[0];
+    *neighbours = v[1];
     return G3_OK;
 }
 
@@ -1537,9 +1578,12 @@ g3_status g3_kernel_time_reset(g3_plan p, int32_t enable)
         G3_TRY_HIP(hipStreamSynchronize(p->stream));
         G3_TRY_HIP(hipMemset(p->cand, 0, sizeof(unsigned long long)));
     }
+    if (p->build_cnt) G3_TRY_HIP(hipMemset(p->build_cnt, 0, 2 * sizeof(unsigned long long)));
     p->timing = enable != 0;
-    p->t_acc_ms = 0;
-    p->t_n = 0;
+    for (int k = 0; k < 3; ++k) {
+        p->t_acc_ms[k] = 0;
+        p->t_n[k] = 0;
+    }
     return G3_OK;
 }
 

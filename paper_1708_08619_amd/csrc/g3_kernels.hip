@@ -257,7 +257,8 @@ constexpr uint32_t kChunk = kBuildChunk;
 // CU: the build is latency-bound, and its few spills sit outside the pass-1 loop.
 template <bool WIDE, bool ONE_STEP>
 __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __restrict__ sys,
-                                                             const Job* __restrict__ jobs, int list)
+                                                             const Job* __restrict__ jobs, int list,
+                                                             unsigned long long* cnt)
 {
     using E = typename std::conditional<WIDE, int4, uint2>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -370,6 +371,7 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
         }
     };
     fetch_cell(blockIdx.x);
+    uint64_t n_tested = 0, n_found = 0;   // this wave's candidates and neighbours
 
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
         const int c0 = p_c0, c1 = p_c1;
@@ -595,6 +597,8 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
             else if (fast) pass12(std::integral_constant<int, 1>{});
             else pass12(std::integral_constant<int, 0>{});
             wave_sync();
+            n_tested += (uint64_t)(T - t_first - (tri_once ? 0 : 1));
+            n_found += n;
             // a list longer than m_safe could take an item of the triplet
             // kernel past 2^32 candidate pairs: the frame is recomputed
             // with smaller items (its lists and pairs are still built here)
@@ -706,6 +710,10 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
         __syncthreads();
         flush_g2();
     }
+    if (cnt && lane == 0 && n_tested) {
+        atomicAdd(cnt, (unsigned long long)n_tested);
+        atomicAdd(cnt + 1, (unsigned long long)n_found);
+    }
 }
 
 // ------------------------------------------------------------------ per-wave neighbours
@@ -766,7 +774,7 @@ __device__ __forceinline__ uint32_t as_u32(short2p v) { return __builtin_bit_cas
 template <bool ONE_STEP>
 __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys* __restrict__ sys,
                                                                    const Job* __restrict__ jobs,
-                                                                   int cap)
+                                                                   int cap, unsigned long long* cnt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                    // [kThrMax]
@@ -860,6 +868,7 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys*
     };
     const uint2 pad_e = make_uint2(0x80008000u, 0x00008000u);   // pad entry after every list
     uint32_t chunk_base = 0, chunk_left = 0;   // this wave's slice of the frame's pool
+    uint64_t n_tested = 0, n_found = 0;        // this wave's candidates and neighbours
 
     for (int cell = blockIdx.x * kWaveBuildWaves + wave; cell < ncell;
          cell += gridDim.x * kWaveBuildWaves) {
@@ -975,6 +984,8 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys*
             if (tri_once) pass1(std::true_type{});
             else pass1(std::false_type{});
             wave_sync();
+            n_tested += (uint64_t)(tri_once ? Tu - tself - 1 : Tu - 1);
+            n_found += n;
             // entry, pair bin and slab of accepted index e (slab via q)
             auto entry = [&](uint32_t e, int& b) -> uint2 {
                 short2p dxy, dz;
@@ -1078,6 +1089,10 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys*
         }
     }
     if (pair_hist && g2_pending) flush_g2();
+    if (cnt && lane == 0 && n_tested) {
+        atomicAdd(cnt, (unsigned long long)n_tested);
+        atomicAdd(cnt + 1, (unsigned long long)n_found);
+    }
 }
 
 // ------------------------------------------------------------------ triplets
@@ -1887,7 +1902,7 @@ size_t nbr_build_lds_bytes()
 }
 
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
-                      bool one_step, bool list, hipStream_t s)
+                      bool one_step, bool list, unsigned long long* cnt, hipStream_t s)
 {
     // enough workgroups per frame to fill the chip, each looping over cells
     // (over the overflow list: a few per frame, most of which find it empty)
@@ -1897,11 +1912,11 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
     const dim3 g(per_job, n_jobs), b(kBuildThreads);
     const int lm = list ? 1 : 0;
     if (wide) {
-        if (one_step) hipLaunchKernelGGL((k_nbr_build<true, true>), g, b, lds, s, sys, jobs, lm);
-        else hipLaunchKernelGGL((k_nbr_build<true, false>), g, b, lds, s, sys, jobs, lm);
+        if (one_step) hipLaunchKernelGGL((k_nbr_build<true, true>), g, b, lds, s, sys, jobs, lm, cnt);
+        else hipLaunchKernelGGL((k_nbr_build<true, false>), g, b, lds, s, sys, jobs, lm, cnt);
     } else {
-        if (one_step) hipLaunchKernelGGL((k_nbr_build<false, true>), g, b, lds, s, sys, jobs, lm);
-        else hipLaunchKernelGGL((k_nbr_build<false, false>), g, b, lds, s, sys, jobs, lm);
+        if (one_step) hipLaunchKernelGGL((k_nbr_build<false, true>), g, b, lds, s, sys, jobs, lm, cnt);
+        else hipLaunchKernelGGL((k_nbr_build<false, false>), g, b, lds, s, sys, jobs, lm, cnt);
     }
 }
 
@@ -1911,15 +1926,15 @@ size_t nbr_wave_lds_bytes(int stage_cap)
 }
 
 void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool one_step,
-                     int stage_cap, hipStream_t s)
+                     int stage_cap, unsigned long long* cnt, hipStream_t s)
 {
     // about two rounds of resident workgroups over the whole batch; a wave
     // takes cells blockIdx.x * 8 + wave + k * gridDim.x * 8
     const int per_job = wave_wgs_per_job(n_jobs, max_cells);
     const size_t lds = nbr_wave_lds_bytes(stage_cap);
     const dim3 g(per_job, n_jobs), b(kWaveBuildWaves * 64);
-    if (one_step) hipLaunchKernelGGL((k_nbr_wave<true>), g, b, lds, s, sys, jobs, stage_cap);
-    else hipLaunchKernelGGL((k_nbr_wave<false>), g, b, lds, s, sys, jobs, stage_cap);
+    if (one_step) hipLaunchKernelGGL((k_nbr_wave<true>), g, b, lds, s, sys, jobs, stage_cap, cnt);
+    else hipLaunchKernelGGL((k_nbr_wave<false>), g, b, lds, s, sys, jobs, stage_cap, cnt);
 }
 
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes, size_t wave_build_bytes)

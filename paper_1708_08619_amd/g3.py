@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libg3.so")
 
 HALF, FULL = 0, 1
+STAGE_TRIPLET, STAGE_NEIGHBOURS, STAGE_CELLS = 0, 1, 2
 OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, EBUSY = range(6)
 MAX_NBINS = 160
 MAX_RMAX = 46340.0
@@ -92,8 +93,11 @@ def lib():
         "g3_autotune": ([P, P, I32, P], I32),
         "g3_kernel_time": ([P, C.POINTER(D), C.POINTER(I64)], I32),
         "g3_kernel_time_reset": ([P, I32], I32),
+        "g3_stage_time": ([P, I32, C.POINTER(D), C.POINTER(I64)], I32),
+        "g3_build_counts": ([P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], I32),
         "g3_candidates": ([P, C.POINTER(C.c_uint64)], I32),
         "g3_strerror": ([I32], C.c_char_p),
+        "g3_lds_rate": ([I32, I32, C.POINTER(D)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -199,6 +203,17 @@ def isosceles(g3: np.ndarray, layout: int, nbins: int, a: int):
 
 def strerror(status: int) -> str:
     return _strerror(status)
+
+
+LDS_ADD_LANE, LDS_ADD_RANDOM, LDS_READ_RANDOM, LDS_READ_ADD = range(4)
+
+
+def lds_rate(pattern: int, words: int) -> float:
+    """Measured LDS lane operations per second of the current device
+    (g3_lds_rate)."""
+    v = C.c_double()
+    _check(lib().g3_lds_rate(int(pattern), int(words), C.byref(v)), "g3_lds_rate")
+    return float(v.value)
 
 
 # ------------------------------------------------------------------ device plan
@@ -333,6 +348,18 @@ class Plan:
         n = C.c_uint64()
         _check(lib().g3_candidates(self._h, C.byref(n)), "g3_candidates")
         return int(n.value)
+
+    def stage_time(self, stage: int) -> tuple[float, int]:
+        """(ms per launch, launches) of one stage since the last reset."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().g3_stage_time(self._h, int(stage), C.byref(ms), C.byref(n)), "g3_stage_time")
+        return float(ms.value), int(n.value)
+
+    def build_counts(self) -> tuple[int, int]:
+        """(candidates tested, neighbours accepted) by the neighbour builds."""
+        a, b = C.c_uint64(), C.c_uint64()
+        _check(lib().g3_build_counts(self._h, C.byref(a), C.byref(b)), "g3_build_counts")
+        return int(a.value), int(b.value)
 
     def kernel_time(self) -> tuple[float, int]:
         ms, n = C.c_double(), C.c_int64()
