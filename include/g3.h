@@ -153,6 +153,30 @@ g3_status g3_accumulate_system(g3_plan p, const g3_system* system);
  * pair_hist arrays overlap). */
 g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_systems);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the plain
+ * form of g3_accumulate_system (same arguments, same results, one frame at a
+ * time on the plan's stream) with every scratch buffer taken from a static
+ * device array of G3_NOALLOC_BYTES that the library holds on each GPU it runs
+ * on (from module load until the process ends).  It calls no hipMalloc,
+ * hipFree or other allocating routine; its tables are written by kernels
+ * that take them as arguments.  The caller still owns frames, hist and
+ * pair_hist.
+ * Limits: one frame's scratch -- about 16 bytes per atom plus 8 bytes per
+ * neighbour-list entry with the library's headroom (roughly 100 MiB for
+ * N = 65536 at 96 neighbours per atom), plus the bin tables and up to 1/8 of
+ * the array for partial histogram slots -- must fit G3_NOALLOC_BYTES, else
+ * G3_ENOMEM is returned before anything is queued; at most 65536 frames per
+ * call; G3_EDEVICE if the array's address could not be obtained on this
+ * device.  Every such call on one GPU shares that GPU's array (it keeps the
+ * last call's contents; the library clears what must start at zero): calls
+ * from different plans or streams that overlap in time on one GPU race.
+ * g3_sync recomputes flagged frames as for g3_accumulate, through the same
+ * array; a frame whose neighbour lists overflow even the largest pool that
+ * fits it makes g3_sync return G3_ENOMEM. */
+#define G3_NOALLOC_BYTES (128u << 20)
+g3_status g3_accumulate_noalloc(g3_plan p, const g3_system* system);
+
 /* Wait for the plan's queued work and report asynchronous errors:
  * G3_EDOMAIN if a frame held a coordinate outside the box (such frames add
  * nothing to hist or pair_hist), G3_ENOMEM if a centre exceeded the

@@ -22,7 +22,7 @@ COMMON = [
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     "-Wall", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["g3_kernels.hip", "g3_host.cpp", "g3_probe.hip"]
+SOURCES = ["g3_kernels.hip", "g3_host.cpp", "g3_probe.hip", "g3_static.hip"]
 
 
 def hipcc() -> str:

@@ -93,6 +93,7 @@ struct Sys {
     // listed here ([ncell] per frame, count in the frame's cursor line)
     int32_t pk_ok;
     int32_t* ovf_cells;
+    uint32_t chunk;          // pool entries a build wave reserves at a time
 };
 
 struct Job {
@@ -148,7 +149,8 @@ inline size_t triplet_lds_bytes(int hb_max, int cb)
 // Neighbour build launch shape: workgroups per frame (each loops over cells),
 // waves per workgroup and the pool entries a wave reserves at a time.
 constexpr int kBuildWavesPerWG = 8;
-constexpr uint32_t kBuildChunk = 2048;
+constexpr uint32_t kBuildChunk = 2048;     // batched launches (many cells per wave)
+constexpr uint32_t kPlainChunk = 256;      // per-frame launches (about one cell per wave)
 constexpr int kStageCap = 768;       // stencil atoms staged in LDS per home cell
 inline int build_wgs_per_job(int n_jobs, int max_cells)
 {
@@ -168,6 +170,14 @@ inline int wave_wgs_per_job(int n_jobs, int max_cells)
     if (per_job > cells_wg) per_job = cells_wg;
     return per_job < 1 ? 1 : per_job;
 }
+
+// Static scratch for callers that cannot allocate (g3_static.hip): its
+// device address on `device` (looked up once per device; the caller makes
+// `device` current), and a writer of small tables through kernel arguments.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+constexpr int kPutWords = 760;        // uint32 words per table-writing launch (<= 4 KB of arguments)
+void* static_scratch(int device, hipError_t* err);
+void launch_put_words(uint32_t* dst, const uint32_t* src, size_t n_words, hipStream_t s);
 
 // Launch wrappers (defined in g3_kernels.hip).
 void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);

@@ -26,7 +26,8 @@ using namespace g3;
 constexpr int kTabMax = kTabBytes;   // bytes of the bin lookup table in LDS
 constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
 constexpr size_t kLdsPerCU = 160 * 1024;
-constexpr int kWaveStageMax = 1024;    // largest stencil a wave of the per-wave build stages
+constexpr int kWaveStageMax = 1024;
+static_assert(G3_NOALLOC_BYTES == g3::kStaticScratchBytes, "static scratch size");    // largest stencil a wave of the per-wave build stages
 
 #define G3_TRY_HIP(expr)                         \
     do {                                         \
@@ -309,10 +310,11 @@ struct g3_plan_s {
     uint32_t* flag_log = nullptr;
     int flag_used = 0;
 
-    struct Rec {            // what a range of the flag log belongs to
+    struct Rec {            // what a range of flag words belongs to
         g3_system sys;
-        int log_off;
+        int log_off;        // in the flag log (plan-allocated calls)
         bool worst_case;    // already the recomputation with the largest pool
+        const uint32_t* na_flags;   // no-allocation calls: their words in the static scratch
     };
     std::vector<Rec> recs;
 
@@ -330,6 +332,12 @@ struct g3_plan_s {
     std::string gkey[2];
     std::string last_key[2];   // signature of the previous batched call
     bool lds_set = false;
+
+    // no-allocation path: this device's static scratch (address looked up
+    // once per device at plan creation) and the use of its flag ring
+    char* na_base = nullptr;
+    hipError_t na_err = hipSuccess;
+    int na_flag_used = 0;
 
     // Completion tickets (one per accumulate call): the call's flag words are
     // copied to pinned host memory behind its kernels and an event marks the
@@ -469,7 +477,8 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
     // (each wave of the per-wave build and of the general build may leave a
     // chunk's tail unused)
     const int64_t slack = ((int64_t)build_wgs_per_job(n_jobs, max_cells) * kBuildWavesPerWG +
-                           (int64_t)wave_wgs_per_job(n_jobs, max_cells) * kWaveBuildWaves) * kBuildChunk;
+                           (int64_t)wave_wgs_per_job(n_jobs, max_cells) * kWaveBuildWaves) *
+                          (per_frame ? kBuildChunk : kPlainChunk);
     for (auto& P : ps) {
         const Geometry& g = P.g;
         const size_t F = per_frame ? (size_t)std::max(P.in.n_frames, 1) : 1;
@@ -612,6 +621,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
     s.flags = flags;
     s.pk_ok = g.pk_ok;
     s.ovf_cells = reinterpret_cast<int32_t*>(arena + P.off_ovf);
+    s.chunk = P.per_frame ? kBuildChunk : kPlainChunk;
     return s;
 }
 
@@ -708,6 +718,7 @@ g3_status ensure_common(g3_plan p)
 }
 
 g3_status drain(g3_plan p);
+g3_status run_plain_noalloc(g3_plan p, const g3_system& s, bool worst_case);
 
 // Reserve n entries of the flag log (zeroed on the stream).
 g3_status reserve_flags(g3_plan p, int n, uint32_t** out, int* off)
@@ -856,7 +867,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     int foff;
     st = reserve_flags(p, s.n_frames, &flags, &foff);
     if (st) return st;
-    p->recs.push_back({s, foff, worst_case});
+    p->recs.push_back({s, foff, worst_case, nullptr});
 
     const Prepared& P = ps[0];
     const int F = s.n_frames;
@@ -934,6 +945,118 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     return G3_OK;
 }
 
+// ------------------------------------------------------------------ plain path, no allocation
+// The plain path with every buffer carved out of this device's static
+// scratch (the control words, a ring of per-frame flag words, the tables,
+// the per-frame scratch and the partial slots), tables written by kernels
+// that take them as arguments, and one frame at a time (a per-frame copy of
+// the system's descriptor).  Nothing is allocated: a call whose scratch does
+// not fit returns G3_ENOMEM before queuing anything.
+constexpr size_t kNaCtl = 0;                 // Ctl
+constexpr size_t kNaCand = 1024;             // candidate counter
+constexpr size_t kNaFlags = 4096;            // flag ring
+constexpr int kNaFlagCap = 1 << 16;          // flag words (frames queued between syncs)
+constexpr size_t kNaTables = kNaFlags + (size_t)kNaFlagCap * 4;
+
+g3_status put_bytes(g3_plan p, void* dst, const void* src, size_t n)
+{
+    if (!n) return G3_OK;
+    std::vector<uint32_t> w((n + 3) / 4, 0u);
+    std::memcpy(w.data(), src, n);
+    launch_put_words((uint32_t*)dst, w.data(), w.size(), p->stream);
+    return G3_OK;
+}
+
+g3_status run_plain_noalloc(g3_plan p, const g3_system& s, bool worst_case)
+{
+    if (!p->na_base) return p->na_err != hipSuccess ? fail(p, p->na_err) : G3_EDEVICE;
+    if (s.n_frames == 0 || s.n_atoms == 0) return check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
+    if (s.n_frames > kNaFlagCap) return G3_EINVAL;
+    Tun tn = effective(p);
+    std::vector<Prepared> ps(1);
+    g3_status st = prepare(s, tn.hb_max, ps[0]);
+    if (st) return st;
+    Prepared& P = ps[0];
+    // tables: [Sys][Job][Segs][slot_seg], then the frame scratch, then slots
+    std::vector<Seg> segs;
+    int items = 0;
+    add_segments(P, 0, 0, 1, tn.cb, segs, items);
+    const int S = (int)P.g.slab_lo.size() - 1;
+    const int n_wg = p->n_cu * tn.wg_per_cu;
+    const size_t o_sys = kNaTables, o_jobs = align_up(o_sys + sizeof(Sys), 256),
+                 o_segs = align_up(o_jobs + sizeof(Job), 256), o_slotseg = align_up(o_segs + sizeof(Seg) * S, 256);
+    // partial slots: what the tuning asks for, but at most 1/8 of the static
+    // scratch (the flush adds the rest to the output with 64-bit atomics)
+    const int slots_fit = (int)std::max<size_t>(1, (kStaticScratchBytes / 8) / ((size_t)tn.hb_max * 4));
+    const int max_slots = std::min(slot_count(n_wg, S, tn.hb_max, tn.slot_limit), slots_fit);
+    const size_t o_arena = align_up(o_slotseg + sizeof(int32_t) * max_slots, 256);
+    const size_t arena_end = layout_scratch(ps, false, worst_case, o_arena, tn.tri_once);
+    const size_t o_slots = align_up(arena_end, 256);
+    const size_t end = o_slots + (size_t)max_slots * tn.hb_max * 4;
+    if (end > kStaticScratchBytes) return G3_ENOMEM;
+    st = set_lds_limits(p);
+    if (st) return st;
+    // flag words for every frame (a full ring is drained first)
+    if (p->na_flag_used + s.n_frames > kNaFlagCap) {
+        if ((st = drain(p))) return st;
+    }
+    char* B = p->na_base;
+    uint32_t* flags = (uint32_t*)(B + kNaFlags) + p->na_flag_used;
+    p->na_flag_used += s.n_frames;
+    launch_zero_u32(flags, (size_t)s.n_frames, p->stream);
+    p->recs.push_back({s, 0, worst_case, flags});
+
+    const int F = s.n_frames, N = P.g.N;
+    const BuildPlan bp = plan_build(ps);
+    const Job job{0, 0};
+    // geometry tables (in the arena) and the per-call tables
+    if ((st = put_bytes(p, B + P.off_thr, P.g.thr.data(), P.g.thr.size() * 4))) return st;
+    if ((st = put_bytes(p, B + P.off_tab, P.g.tab.data(), P.g.tab.size()))) return st;
+    if (!P.g.step.empty() && (st = put_bytes(p, B + P.off_step, P.g.step.data(), P.g.step.size() * 4)))
+        return st;
+    if ((st = put_bytes(p, B + o_jobs, &job, sizeof(Job)))) return st;
+    if ((st = put_bytes(p, B + o_segs, segs.data(), sizeof(Seg) * S))) return st;
+    const Sys* dsys = (const Sys*)(B + o_sys);
+    const Job* djob = (const Job*)(B + o_jobs);
+    TripletArgs a;
+    a.sys = dsys;
+    a.segs = (const Seg*)(B + o_segs);
+    a.n_segs = S;
+    a.total_items = items;
+    a.ctl = (Ctl*)(B + kNaCtl);
+    a.slots = (uint32_t*)(B + o_slots);
+    a.slot_seg = (int32_t*)(B + o_slotseg);
+    a.max_slots = max_slots;
+    a.hb_max = tn.hb_max;
+    a.cb = tn.cb;
+    a.tb_max = kTabMax;
+    a.cand = (unsigned long long*)(B + kNaCand);
+    const auto tri = tri_range(ps);
+    for (int f = 0; f < F; ++f) {
+        // this frame's descriptor: its coordinates and flag word, one frame
+        g3_system one = s;
+        one.frames = s.frames + (size_t)f * 3 * N;
+        one.n_frames = 1;
+        P.in = one;
+        Sys sys = make_sys(P, B, flags + f, tn.cb);
+        if ((st = put_bytes(p, (void*)dsys, &sys, sizeof(Sys)))) return st;
+        launch_zero_u32((uint32_t*)(B + P.off_cursor), (size_t)kCursorStride, p->stream);
+        launch_zero_u32((uint32_t*)(B + P.off_cell_count), (size_t)P.g.ncell, p->stream);
+        launch_cell_count(dsys, djob, 1, N, p->stream);
+        launch_cell_scan(dsys, djob, 1, p->stream);
+        launch_cell_scatter(dsys, djob, 1, N, p->stream);
+        launch_build(dsys, djob, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, bp, nullptr, p->stream);
+        launch_zero_u32((uint32_t*)(B + kNaCtl), sizeof(Ctl) / 4, p->stream);
+        if (tri.second > tri.first)
+            launch_zero_u32((uint32_t*)(B + tri.first), (tri.second - tri.first) / 4, p->stream);
+        launch_triplet(a, P.g.wide != 0, lookup_of(P.g), pads_rejected(P.g), n_wg, p->stream);
+        launch_reduce(a, tn.hb_max, S, p->stream);
+        if (P.tri_once) launch_expand(dsys, 1, P.g.nbins, p->stream);
+    }
+    G3_TRY_HIP(hipGetLastError());
+    return G3_OK;
+}
+
 // ------------------------------------------------------------------ batched path
 // All frames of all systems: batched cell and neighbour builds (one launch
 // per stage over every (system, frame) job), one persistent triplet launch per
@@ -972,7 +1095,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         std::vector<Seg> segs;
         int items = 0, fo = foff, max_n = 0, max_hb = 0;
         for (size_t k = 0; k < ps.size(); ++k) {
-            p->recs.push_back({ps[k].in, fo, false});
+            p->recs.push_back({ps[k].in, fo, false, nullptr});
             sys.push_back(make_sys(ps[k], (char*)p->arena, p->flag_log + fo, tn.cb));
             fo += ps[k].in.n_frames;
             for (int f = 0; f < ps[k].in.n_frames; ++f) jobs.push_back({(int)k, f});
@@ -1136,8 +1259,11 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
     return G3_OK;
 }
 
-// Wait, read the flag log, recompute through the plain path the frames whose
-// pool overflowed or whose lists were too long for the tuning's items.
+// Wait, read the flag words, recompute through the plain path the frames
+// whose pool overflowed or whose lists were too long for the tuning's items
+// (a no-allocation call's frames through the no-allocation path: a pool
+// overflow there with the largest pool that fits the static scratch is
+// G3_ENOMEM).
 g3_status drain(g3_plan p)
 {
     G3_TRY_HIP(hipStreamSynchronize(p->stream));
@@ -1149,40 +1275,58 @@ g3_status drain(g3_plan p)
     p->final_upto = p->next_ticket - 1;
     p->call_first = -1;
     g3_status result = p->sticky;
-    if (p->flag_used > 0) {
-        std::vector<uint32_t> fl(p->flag_used);
+    if (p->recs.empty()) {
+        p->flag_used = 0;
+        p->na_flag_used = 0;
+        return result;
+    }
+    std::vector<uint32_t> fl(p->flag_used);
+    if (p->flag_used > 0)
         G3_TRY_HIP(hipMemcpy(fl.data(), p->flag_log, sizeof(uint32_t) * fl.size(), hipMemcpyDeviceToHost));
-        std::vector<g3_system> redo;
-        for (const auto& r : p->recs) {
-            for (int f = 0; f < r.sys.n_frames; ++f) {
-                const uint32_t v = fl[r.log_off + f];
-                if (v & kFlagDomain) { if (result == G3_OK) result = G3_EDOMAIN; }
-                else if (v & kFlagList) { if (result == G3_OK) result = G3_ENOMEM; }
-                else if ((v & kFlagPool) && r.worst_case) { if (result == G3_OK) result = G3_ENOMEM; }
-                else if (v & (kFlagPool | kFlagDense)) {
-                    g3_system one = r.sys;
-                    one.frames = r.sys.frames + (size_t)f * 3 * r.sys.n_atoms;
-                    one.pair_hist = nullptr;   // its pairs were counted in full already
-                    one.n_frames = 1;
-                    redo.push_back(one);
-                }
+    struct Redo {
+        g3_system one;
+        bool noalloc, worst;
+    };
+    std::vector<Redo> redo;
+    for (const auto& r : p->recs) {
+        std::vector<uint32_t> nfl;
+        if (r.na_flags) {
+            nfl.resize(r.sys.n_frames);
+            G3_TRY_HIP(hipMemcpy(nfl.data(), r.na_flags, sizeof(uint32_t) * nfl.size(), hipMemcpyDeviceToHost));
+        }
+        for (int f = 0; f < r.sys.n_frames; ++f) {
+            const uint32_t v = r.na_flags ? nfl[f] : fl[r.log_off + f];
+            if (v & kFlagDomain) { if (result == G3_OK) result = G3_EDOMAIN; }
+            else if (v & kFlagList) { if (result == G3_OK) result = G3_ENOMEM; }
+            else if ((v & kFlagPool) && r.worst_case) { if (result == G3_OK) result = G3_ENOMEM; }
+            else if (v & (kFlagPool | kFlagDense)) {
+                g3_system one = r.sys;
+                one.frames = r.sys.frames + (size_t)f * 3 * r.sys.n_atoms;
+                one.pair_hist = nullptr;   // its pairs were counted in full already
+                one.n_frames = 1;
+                redo.push_back({one, r.na_flags != nullptr, (v & kFlagPool) != 0});
             }
         }
-        p->recs.clear();
-        p->flag_used = 0;
-        // recomputed frames use items of kSafeItemCentres centres, whose
-        // candidate pairs stay below 2^32 for any list
-        const g3_tuning saved = p->tun;
-        if (!redo.empty() && effective(p).cb > kSafeItemCentres) p->tun.centres_per_item = kSafeItemCentres;
-        for (const auto& one : redo) {
-            g3_status st = run_plain(p, one, true);
-            if (st) { p->tun = saved; return st; }
+    }
+    p->recs.clear();
+    p->flag_used = 0;
+    p->na_flag_used = 0;
+    // recomputed frames use items of kSafeItemCentres centres, whose
+    // candidate pairs stay below 2^32 for any list
+    const g3_tuning saved = p->tun;
+    if (!redo.empty() && effective(p).cb > kSafeItemCentres) p->tun.centres_per_item = kSafeItemCentres;
+    for (const auto& r : redo) {
+        g3_status st = r.noalloc ? run_plain_noalloc(p, r.one, r.worst) : run_plain(p, r.one, true);
+        if (st == G3_ENOMEM && r.noalloc) {   // the largest pool does not fit the static scratch
+            if (result == G3_OK) result = G3_ENOMEM;
+            continue;
         }
-        p->tun = saved;
-        if (!redo.empty()) {
-            g3_status st = drain(p);
-            if (st && result == G3_OK) result = st;
-        }
+        if (st) { p->tun = saved; return st; }
+    }
+    p->tun = saved;
+    if (!redo.empty()) {
+        g3_status st = drain(p);
+        if (st && result == G3_OK) result = st;
     }
     return result;
 }
@@ -1227,6 +1371,9 @@ g3_status g3_plan_create(g3_plan* out, void* hip_stream)
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && ncu > 0)
         p->n_cu = ncu;
+    // the static scratch's address on this device (looked up once per
+    // device); a failure only disables g3_accumulate_noalloc
+    p->na_base = (char*)static_scratch(p->device, &p->na_err);
     *out = p;
     return G3_OK;
 }
@@ -1314,6 +1461,18 @@ g3_status g3_accumulate_system(g3_plan p, const g3_system* s)
 {
     if (!p || !s) return G3_EINVAL;
     return accumulate_one(p, *s);
+}
+
+g3_status g3_accumulate_noalloc(g3_plan p, const g3_system* sp)
+{
+    if (!p || !sp) return G3_EINVAL;
+    const g3_system& s = *sp;
+    g3_status st = check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
+    if (st) return st;
+    if (s.n_frames < 0 || (s.n_frames > 0 && s.n_atoms > 0 && (!s.frames || !s.hist))) return G3_EINVAL;
+    if (s.n_frames == 0 || s.n_atoms < (s.pair_hist ? 2 : 3)) return G3_OK;
+    if (s.pair_hist && overlaps(s, s)) return G3_EINVAL;
+    return run_plain_noalloc(p, s, false);
 }
 
 g3_status g3_accumulate_batch(g3_plan p, const g3_system* systems, int32_t n_systems)

@@ -251,7 +251,6 @@ template <bool WIDE>
 constexpr int wave_buf() { return kBufBytes / (WIDE ? 16 : 8); }
 constexpr int kWaveBufMax = kBufBytes / 8;
 constexpr int kSplitSlabs = 8;    // slabs up to which a short list is partitioned in registers
-constexpr uint32_t kChunk = kBuildChunk;
 
 // At most 64 VGPRs (8 waves per SIMD), so that four 8-wave workgroups share a
 // CU: the build is latency-bound, and its few spills sit outside the pass-1 loop.
@@ -632,7 +631,7 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
             // entries); one global atomic per chunk
             const uint32_t nres = n ? n + (uint32_t)kListPad : 0u;
             if (nres > chunk_left) {
-                const uint32_t want = nres > kChunk ? nres : kChunk;
+                const uint32_t want = nres > S.chunk ? nres : S.chunk;
                 uint32_t got = 0;
                 if (lane == 0) got = __hip_atomic_fetch_add(cursor, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 chunk_base = __shfl(got, 0, 64);
@@ -1002,7 +1001,7 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys*
             // bump-allocate the list and its pad entries from the wave's chunk
             const uint32_t nres = n ? n + (uint32_t)kListPad : 0u;
             if (nres > chunk_left) {
-                const uint32_t want = nres > kChunk ? nres : kChunk;
+                const uint32_t want = nres > S.chunk ? nres : S.chunk;
                 uint32_t got = 0;
                 if (lane == 0) got = __hip_atomic_fetch_add(cursor, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 chunk_base = __shfl(got, 0, 64);

@@ -74,6 +74,7 @@ def lib():
         "g3_accumulate": ([P, P, I32, I32, P, D, I32, I32, P, P], I32),
         "g3_accumulate_batch": ([P, P, I32], I32),
         "g3_accumulate_system": ([P, P], I32),
+        "g3_accumulate_noalloc": ([P, P], I32),
         "g3_hist_len3": ([I32, I32, I32], C.c_size_t),
         "g3_normalize3": ([P, I32, I32, I32, D, I64, I32, P, P], I32),
         "g3_sync": ([P], I32),
@@ -266,6 +267,13 @@ class Plan:
         arr = self._systems([dict(frames=frames, box=box, rmax=rmax, nbins=nbins, layout=layout,
                                   hist=hist, pair_hist=pair_hist, nbins_third=nbins_third)])
         _check(lib().g3_accumulate_system(self._h, arr), "g3_accumulate_system")
+
+    # -- g3_accumulate_noalloc: the plain form on the library's static scratch
+    def accumulate_noalloc(self, frames, box, rmax: float, nbins: int, layout: int, hist,
+                           pair_hist=None, nbins_third: int | None = None):
+        arr = self._systems([dict(frames=frames, box=box, rmax=rmax, nbins=nbins, layout=layout,
+                                  hist=hist, pair_hist=pair_hist, nbins_third=nbins_third)])
+        _check(lib().g3_accumulate_noalloc(self._h, arr), "g3_accumulate_noalloc")
 
     @staticmethod
     def _systems(systems: Sequence[dict]):

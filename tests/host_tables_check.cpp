@@ -25,6 +25,8 @@ void launch_triplet(const TripletArgs&, bool, int, bool, int, hipStream_t) {}
 void launch_reduce(const TripletArgs&, int, int, hipStream_t) {}
 void launch_expand(const Sys*, int, int, hipStream_t) {}
 hipError_t set_kernel_lds_limits(size_t, size_t, size_t) { return hipSuccess; }
+void* static_scratch(int, hipError_t* e) { *e = hipErrorNotSupported; return nullptr; }
+void launch_put_words(uint32_t*, const uint32_t*, size_t, hipStream_t) {}
 }  // namespace g3
 
 int main()

@@ -1,0 +1,68 @@
+"""GPU: the no-allocation entry point (g3_accumulate_noalloc) against the
+plain entry point it varies (g3_accumulate_system), bin for bin, on two calls
+in a row -- the large-system workload, then a smaller system with the full
+layout and the pair histogram -- synchronised once after both, and the
+rejection of a system whose scratch does not fit the static array."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_1708_08619_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.uint64)
+
+
+def test_noalloc_equals_plain_twice(torch_dev):
+    import torch
+    from paper_1708_08619_amd import g3
+    big = synth.lj_large(n_frames=2)                              # N = 65536, half layout
+    fr_s, box_s = synth.jittered_fcc(4000, 0.8, 0.1, 3, [97, 1])   # smaller, full layout
+    small = synth.Workload("small", fr_s, box_s, 2.5 * 4096, 50, g3.FULL)
+    cases = [(big, False), (small, True)]
+    dev_frames = [torch.from_numpy(w.frames).to(torch_dev) for w, _ in cases]
+    with g3.Plan() as plan:
+        got = []
+        for (w, pairs), fr in zip(cases, dev_frames):
+            h = g3.new_hist(w.nbins, w.layout, torch_dev)
+            ph = g3.new_pair_hist(w.nbins, torch_dev) if pairs else None
+            print(f"noalloc: N={w.n_atoms} frames={w.n_frames} layout={w.layout}", flush=True)
+            plan.accumulate_noalloc(fr, w.box, w.rmax, w.nbins, w.layout, h, pair_hist=ph)
+            got.append((h, ph))
+        plan.sync()
+        for ((w, pairs), fr), (h, ph) in zip(zip(cases, dev_frames), got):
+            ref = g3.new_hist(w.nbins, w.layout, torch_dev)
+            rph = g3.new_pair_hist(w.nbins, torch_dev) if pairs else None
+            plan.accumulate(fr, w.box, w.rmax, w.nbins, w.layout, ref, pair_hist=rph)
+            plan.sync()
+            assert int(_host(ref).sum()) > 0
+            assert np.array_equal(_host(h), _host(ref)), w.name
+            if pairs:
+                assert np.array_equal(_host(ph), _host(rph)), w.name
+
+
+def test_noalloc_rejects_what_does_not_fit(torch_dev):
+    import torch
+    from paper_1708_08619_amd import g3
+    N = 400000                                    # ~0.6 GB of neighbour lists per frame
+    frames, box = synth.jittered_fcc(N, 0.85, 0.15, 1, [97, 2])
+    h = g3.new_hist(60, g3.HALF, torch_dev)
+    with g3.Plan() as plan:
+        with pytest.raises(g3.G3Error) as e:
+            plan.accumulate_noalloc(torch.from_numpy(frames).to(torch_dev), box, 3.0 * 4096, 60,
+                                    g3.HALF, h)
+        assert e.value.status == g3.ENOMEM
+        plan.sync()
+    assert int(h.count_nonzero().item()) == 0
