@@ -218,10 +218,18 @@ __global__ void __launch_bounds__(256) k_cell_scatter(const Sys* __restrict__ sy
 // C <= 46340, products on the 24-bit multiplier).
 namespace {
 
-// The stencil of a cell: the home cell first, then the other cells.  Atoms
-// are ranked by their cell-sorted index, so in triangle-once mode the other
-// cells kept are those of higher cell index (all their atoms rank above the
-// home cell's), and "atom j ranks above the centre" is simply t > tself.
+// The stencil of a cell: the home cell first, then the other cells.  In
+// triangle-once mode an unordered pair belongs to one of its atoms: across
+// two cells, to the atom from whose cell the other cell lies at a
+// lexicographically positive offset (z first, then y, then x; stencil lanes
+// run in that order, so these are the lanes after the home lane); within a
+// cell, to the atom of lower cell-sorted index.  Every cell thus keeps 13
+// neighbour cells, wherever the periodic grid wraps, and "atom j ranks above
+// the centre" is simply t > tself.  A triangle accepted at one atom has
+// sides below rmax <= the cell width, so seen from any of its atoms the
+// three cells sit at the same unwrapped offsets (each component -1, 0 or 1):
+// the relation orders the three atoms totally and exactly one of them holds
+// the other two in its list.
 struct Stencil {
     int n;                 // stencil cells kept
     int start[27], pre[28];
@@ -374,7 +382,7 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
 
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
         const int c0 = p_c0, c1 = p_c1;
-        const int c = p_c, a = p_a, e_end = p_e, shx = p_sx, shy = p_sy, shz = p_sz;
+        const int a = p_a, e_end = p_e, shx = p_sx, shy = p_sy, shz = p_sz;
         fetch_cell(k + gridDim.x);
         if (c0 == c1) continue;   // uniform over the workgroup
         // stencil table: lane e of wave 0 takes stencil offset e; the home
@@ -382,8 +390,8 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
         // cells are distinct), then a prefix sum of the counts in that order
         if (wave == 0) {
             const int cnt_e = lane < nst ? e_end - a : 0;
-            const int c_home = __shfl(c, home, 64);
-            const bool other = lane < nst && lane != home && (!tri_once || c > c_home);
+            // (triangle-once: the lexicographically positive offsets)
+            const bool other = lane < nst && lane != home && (!tri_once || lane > home);
             const uint64_t om = __ballot(other);
             const int n_keep = 1 + (int)__popcll(om);
             int pos = -1;
@@ -898,7 +906,8 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys*
             ne = cs[ce + 1] - ae;
             ox = sx - refx; oy = sy - refy; oz = sz - refz;
         }
-        const bool other = lane < 27 && lane != 13 && (!tri_once || ce > cell);
+        // (triangle-once: the lexicographically positive offsets, lanes 14..26)
+        const bool other = lane < 27 && lane != 13 && (!tri_once || lane > 13);
         const uint64_t om = __ballot(other);
         const int n_keep = 1 + (int)__popcll(om);
         int pos = -1;
