@@ -185,10 +185,12 @@ void launch_cell_count(const Sys* sys, const Job* jobs, int n_jobs, int max_n, h
 void launch_cell_scan(const Sys* sys, const Job* jobs, int n_jobs, hipStream_t s);
 void launch_cell_scatter(const Sys* sys, const Job* jobs, int n_jobs, int max_n, hipStream_t s);
 size_t nbr_build_lds_bytes();
-// General build over every cell of every job, or (list) over the cells the
-// per-wave build left in each frame's overflow list.
+// General build over every cell of every job (list 0), or over the cells the
+// per-wave build left in each frame's overflow list: a few workgroups per
+// frame (list 1), or the full grid when some system leaves all its cells
+// there (list 2).
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
-                      bool one_step, bool list, unsigned long long* cnt, hipStream_t s);
+                      bool one_step, int list, unsigned long long* cnt, hipStream_t s);
 // Per-wave build (narrow entries): a wave stages one cell's stencil, at most
 // stage_cap atoms, as packed int16 coordinates and builds its centres' lists.
 constexpr int kWaveBuildWaves = kWaveBuildWavesPerWG;

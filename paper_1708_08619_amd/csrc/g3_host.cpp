@@ -570,6 +570,19 @@ bool pads_rejected(const Geometry& g)
     return s >= (uint64_t)g.R3;
 }
 
+// Atoms expected in a cell's stencil (the home cell and the neighbour cells
+// kept), and whether the per-wave build takes the system: its stencil fits
+// int16 and, with room for fluctuations, the largest stage.
+double expected_stencil(const Prepared& P)
+{
+    return (double)P.g.N / (double)P.g.ncell * (P.tri_once ? 14.0 : 27.0);
+}
+
+bool wave_build_fits(const Prepared& P)
+{
+    return P.g.pk_ok && 1.3 * expected_stencil(P) + 64.0 <= (double)kWaveStageMax;
+}
+
 Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
 {
     Sys s;
@@ -619,7 +632,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
     s.pool_cap = P.pool_cap;
     s.per_frame = P.per_frame;
     s.flags = flags;
-    s.pk_ok = g.pk_ok;
+    s.pk_ok = wave_build_fits(P) ? 1 : 0;
     s.ovf_cells = reinterpret_cast<int32_t*>(arena + P.off_ovf);
     s.chunk = P.per_frame ? kBuildChunk : kPlainChunk;
     return s;
@@ -628,9 +641,13 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
 // Neighbour build of a group: the per-wave build when some system qualifies
 // (then the general build over the cells it left), else the general build.
 // The wave's stage capacity covers the largest expected stencil with room
-// for fluctuations (a larger cell goes to the general build).
+// for fluctuations (a larger cell goes to the general build).  A system whose
+// expected stencil does not fit the largest stage (dense cells, or the
+// per-centre enumeration's full stencil) leaves all its cells to the general
+// build, which then runs on the full grid.
 struct BuildPlan {
-    bool wave = false;
+    bool wave = false;   // some system takes the per-wave build
+    bool rest = false;   // some system leaves all its cells to the general build
     int cap = 0;
 };
 
@@ -639,10 +656,12 @@ BuildPlan plan_build(const std::vector<Prepared>& ps)
     BuildPlan b;
     double t_max = 0;
     for (const auto& P : ps) {
-        if (!P.g.pk_ok) continue;
+        if (!wave_build_fits(P)) {
+            b.rest = true;
+            continue;
+        }
         b.wave = true;
-        const double per_cell = (double)P.g.N / (double)P.g.ncell;
-        t_max = std::max(t_max, per_cell * (P.tri_once ? 14.0 : 27.0));
+        t_max = std::max(t_max, expected_stencil(P));
     }
     if (b.wave) {
         const int want = (int)std::ceil(1.3 * t_max + 64.0);
@@ -656,9 +675,9 @@ void launch_build(const Sys* dsys, const Job* djobs, int nj, int max_cells, bool
 {
     if (bp.wave) {
         launch_nbr_wave(dsys, djobs, nj, max_cells, one_step, bp.cap, cnt, sm);
-        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, true, cnt, sm);
+        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, bp.rest ? 2 : 1, cnt, sm);
     } else {
-        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, false, cnt, sm);
+        launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, 0, cnt, sm);
     }
 }
 

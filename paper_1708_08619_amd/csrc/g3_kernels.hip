@@ -1695,9 +1695,11 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                 // run their A and B groups together instead of every A loop
                 // as long as the longest, then every B loop.  A run's last
                 // group may reach up to 3 entries past the list, into its pad
-                // entries, which every row rejects; the loads one group past
-                // the part (never evaluated) may read 4 entries further, into
-                // the next list or the pool slot's padding.
+                // entries, which every row rejects.  Narrow entries use three
+                // register groups, with the loads two groups ahead of the
+                // evaluation; the loads past the part (never evaluated) may
+                // read 8 entries further, into the next list or the pool
+                // slot's padding.  32-bit entries: two groups, one ahead.
                 const int nA = hasA ? min(g1, gA) - g0 : 0;
                 const int n = g1 - g0;
                 if (n <= 0) continue;
@@ -1710,22 +1712,51 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
                     vA = vB;
                 }
                 with_rows(vA, vB, [&](auto& evalg, auto&, auto& second) {
-                    uint32_t ko = ko0;
-                    int left = n;
-                    E gb[4];
-                    for (; left >= 2; left -= 2) {
-                        const bool s1 = ko == koSw;
-                        const uint32_t k1 = s1 ? koB : ko + 4u * ES;
+                    if constexpr (WIDE) {
+                        uint32_t ko = ko0;
+                        int left = n;
+                        E gb[4];
+                        for (; left >= 2; left -= 2) {
+                            const bool s1 = ko == koSw;
+                            const uint32_t k1 = s1 ? koB : ko + 4u * ES;
+                            pool.load4(k1, gb);
+                            evalg(gAv);
+                            if (s1) second();
+                            const bool s2 = k1 == koSw;
+                            ko = s2 ? koB : k1 + 4u * ES;
+                            pool.load4(ko, gAv);
+                            evalg(gb);
+                            if (s2) second();
+                        }
+                        if (left) evalg(gAv);
+                    } else {
+                        auto adv = [&](uint32_t k) -> uint32_t { return k == koSw ? koB : k + 4u * ES; };
+                        uint32_t ko = ko0;
+                        uint32_t k1 = adv(ko);
+                        E gb[4], gc[4];
                         pool.load4(k1, gb);
-                        evalg(gAv);
-                        if (s1) second();
-                        const bool s2 = k1 == koSw;
-                        ko = s2 ? koB : k1 + 4u * ES;
-                        pool.load4(ko, gAv);
-                        evalg(gb);
-                        if (s2) second();
+                        uint32_t k2 = adv(k1);
+                        int left = n;
+                        for (; left >= 3; left -= 3) {
+                            pool.load4(k2, gc);
+                            evalg(gAv);
+                            if (ko == koSw) second();
+                            const uint32_t k3 = adv(k2);
+                            pool.load4(k3, gAv);
+                            evalg(gb);
+                            if (k1 == koSw) second();
+                            const uint32_t k4 = adv(k3);
+                            pool.load4(k4, gb);
+                            evalg(gc);
+                            if (k2 == koSw) second();
+                            ko = k3; k1 = k4; k2 = adv(k4);
+                        }
+                        if (left) {
+                            evalg(gAv);
+                            if (ko == koSw) second();
+                            if (left == 2) evalg(gb);
+                        }
                     }
-                    if (left) evalg(gAv);
                 });
                 continue;
             }
@@ -1910,12 +1941,13 @@ size_t nbr_build_lds_bytes()
 }
 
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
-                      bool one_step, bool list, unsigned long long* cnt, hipStream_t s)
+                      bool one_step, int list, unsigned long long* cnt, hipStream_t s)
 {
     // enough workgroups per frame to fill the chip, each looping over cells
-    // (over the overflow list: a few per frame, most of which find it empty)
-    const int per_job = list ? std::min(build_wgs_per_job(n_jobs, max_cells), 8)
-                             : build_wgs_per_job(n_jobs, max_cells);
+    // (over the overflow list: a few per frame, most of which find it empty,
+    // unless some system leaves all its cells to it)
+    const int per_job = list == 1 ? std::min(build_wgs_per_job(n_jobs, max_cells), 8)
+                                  : build_wgs_per_job(n_jobs, max_cells);
     const size_t lds = nbr_build_lds_bytes();
     const dim3 g(per_job, n_jobs), b(kBuildThreads);
     const int lm = list ? 1 : 0;
