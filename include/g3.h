@@ -21,7 +21,14 @@
  *   rmax     cutoff in coordinate units (binary64, used exactly); requires
  *            1 <= rmax <= 46340 and 2*rmax < box[d] on every axis.
  *   nbins    bins per axis, 1..G3_MAX_NBINS; bin width dr = rmax / nbins,
- *            bins half-open [b dr, (b+1) dr), cutoff strict.
+ *            bins half-open [b dr, (b+1) dr), cutoff strict.  The accumulate
+ *            calls keep the histogram in LDS slabs of whole rows lo, at most
+ *            63 per system, each row holding (nbins - lo) * nbins_third
+ *            uint32 counters within the tuning's LDS histogram
+ *            (lds_hist_bins): with the default tuning nbins <= 147 when
+ *            nbins_third = nbins and <= 116 when nbins_third = 2 nbins
+ *            (139 and 110 at 2048 centres per item); a larger nbins makes
+ *            them return G3_EINVAL before queuing anything.
  *   layout   G3_HALF: unordered {j,k}, index ((rowoff(lo) + hi - lo) * nbins + c)
  *            with lo = min(b_ij, b_ik), hi = max, c = b_jk and
  *            rowoff(lo) = lo*nbins - lo*(lo-1)/2; nbins*nbins*(nbins+1)/2 bins.

@@ -225,11 +225,11 @@ namespace {
 // run in that order, so these are the lanes after the home lane); within a
 // cell, to the atom of lower cell-sorted index.  Every cell thus keeps 13
 // neighbour cells, wherever the periodic grid wraps, and "atom j ranks above
-// the centre" is simply t > tself.  A triangle accepted at one atom has
-// sides below rmax <= the cell width, so seen from any of its atoms the
-// three cells sit at the same unwrapped offsets (each component -1, 0 or 1):
-// the relation orders the three atoms totally and exactly one of them holds
-// the other two in its list.
+// the centre" is simply t > tself.  Every component of an accepted side is
+// at most C - 1, and cells are at least C - 1 wide, so seen from any atom of
+// an accepted triangle the three cells sit at the same unwrapped offsets
+// (each component -1, 0 or 1): the relation orders the three atoms totally
+// and exactly one of them holds the other two in its list.
 struct Stencil {
     int n;                 // stencil cells kept
     int start[27], pre[28];
