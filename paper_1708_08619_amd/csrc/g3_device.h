@@ -40,6 +40,18 @@ constexpr uint32_t kFlagDense = 8u;    // a list longer than m_safe: recomputed 
 // Neighbour entry (minimum-image vector d_ij and its pair bin b):
 //  narrow (C <= 32767): x = (dx & 0xffff) | dy << 16, y = (dz & 0xffff) | (b * nbins) << 16
 //  wide:                int4 {dx, dy, dz, b * nbins}
+// Reference point of cell k (0 <= k < nc <= 1024) on an axis of L < 2^29
+// units: the cell's midpoint (2k+1) L / (2 nc), from the width floor(L 2^20 /
+// nc) in fixed point, rounded down; within one unit of the exact midpoint.
+__host__ __device__ inline uint64_t cell_mid_step(int L, int nc)
+{
+    return ((uint64_t)L << 20) / (uint64_t)nc;
+}
+__host__ __device__ inline int cell_mid(uint64_t step, int k)
+{
+    return (int)(((uint64_t)(2 * k + 1) * step) >> 21);
+}
+
 struct Sys {
     // inputs
     const int32_t* frames;   // [F][3][N]
@@ -51,6 +63,7 @@ struct Sys {
     int32_t F, N;
     int32_t box[3];
     int32_t nc[3];           // cells per axis; 1 means "whole axis, explicit minimum image"
+    uint64_t mid_q[3];       // cell width in 2^-20 units (cell_mid_step), for cell_mid
     int32_t ncell;
     int32_t C;               // ceil(rmax): every accepted component satisfies |d| <= C-1
     uint32_t R2;             // thr[nbins]: a pair is accepted iff s < R2
@@ -160,13 +173,22 @@ inline int build_wgs_per_job(int n_jobs, int max_cells)
     return per_job < 1 ? 1 : per_job;
 }
 
-// Workgroups per job of the per-wave build: about two rounds of resident
-// workgroups over the batch, at most one cell per wave.
-constexpr int kWaveBuildWavesPerWG = 8;
-inline int wave_wgs_per_job(int n_jobs, int max_cells)
+// Per-wave build: 4-wave workgroups (one wave per SIMD, so that as many fit
+// as LDS and registers allow), at most six per CU (the kernel's VGPR budget
+// gives six waves per SIMD).  Workgroups per job: about four rounds of the
+// workgroups resident at once on 256 CUs, at most one cell per wave.
+constexpr size_t kLdsPerCU = 160 * 1024;
+constexpr int kWaveBuildWavesPerWG = 4;
+constexpr int kWaveBuildMaxWgsPerCU = 6;
+inline int wave_wgs_per_cu(size_t lds_bytes)
+{
+    const int n = (int)(kLdsPerCU / (lds_bytes > 0 ? lds_bytes : 1));
+    return n < 1 ? 1 : (n > kWaveBuildMaxWgsPerCU ? kWaveBuildMaxWgsPerCU : n);
+}
+inline int wave_wgs_per_job(int n_jobs, int max_cells, int wgs_per_cu)
 {
     const int cells_wg = (max_cells + kWaveBuildWavesPerWG - 1) / kWaveBuildWavesPerWG;
-    int per_job = 1024 / (n_jobs > 0 ? n_jobs : 1);
+    int per_job = 4 * 256 * wgs_per_cu / (n_jobs > 0 ? n_jobs : 1);
     if (per_job > cells_wg) per_job = cells_wg;
     return per_job < 1 ? 1 : per_job;
 }
@@ -191,15 +213,15 @@ size_t nbr_build_lds_bytes();
 // there (list 2).
 void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool wide,
                       bool one_step, int list, unsigned long long* cnt, hipStream_t s);
+// Bin lookups of the triplet kernel and the per-wave build: u8 table then
+// threshold steps (loop or one step), or the step table.
+enum Lookup : int { kLookupSteps = 0, kLookupOneStep = 1, kLookupStepTable = 2 };
 // Per-wave build (narrow entries): a wave stages one cell's stencil, at most
 // stage_cap atoms, as packed int16 coordinates and builds its centres' lists.
 constexpr int kWaveBuildWaves = kWaveBuildWavesPerWG;
 size_t nbr_wave_lds_bytes(int stage_cap);
-void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool one_step,
+void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int lookup,
                      int stage_cap, unsigned long long* cnt, hipStream_t s);
-// Bin lookups of the triplet kernel: u8 table then threshold steps (loop or
-// one step), or the step table.
-enum Lookup : int { kLookupSteps = 0, kLookupOneStep = 1, kLookupStepTable = 2 };
 void launch_triplet(const TripletArgs& a, bool wide, int lookup, bool padded, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
 void launch_expand(const Sys* sys, int n_sys, int max_nbins, hipStream_t s);

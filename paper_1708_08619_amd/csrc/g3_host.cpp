@@ -25,9 +25,8 @@ using namespace g3;
 
 constexpr int kTabMax = kTabBytes;   // bytes of the bin lookup table in LDS
 constexpr int kFlagLogCap = 1 << 20; // per-frame flags kept until g3_sync
-constexpr size_t kLdsPerCU = 160 * 1024;
-constexpr int kWaveStageMax = 1024;
-static_assert(G3_NOALLOC_BYTES == g3::kStaticScratchBytes, "static scratch size");    // largest stencil a wave of the per-wave build stages
+constexpr int kWaveStageMax = 1024;  // largest stencil a wave of the per-wave build stages
+static_assert(G3_NOALLOC_BYTES == g3::kStaticScratchBytes, "static scratch size");
 
 #define G3_TRY_HIP(expr)                         \
     do {                                         \
@@ -477,7 +476,8 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
     // (each wave of the per-wave build and of the general build may leave a
     // chunk's tail unused)
     const int64_t slack = ((int64_t)build_wgs_per_job(n_jobs, max_cells) * kBuildWavesPerWG +
-                           (int64_t)wave_wgs_per_job(n_jobs, max_cells) * kWaveBuildWaves) *
+                           (int64_t)wave_wgs_per_job(n_jobs, max_cells, kWaveBuildMaxWgsPerCU) *
+                               kWaveBuildWaves) *
                           (per_frame ? kBuildChunk : kPlainChunk);
     for (auto& P : ps) {
         const Geometry& g = P.g;
@@ -594,7 +594,11 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
     s.tri = P.tri_once ? reinterpret_cast<uint64_t*>(arena + P.off_tri) : nullptr;
     s.F = P.in.n_frames;
     s.N = g.N;
-    for (int d = 0; d < 3; ++d) { s.box[d] = g.box[d]; s.nc[d] = g.nc[d]; }
+    for (int d = 0; d < 3; ++d) {
+        s.box[d] = g.box[d];
+        s.nc[d] = g.nc[d];
+        s.mid_q[d] = cell_mid_step(g.box[d], g.nc[d]);
+    }
     s.ncell = g.ncell;
     s.C = g.C;
     s.R2 = g.R2;
@@ -671,10 +675,10 @@ BuildPlan plan_build(const std::vector<Prepared>& ps)
 }
 
 void launch_build(const Sys* dsys, const Job* djobs, int nj, int max_cells, bool wide, bool one_step,
-                  const BuildPlan& bp, unsigned long long* cnt, hipStream_t sm)
+                  int lookup, const BuildPlan& bp, unsigned long long* cnt, hipStream_t sm)
 {
     if (bp.wave) {
-        launch_nbr_wave(dsys, djobs, nj, max_cells, one_step, bp.cap, cnt, sm);
+        launch_nbr_wave(dsys, djobs, nj, max_cells, lookup, bp.cap, cnt, sm);
         launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, bp.rest ? 2 : 1, cnt, sm);
     } else {
         launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, 0, cnt, sm);
@@ -947,7 +951,8 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
         launch_cell_scatter(dsys, j, 1, N, p->stream);
         timing_end(p, ec);
         timing_begin(p, &eb, G3_STAGE_NEIGHBOURS);
-        launch_build(dsys, j, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, bp, p->build_cnt, p->stream);
+        launch_build(dsys, j, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, lookup_of(P.g), bp,
+                     p->build_cnt, p->stream);
         timing_end(p, eb);
         launch_zero_u32((uint32_t*)p->ctl, sizeof(Ctl) / 4, p->stream);
         if (tri.second > tri.first)
@@ -1064,7 +1069,8 @@ g3_status run_plain_noalloc(g3_plan p, const g3_system& s, bool worst_case)
         launch_cell_count(dsys, djob, 1, N, p->stream);
         launch_cell_scan(dsys, djob, 1, p->stream);
         launch_cell_scatter(dsys, djob, 1, N, p->stream);
-        launch_build(dsys, djob, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, bp, nullptr, p->stream);
+        launch_build(dsys, djob, 1, P.g.ncell, P.g.wide != 0, P.g.one_step != 0, lookup_of(P.g), bp, nullptr,
+                     p->stream);
         launch_zero_u32((uint32_t*)(B + kNaCtl), sizeof(Ctl) / 4, p->stream);
         if (tri.second > tri.first)
             launch_zero_u32((uint32_t*)(B + tri.first), (tri.second - tri.first) / 4, p->stream);
@@ -1160,6 +1166,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         put(&lookup, sizeof(lookup));
         put(&padded, sizeof(padded));
         put(&bp.wave, sizeof(bp.wave));
+        put(&bp.rest, sizeof(bp.rest));
         put(&bp.cap, sizeof(bp.cap));
         // tuning fields one by one (the struct's padding bytes are undefined)
         const int32_t tk[5] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0, tn.slot_limit};
@@ -1215,7 +1222,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_count(dsys, djobs, nj, max_n, sm);
             launch_cell_scan(dsys, djobs, nj, sm);
             launch_cell_scatter(dsys, djobs, nj, max_n, sm);
-            launch_build(dsys, djobs, nj, max_cells, wide, one_step, bp, p->build_cnt, sm);
+            launch_build(dsys, djobs, nj, max_cells, wide, one_step, lookup, bp, p->build_cnt, sm);
             launch_triplet(a, wide, lookup, padded, n_wg, sm);
             launch_reduce(a, max_hb, ns, sm);
             if (any_tri) launch_expand(dsys, n_sys, max_nb, sm);
@@ -1231,7 +1238,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             launch_cell_scatter(dsys, djobs, nj, max_n, p->stream);
             timing_end(p, ec);
             timing_begin(p, &eb, G3_STAGE_NEIGHBOURS);
-            launch_build(dsys, djobs, nj, max_cells, wide, one_step, bp, p->build_cnt, p->stream);
+            launch_build(dsys, djobs, nj, max_cells, wide, one_step, lookup, bp, p->build_cnt, p->stream);
             timing_end(p, eb);
             hipEvent_t e0;
             timing_begin(p, &e0);

@@ -748,25 +748,31 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
 namespace {
 
 constexpr int kStagePad = 64;
-constexpr uint32_t kWaveShared = 4 * kThrMax + 8192 + 256;   // thr, bin table, bin -> slab
+constexpr uint32_t kWaveShared = 256;   // bin -> slab
 
 struct WaveLds {   // byte offsets inside one wave's LDS region
     uint32_t stage, idx, scnt, g2, pre, start, offx, offy, offz, size;
 };
 
+// The stencil-cell table (pre, start, offx/y/z) is needed only while the
+// stage is filled and the index list only after it, so the two share
+// bytes: six 4-wave workgroups with a stage of 512 atoms then fit in one
+// CU's LDS.
 __host__ __device__ inline WaveLds wave_lds(int cap)
 {
     WaveLds w;
     uint32_t o = 0;
     w.stage = o; o += (uint32_t)(cap + kStagePad) * 8u;
-    w.idx = o;   o += ((uint32_t)cap * 2u + 15u) & ~15u;
+    w.idx = o;
+    w.pre = o;
+    w.start = o + 32u * 4u;
+    w.offx = o + 64u * 4u;
+    w.offy = o + 96u * 4u;
+    w.offz = o + 128u * 4u;
+    const uint32_t ib = (uint32_t)cap * 2u > 160u * 4u ? (uint32_t)cap * 2u : 160u * 4u;
+    o += (ib + 15u) & ~15u;
     w.scnt = o;  o += 64u * 4u;
     w.g2 = o;    o += (uint32_t)kNbinsMax * 4u;
-    w.pre = o;   o += 32u * 4u;
-    w.start = o; o += 32u * 4u;
-    w.offx = o;  o += 32u * 4u;
-    w.offy = o;  o += 32u * 4u;
-    w.offz = o;  o += 32u * 4u;
     w.size = o;
     return w;
 }
@@ -778,15 +784,13 @@ __device__ __forceinline__ uint32_t as_u32(short2p v) { return __builtin_bit_cas
 
 }  // namespace
 
-template <bool ONE_STEP>
-__global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys* __restrict__ sys,
+template <int LOOKUP>
+__global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k_nbr_wave(const Sys* __restrict__ sys,
                                                                    const Job* __restrict__ jobs,
                                                                    int cap, unsigned long long* cnt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* s_thr = reinterpret_cast<uint32_t*>(smem);                    // [kThrMax]
-    uint8_t* s_tab = reinterpret_cast<uint8_t*>(s_thr + kThrMax);           // [8192]
-    uint8_t* s_slab = s_tab + 8192;                                          // [256] bin -> slab
+    uint8_t* s_slab = smem;                                                  // [256] bin -> slab
     const WaveLds WL = wave_lds(cap);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     unsigned char* wb = smem + kWaveShared + (size_t)wave * WL.size;
@@ -827,12 +831,11 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys*
     const uint32_t pair_inc = tri_once ? 2u : 1u;
 
     // bin tables and the bin -> slab map, once per workgroup
-    for (int x = tid; x <= nb3; x += kWaveBuildWaves * 64) s_thr[x] = gp(S.thr)[x];
-    {
-        const int n4 = (S.tab_len + 3) / 4;
-        const gptr<const uint32_t> src = gp(reinterpret_cast<const uint32_t*>(S.tab));
-        for (int x = tid; x < n4; x += kWaveBuildWaves * 64) reinterpret_cast<uint32_t*>(s_tab)[x] = src[x];
-    }
+    // the bin tables (a few KB) are read through the vector cache, which
+    // keeps LDS for the stages: up to six 4-wave workgroups share a CU
+    const gptr<const uint32_t> g_thr = gp(S.thr);
+    const gptr<const uint8_t> g_tab = gp(S.tab);
+    const gptr<const uint32_t> g_step = gp(S.step);
     for (int b = tid; b < 256; b += kWaveBuildWaves * 64) {
         int q = 0;
         while (q + 1 < n_slabs && S.slab_lo[q + 1] <= b) ++q;
@@ -864,12 +867,16 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys*
     };
     auto bin_of = [&](uint32_t s) -> int {
         int b;
-        if constexpr (ONE_STEP) {
-            b = s_tab[__builtin_amdgcn_ubfe(s, (uint32_t)sh, (uint32_t)tbits)];
-            b += (s >= s_thr[b + 1]) ? 1 : 0;
+        if constexpr (LOOKUP == kLookupStepTable) {
+            // one read: the cell's bin and the offset of its inner threshold
+            const uint32_t ssh = (uint32_t)S.step_sh;
+            b = (int)((g_step[__builtin_amdgcn_ubfe(s, ssh, (uint32_t)S.step_bits)] + s) >> ssh);
+        } else if constexpr (LOOKUP == kLookupOneStep) {
+            b = g_tab[__builtin_amdgcn_ubfe(s, (uint32_t)sh, (uint32_t)tbits)];
+            b += (s >= g_thr[b + 1]) ? 1 : 0;
         } else {
-            b = s_tab[s >> sh];
-            while (s >= s_thr[b + 1]) ++b;
+            b = g_tab[s >> sh];
+            while (s >= g_thr[b + 1]) ++b;
         }
         return b;
     };
@@ -886,14 +893,15 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, 4) k_nbr_wave(const Sys*
             push_ovf(cell);
             continue;
         }
+        wave_sync();   // the previous cell's index list shares bytes with the cell table
         // stencil: lane e < 27 takes offset e; the home cell (e = 13) goes to
         // position 0, the kept others follow in lane order
         const int kx = cell % ncx, ky = (cell / ncx) % ncy, kz = cell / (ncx * ncy);
         // the home cell's midpoint (any point within a unit or two will do:
         // the host bound leaves a margin)
-        const int refx = (int)((double)(2 * kx + 1) * (double)Lx / (double)(2 * ncx));
-        const int refy = (int)((double)(2 * ky + 1) * (double)Ly / (double)(2 * ncy));
-        const int refz = (int)((double)(2 * kz + 1) * (double)Lz / (double)(2 * ncz));
+        const int refx = cell_mid(S.mid_q[0], kx);
+        const int refy = cell_mid(S.mid_q[1], ky);
+        const int refz = cell_mid(S.mid_q[2], kz);
         int ce = 0x7fffffff, ae = 0, ne = 0, ox = 0, oy = 0, oz = 0;
         if (lane < 27) {
             int x = kx + lane % 3 - 1, y = ky + (lane / 3) % 3 - 1, z = kz + lane / 9 - 1;
@@ -1965,16 +1973,20 @@ size_t nbr_wave_lds_bytes(int stage_cap)
     return kWaveShared + (size_t)kWaveBuildWaves * wave_lds(stage_cap).size;
 }
 
-void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, bool one_step,
+void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int lookup,
                      int stage_cap, unsigned long long* cnt, hipStream_t s)
 {
-    // about two rounds of resident workgroups over the whole batch; a wave
-    // takes cells blockIdx.x * 8 + wave + k * gridDim.x * 8
-    const int per_job = wave_wgs_per_job(n_jobs, max_cells);
+    // about four rounds of resident workgroups over the whole batch; a wave
+    // takes cells blockIdx.x * 4 + wave + k * gridDim.x * 4
     const size_t lds = nbr_wave_lds_bytes(stage_cap);
+    const int per_job = wave_wgs_per_job(n_jobs, max_cells, wave_wgs_per_cu(lds));
     const dim3 g(per_job, n_jobs), b(kWaveBuildWaves * 64);
-    if (one_step) hipLaunchKernelGGL((k_nbr_wave<true>), g, b, lds, s, sys, jobs, stage_cap, cnt);
-    else hipLaunchKernelGGL((k_nbr_wave<false>), g, b, lds, s, sys, jobs, stage_cap, cnt);
+    if (lookup == kLookupStepTable)
+        hipLaunchKernelGGL((k_nbr_wave<kLookupStepTable>), g, b, lds, s, sys, jobs, stage_cap, cnt);
+    else if (lookup == kLookupOneStep)
+        hipLaunchKernelGGL((k_nbr_wave<kLookupOneStep>), g, b, lds, s, sys, jobs, stage_cap, cnt);
+    else
+        hipLaunchKernelGGL((k_nbr_wave<kLookupSteps>), g, b, lds, s, sys, jobs, stage_cap, cnt);
 }
 
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes, size_t wave_build_bytes)

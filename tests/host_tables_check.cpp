@@ -20,7 +20,7 @@ void launch_cell_scatter(const Sys*, const Job*, int, int, hipStream_t) {}
 size_t nbr_build_lds_bytes() { return 0; }
 void launch_nbr_build(const Sys*, const Job*, int, int, bool, bool, int, unsigned long long*, hipStream_t) {}
 size_t nbr_wave_lds_bytes(int) { return 0; }
-void launch_nbr_wave(const Sys*, const Job*, int, int, bool, int, unsigned long long*, hipStream_t) {}
+void launch_nbr_wave(const Sys*, const Job*, int, int, int, int, unsigned long long*, hipStream_t) {}
 void launch_triplet(const TripletArgs&, bool, int, bool, int, hipStream_t) {}
 void launch_reduce(const TripletArgs&, int, int, hipStream_t) {}
 void launch_expand(const Sys*, int, int, hipStream_t) {}
@@ -133,7 +133,7 @@ int main()
         if (g.pk_ok) {
             auto lo_of = [&](int64_t k) { return (k * L + nc - 1) / nc; };   // least x in cell k
             for (int k = 0; k < nc; ++k) {
-                const int ref = (int)((double)(2 * k + 1) * (double)L / (double)(2 * nc));
+                const int ref = cell_mid(cell_mid_step(L, nc), k);
                 for (int o = -1; o <= 1; ++o) {
                     int kk = k + o, shift = 0;
                     if (kk < 0) { kk += nc; shift = -L; } else if (kk >= nc) { kk -= nc; shift = L; }

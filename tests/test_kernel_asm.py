@@ -61,7 +61,7 @@ def test_hot_kernels_use_no_flat_memory_instructions(asm):
     so an LDS wait would also wait for outstanding global accesses: the
     neighbour build and the triplet kernel address global memory through
     global-address-space pointers only."""
-    for name, count in (("k_triplet", 9), ("k_nbr_build", 4), ("k_nbr_wave", 2)):
+    for name, count in (("k_triplet", 9), ("k_nbr_build", 4), ("k_nbr_wave", 3)):
         bodies = _bodies(asm, name)
         assert len(bodies) == count, name
         for sym, body in bodies.items():
@@ -69,13 +69,14 @@ def test_hot_kernels_use_no_flat_memory_instructions(asm):
 
 
 def test_wave_build_fits_its_occupancy(asm):
-    """The per-wave neighbour build runs two 8-wave workgroups per CU (four
-    waves per SIMD): at most 128 VGPRs, no spills, no static LDS."""
+    """The per-wave neighbour build runs up to six 4-wave workgroups per CU
+    (six waves per SIMD): at most 80 VGPRs, no spills, no static LDS."""
     bodies = _bodies(asm, "k_nbr_wave")
-    assert len(bodies) == 2
+    assert len(bodies) == 3
     for sym in bodies:
         i = asm.index(".name:           " + sym)
         meta = asm[asm.rindex("\n  - ", 0, i):asm.find("\n  - ", i)]
-        assert int(re.search(r"\.vgpr_count:\s+(\d+)", meta).group(1)) <= 128, sym
+        assert int(re.search(r"\.vgpr_count:\s+(\d+)", meta).group(1)) <= 80, sym
+        assert re.search(r"\.private_segment_fixed_size:\s+0\b", meta), sym
         assert re.search(r"\.vgpr_spill_count:\s+0\b", meta), sym
         assert re.search(r"\.group_segment_fixed_size:\s+0\b", meta), sym
