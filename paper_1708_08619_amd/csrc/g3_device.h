@@ -174,15 +174,17 @@ inline int build_wgs_per_job(int n_jobs, int max_cells)
 }
 
 // Per-wave build: 4-wave workgroups (one wave per SIMD, so that as many fit
-// as LDS and registers allow), at most six per CU (the kernel's VGPR budget
-// gives six waves per SIMD).  Workgroups per job: about four rounds of the
+// as LDS and registers allow), at most seven per CU (the kernel's VGPR
+// budget gives seven waves per SIMD).  Workgroups per job: about four rounds of the
 // workgroups resident at once on 256 CUs, at most one cell per wave.
 constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int kWaveBuildWavesPerWG = 4;
-constexpr int kWaveBuildMaxWgsPerCU = 6;
+constexpr int kWaveBuildMaxWgsPerCU = 7;
 inline int wave_wgs_per_cu(size_t lds_bytes)
 {
-    const int n = (int)(kLdsPerCU / (lds_bytes > 0 ? lds_bytes : 1));
+    // LDS is granted in blocks of 512 bytes
+    const size_t blocks = (lds_bytes + 511) / 512;
+    const int n = (int)(kLdsPerCU / (blocks > 0 ? blocks * 512 : 512));
     return n < 1 ? 1 : (n > kWaveBuildMaxWgsPerCU ? kWaveBuildMaxWgsPerCU : n);
 }
 inline int wave_wgs_per_job(int n_jobs, int max_cells, int wgs_per_cu)
@@ -219,9 +221,11 @@ enum Lookup : int { kLookupSteps = 0, kLookupOneStep = 1, kLookupStepTable = 2 }
 // Per-wave build (narrow entries): a wave stages one cell's stencil, at most
 // stage_cap atoms, as packed int16 coordinates and builds its centres' lists.
 constexpr int kWaveBuildWaves = kWaveBuildWavesPerWG;
-size_t nbr_wave_lds_bytes(int stage_cap);
+// `pairs`: some system of the launch counts the pair histogram (each wave
+// then holds pair counters in LDS).
+size_t nbr_wave_lds_bytes(int stage_cap, bool pairs);
 void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int lookup,
-                     int stage_cap, unsigned long long* cnt, hipStream_t s);
+                     int stage_cap, bool pairs, unsigned long long* cnt, hipStream_t s);
 void launch_triplet(const TripletArgs& a, bool wide, int lookup, bool padded, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);
 void launch_expand(const Sys* sys, int n_sys, int max_nbins, hipStream_t s);

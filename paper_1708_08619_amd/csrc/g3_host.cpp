@@ -580,7 +580,7 @@ double expected_stencil(const Prepared& P)
 
 bool wave_build_fits(const Prepared& P)
 {
-    return P.g.pk_ok && 1.3 * expected_stencil(P) + 64.0 <= (double)kWaveStageMax;
+    return P.g.pk_ok && 1.2 * expected_stencil(P) + 64.0 <= (double)kWaveStageMax;
 }
 
 Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
@@ -652,6 +652,7 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
 struct BuildPlan {
     bool wave = false;   // some system takes the per-wave build
     bool rest = false;   // some system leaves all its cells to the general build
+    bool pairs = false;  // some system of the per-wave build counts pairs
     int cap = 0;
 };
 
@@ -665,11 +666,12 @@ BuildPlan plan_build(const std::vector<Prepared>& ps)
             continue;
         }
         b.wave = true;
+        b.pairs = b.pairs || P.in.pair_hist != nullptr;
         t_max = std::max(t_max, expected_stencil(P));
     }
     if (b.wave) {
-        const int want = (int)std::ceil(1.3 * t_max + 64.0);
-        b.cap = std::min(kWaveStageMax, std::max(256, (want + 63) & ~63));
+        const int want = (int)std::ceil(1.2 * t_max + 64.0);
+        b.cap = std::min(kWaveStageMax, std::max(256, (want + 15) & ~15));
     }
     return b;
 }
@@ -678,7 +680,7 @@ void launch_build(const Sys* dsys, const Job* djobs, int nj, int max_cells, bool
                   int lookup, const BuildPlan& bp, unsigned long long* cnt, hipStream_t sm)
 {
     if (bp.wave) {
-        launch_nbr_wave(dsys, djobs, nj, max_cells, lookup, bp.cap, cnt, sm);
+        launch_nbr_wave(dsys, djobs, nj, max_cells, lookup, bp.cap, bp.pairs, cnt, sm);
         launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, bp.rest ? 2 : 1, cnt, sm);
     } else {
         launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, 0, cnt, sm);
@@ -864,7 +866,7 @@ g3_status upload_geometry(g3_plan p, const std::vector<Prepared>& ps)
 g3_status set_lds_limits(g3_plan p)
 {
     if (p->lds_set) return G3_OK;
-    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_build_lds_bytes(), nbr_wave_lds_bytes(kWaveStageMax)));
+    G3_TRY_HIP(set_kernel_lds_limits(kLdsPerCU - 256, nbr_build_lds_bytes(), nbr_wave_lds_bytes(kWaveStageMax, true)));
     p->lds_set = true;
     return G3_OK;
 }
@@ -1167,6 +1169,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         put(&padded, sizeof(padded));
         put(&bp.wave, sizeof(bp.wave));
         put(&bp.rest, sizeof(bp.rest));
+        put(&bp.pairs, sizeof(bp.pairs));
         put(&bp.cap, sizeof(bp.cap));
         // tuning fields one by one (the struct's padding bytes are undefined)
         const int32_t tk[5] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0, tn.slot_limit};

@@ -756,9 +756,10 @@ struct WaveLds {   // byte offsets inside one wave's LDS region
 
 // The stencil-cell table (pre, start, offx/y/z) is needed only while the
 // stage is filled and the index list only after it, so the two share
-// bytes: six 4-wave workgroups with a stage of 512 atoms then fit in one
-// CU's LDS.
-__host__ __device__ inline WaveLds wave_lds(int cap)
+// bytes; the pair-histogram counters exist only in launches that count
+// pairs.  Seven 4-wave workgroups with a stage of 480 atoms and no pair
+// counters then fit in one CU's LDS.
+__host__ __device__ inline WaveLds wave_lds(int cap, bool g2)
 {
     WaveLds w;
     uint32_t o = 0;
@@ -772,7 +773,7 @@ __host__ __device__ inline WaveLds wave_lds(int cap)
     const uint32_t ib = (uint32_t)cap * 2u > 160u * 4u ? (uint32_t)cap * 2u : 160u * 4u;
     o += (ib + 15u) & ~15u;
     w.scnt = o;  o += 64u * 4u;
-    w.g2 = o;    o += (uint32_t)kNbinsMax * 4u;
+    w.g2 = o;    o += g2 ? (uint32_t)kNbinsMax * 4u : 0u;
     w.size = o;
     return w;
 }
@@ -787,11 +788,12 @@ __device__ __forceinline__ uint32_t as_u32(short2p v) { return __builtin_bit_cas
 template <int LOOKUP>
 __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k_nbr_wave(const Sys* __restrict__ sys,
                                                                    const Job* __restrict__ jobs,
-                                                                   int cap, unsigned long long* cnt)
+                                                                   int cap, int with_g2,
+                                                                   unsigned long long* cnt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint8_t* s_slab = smem;                                                  // [256] bin -> slab
-    const WaveLds WL = wave_lds(cap);
+    const WaveLds WL = wave_lds(cap, with_g2 != 0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     unsigned char* wb = smem + kWaveShared + (size_t)wave * WL.size;
     uint2* stage = reinterpret_cast<uint2*>(wb + WL.stage);
@@ -826,7 +828,8 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k
     const gptr<uint16_t> slab_j = gp(S.slab_j + fr_off(S, f, (size_t)N * (n_slabs + 1)));
     const size_t pbase = S.per_frame ? (size_t)f * (size_t)(pool_cap + kPoolPad) : 0;
     const gptr<uint2> pool = gp(reinterpret_cast<uint2*>(S.pool) + pbase);
-    uint64_t* const pair_hist = S.pair_hist;
+    // (a launch without pair counters has no system that counts pairs)
+    uint64_t* const pair_hist = with_g2 ? S.pair_hist : nullptr;
     const bool tri_once = S.tri != nullptr;
     const uint32_t pair_inc = tri_once ? 2u : 1u;
 
@@ -841,7 +844,8 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k
         while (q + 1 < n_slabs && S.slab_lo[q + 1] <= b) ++q;
         s_slab[b] = (uint8_t)q;
     }
-    for (int b = lane; b < kNbinsMax; b += 64) g2w[b] = 0u;
+    if (with_g2)
+        for (int b = lane; b < kNbinsMax; b += 64) g2w[b] = 0u;
     __syncthreads();   // the only workgroup barrier: waves work alone from here
 
     uint32_t g2_pending = 0;   // increments held in this wave's pair counters
@@ -1968,25 +1972,26 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
     }
 }
 
-size_t nbr_wave_lds_bytes(int stage_cap)
+size_t nbr_wave_lds_bytes(int stage_cap, bool pairs)
 {
-    return kWaveShared + (size_t)kWaveBuildWaves * wave_lds(stage_cap).size;
+    return kWaveShared + (size_t)kWaveBuildWaves * wave_lds(stage_cap, pairs).size;
 }
 
 void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int lookup,
-                     int stage_cap, unsigned long long* cnt, hipStream_t s)
+                     int stage_cap, bool pairs, unsigned long long* cnt, hipStream_t s)
 {
     // about four rounds of resident workgroups over the whole batch; a wave
     // takes cells blockIdx.x * 4 + wave + k * gridDim.x * 4
-    const size_t lds = nbr_wave_lds_bytes(stage_cap);
+    const size_t lds = nbr_wave_lds_bytes(stage_cap, pairs);
+    const int g2 = pairs ? 1 : 0;
     const int per_job = wave_wgs_per_job(n_jobs, max_cells, wave_wgs_per_cu(lds));
     const dim3 g(per_job, n_jobs), b(kWaveBuildWaves * 64);
     if (lookup == kLookupStepTable)
-        hipLaunchKernelGGL((k_nbr_wave<kLookupStepTable>), g, b, lds, s, sys, jobs, stage_cap, cnt);
+        hipLaunchKernelGGL((k_nbr_wave<kLookupStepTable>), g, b, lds, s, sys, jobs, stage_cap, g2, cnt);
     else if (lookup == kLookupOneStep)
-        hipLaunchKernelGGL((k_nbr_wave<kLookupOneStep>), g, b, lds, s, sys, jobs, stage_cap, cnt);
+        hipLaunchKernelGGL((k_nbr_wave<kLookupOneStep>), g, b, lds, s, sys, jobs, stage_cap, g2, cnt);
     else
-        hipLaunchKernelGGL((k_nbr_wave<kLookupSteps>), g, b, lds, s, sys, jobs, stage_cap, cnt);
+        hipLaunchKernelGGL((k_nbr_wave<kLookupSteps>), g, b, lds, s, sys, jobs, stage_cap, g2, cnt);
 }
 
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes, size_t wave_build_bytes)

@@ -19,8 +19,8 @@ void launch_cell_scan(const Sys*, const Job*, int, hipStream_t) {}
 void launch_cell_scatter(const Sys*, const Job*, int, int, hipStream_t) {}
 size_t nbr_build_lds_bytes() { return 0; }
 void launch_nbr_build(const Sys*, const Job*, int, int, bool, bool, int, unsigned long long*, hipStream_t) {}
-size_t nbr_wave_lds_bytes(int) { return 0; }
-void launch_nbr_wave(const Sys*, const Job*, int, int, int, int, unsigned long long*, hipStream_t) {}
+size_t nbr_wave_lds_bytes(int, bool) { return 0; }
+void launch_nbr_wave(const Sys*, const Job*, int, int, int, int, bool, unsigned long long*, hipStream_t) {}
 void launch_triplet(const TripletArgs&, bool, int, bool, int, hipStream_t) {}
 void launch_reduce(const TripletArgs&, int, int, hipStream_t) {}
 void launch_expand(const Sys*, int, int, hipStream_t) {}
