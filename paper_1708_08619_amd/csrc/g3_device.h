@@ -112,6 +112,7 @@ struct Sys {
 struct Job {
     int32_t sys;
     int32_t frame;
+    int32_t wg0;             // per-wave build: this job's first workgroup in its launch
 };
 
 // A run of work items of the persistent triplet kernel: one system, one
@@ -175,8 +176,7 @@ inline int build_wgs_per_job(int n_jobs, int max_cells)
 
 // Per-wave build: 4-wave workgroups (one wave per SIMD, so that as many fit
 // as LDS and registers allow), at most seven per CU (the kernel's VGPR
-// budget gives seven waves per SIMD).  Workgroups per job: about four rounds of the
-// workgroups resident at once on 256 CUs, at most one cell per wave.
+// budget gives seven waves per SIMD).
 constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int kWaveBuildWavesPerWG = 4;
 constexpr int kWaveBuildMaxWgsPerCU = 7;
@@ -186,13 +186,6 @@ inline int wave_wgs_per_cu(size_t lds_bytes)
     const size_t blocks = (lds_bytes + 511) / 512;
     const int n = (int)(kLdsPerCU / (blocks > 0 ? blocks * 512 : 512));
     return n < 1 ? 1 : (n > kWaveBuildMaxWgsPerCU ? kWaveBuildMaxWgsPerCU : n);
-}
-inline int wave_wgs_per_job(int n_jobs, int max_cells, int wgs_per_cu)
-{
-    const int cells_wg = (max_cells + kWaveBuildWavesPerWG - 1) / kWaveBuildWavesPerWG;
-    int per_job = 4 * 256 * wgs_per_cu / (n_jobs > 0 ? n_jobs : 1);
-    if (per_job > cells_wg) per_job = cells_wg;
-    return per_job < 1 ? 1 : per_job;
 }
 
 // Static scratch for callers that cannot allocate (g3_static.hip): its
@@ -220,11 +213,13 @@ void launch_nbr_build(const Sys* sys, const Job* jobs, int n_jobs, int max_cells
 enum Lookup : int { kLookupSteps = 0, kLookupOneStep = 1, kLookupStepTable = 2 };
 // Per-wave build (narrow entries): a wave stages one cell's stencil, at most
 // stage_cap atoms, as packed int16 coordinates and builds its centres' lists.
+// A 1-D grid of n_wgs workgroups: job j owns workgroups [jobs[j].wg0,
+// jobs[j+1].wg0) (the last up to n_wgs).
 constexpr int kWaveBuildWaves = kWaveBuildWavesPerWG;
 // `pairs`: some system of the launch counts the pair histogram (each wave
 // then holds pair counters in LDS).
 size_t nbr_wave_lds_bytes(int stage_cap, bool pairs);
-void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int lookup,
+void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int n_wgs, int lookup,
                      int stage_cap, bool pairs, unsigned long long* cnt, hipStream_t s);
 void launch_triplet(const TripletArgs& a, bool wide, int lookup, bool padded, int n_wg, hipStream_t s);
 void launch_reduce(const TripletArgs& a, int max_hb, int n_segs, hipStream_t s);

@@ -460,6 +460,92 @@ g3_status prepare(const g3_system& s, int hb_max, Prepared& P)
     return G3_OK;
 }
 
+// Atoms expected in a cell's stencil (the home cell and the neighbour cells
+// kept), and whether the per-wave build takes the system: its stencil fits
+// int16 and, with room for fluctuations, the largest stage.
+double expected_stencil(const Prepared& P)
+{
+    return (double)P.g.N / (double)P.g.ncell * (P.tri_once ? 14.0 : 27.0);
+}
+
+bool wave_build_fits(const Prepared& P)
+{
+    return P.g.pk_ok && 1.2 * expected_stencil(P) + 64.0 <= (double)kWaveStageMax;
+}
+
+// Neighbour build of a group: the per-wave build when some system qualifies
+// (then the general build over the cells it left), else the general build.
+// The wave's stage capacity covers the largest expected stencil with room
+// for fluctuations (a larger cell goes to the general build).  A system whose
+// expected stencil does not fit the largest stage (dense cells, or the
+// per-centre enumeration's full stencil) leaves all its cells to the general
+// build, which then runs on the full grid.
+struct BuildPlan {
+    bool wave = false;   // some system takes the per-wave build
+    bool rest = false;   // some system leaves all its cells to the general build
+    bool pairs = false;  // some system of the per-wave build counts pairs
+    int cap = 0;
+    int wave_grid = 0;   // workgroups of a per-wave build launch (plan_wave_grid)
+};
+
+BuildPlan plan_build(const std::vector<Prepared>& ps)
+{
+    BuildPlan b;
+    double t_max = 0;
+    for (const auto& P : ps) {
+        if (!wave_build_fits(P)) {
+            b.rest = true;
+            continue;
+        }
+        b.wave = true;
+        b.pairs = b.pairs || P.in.pair_hist != nullptr;
+        t_max = std::max(t_max, expected_stencil(P));
+    }
+    if (b.wave) {
+        const int want = (int)std::ceil(1.2 * t_max + 64.0);
+        b.cap = std::min(kWaveStageMax, std::max(256, (want + 15) & ~15));
+    }
+    return b;
+}
+
+// Per-wave build grid.  Each job gets workgroups in proportion to its cells:
+// in all about four rounds of the resident workgroups, with at least
+// kWaveMinCells cells per wave unless that leaves less than one round (a
+// wave's set-up and pool chunks cost about as much as a few cells; more
+// waves only pay where the GPU would not be full), and at most one cell per
+// wave.  `cells`: the cells of all jobs of one launch.
+constexpr double kWaveMinCells = 4.0;
+
+double wave_cells_per_wave(int64_t cells, const BuildPlan& bp)
+{
+    const double one_round =
+        256.0 * wave_wgs_per_cu(nbr_wave_lds_bytes(bp.cap, bp.pairs)) * kWaveBuildWaves;
+    const double waves = std::min(4.0 * one_round, std::max(one_round, (double)cells / kWaveMinCells));
+    return std::max((double)cells / waves, 1e-9);
+}
+
+int wave_wgs_of(int ncell, double per_wave)
+{
+    const int most = (ncell + kWaveBuildWaves - 1) / kWaveBuildWaves;
+    const double w = std::ceil((double)ncell / (per_wave * kWaveBuildWaves));
+    return std::max(1, (int)std::min<double>(w, (double)most));
+}
+
+// Sets the first workgroup of each of the n jobs of one launch; returns the
+// launch's workgroups.
+int plan_wave_grid(Job* jobs, int n, const std::vector<Prepared>& ps, const BuildPlan& bp)
+{
+    int64_t cells = 0;
+    for (int j = 0; j < n; ++j) cells += ps[jobs[j].sys].g.ncell;
+    const double per_wave = wave_cells_per_wave(cells, bp);
+    int wg = 0;
+    for (int j = 0; j < n; ++j) {
+        jobs[j].wg0 = wg;
+        wg += wave_wgs_of(ps[jobs[j].sys].g.ncell, per_wave);
+    }
+    return wg;
+}
+
 // Lay out scratch for a list of prepared systems; returns total bytes.
 // Triangle-once buffers of all systems are laid out last, back to back, so one
 // fill clears them.
@@ -467,20 +553,28 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
                       bool tri_once)
 {
     size_t o = base;
-    // unused tails of the per-wave pool chunks of the neighbour build
+    // triangle-once needs every side inside the pair cutoff (nb3 == nbins);
+    // other systems use the per-centre enumeration
+    for (auto& P : ps) P.tri_once = tri_once && P.g.nb3 == P.g.nbins;
+    // unused tails of the per-wave pool chunks of the neighbour build: each
+    // wave of the per-wave build and of the general build may leave one
     int n_jobs = 0, max_cells = 1;
+    int64_t cells = 0;
     for (auto& P : ps) {
-        n_jobs += per_frame ? std::max(P.in.n_frames, 1) : 1;
+        const int f = per_frame ? std::max(P.in.n_frames, 1) : 1;
+        n_jobs += f;
         max_cells = std::max(max_cells, P.g.ncell);
+        cells += (int64_t)f * P.g.ncell;
     }
-    // (each wave of the per-wave build and of the general build may leave a
-    // chunk's tail unused)
-    const int64_t slack = ((int64_t)build_wgs_per_job(n_jobs, max_cells) * kBuildWavesPerWG +
-                           (int64_t)wave_wgs_per_job(n_jobs, max_cells, kWaveBuildMaxWgsPerCU) *
-                               kWaveBuildWaves) *
-                          (per_frame ? kBuildChunk : kPlainChunk);
+    const BuildPlan bp = plan_build(ps);
+    const uint32_t chunk = per_frame ? kBuildChunk : kPlainChunk;
     for (auto& P : ps) {
         const Geometry& g = P.g;
+        // (a per-frame launch has one job: its cells alone set the grid)
+        const double per_wave = wave_cells_per_wave(per_frame ? cells : g.ncell, bp);
+        const int64_t slack = ((int64_t)build_wgs_per_job(n_jobs, max_cells) * kBuildWavesPerWG +
+                               (int64_t)wave_wgs_of(g.ncell, per_wave) * kWaveBuildWaves) *
+                              chunk;
         const size_t F = per_frame ? (size_t)std::max(P.in.n_frames, 1) : 1;
         const size_t N = (size_t)g.N;
         const int S = (int)g.slab_lo.size() - 1;
@@ -515,10 +609,7 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         P.pool_cap = std::min<int64_t>(P.pool_cap, max_cap);
         o = align_up(o + F * (size_t)(P.pool_cap + kPoolPad) * (g.wide ? 16 : 8), 256);
     }
-    // triangle-once needs every side inside the pair cutoff (nb3 == nbins);
-    // other systems use the per-centre enumeration
     for (auto& P : ps) {
-        P.tri_once = tri_once && P.g.nb3 == P.g.nbins;
         P.off_tri = o;
         if (P.tri_once) o = align_up(o + g3_hist_len(P.g.nbins, G3_HALF) * sizeof(uint64_t), 256);
     }
@@ -568,19 +659,6 @@ bool pads_rejected(const Geometry& g)
     const uint64_t d = (uint64_t)(32769 - (int64_t)g.C);
     const uint64_t s = std::min<uint64_t>(3ull * d * d, 0x7fffffffull);
     return s >= (uint64_t)g.R3;
-}
-
-// Atoms expected in a cell's stencil (the home cell and the neighbour cells
-// kept), and whether the per-wave build takes the system: its stencil fits
-// int16 and, with room for fluctuations, the largest stage.
-double expected_stencil(const Prepared& P)
-{
-    return (double)P.g.N / (double)P.g.ncell * (P.tri_once ? 14.0 : 27.0);
-}
-
-bool wave_build_fits(const Prepared& P)
-{
-    return P.g.pk_ok && 1.2 * expected_stencil(P) + 64.0 <= (double)kWaveStageMax;
 }
 
 Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
@@ -642,45 +720,11 @@ Sys make_sys(const Prepared& P, char* arena, uint32_t* flags, int cb)
     return s;
 }
 
-// Neighbour build of a group: the per-wave build when some system qualifies
-// (then the general build over the cells it left), else the general build.
-// The wave's stage capacity covers the largest expected stencil with room
-// for fluctuations (a larger cell goes to the general build).  A system whose
-// expected stencil does not fit the largest stage (dense cells, or the
-// per-centre enumeration's full stencil) leaves all its cells to the general
-// build, which then runs on the full grid.
-struct BuildPlan {
-    bool wave = false;   // some system takes the per-wave build
-    bool rest = false;   // some system leaves all its cells to the general build
-    bool pairs = false;  // some system of the per-wave build counts pairs
-    int cap = 0;
-};
-
-BuildPlan plan_build(const std::vector<Prepared>& ps)
-{
-    BuildPlan b;
-    double t_max = 0;
-    for (const auto& P : ps) {
-        if (!wave_build_fits(P)) {
-            b.rest = true;
-            continue;
-        }
-        b.wave = true;
-        b.pairs = b.pairs || P.in.pair_hist != nullptr;
-        t_max = std::max(t_max, expected_stencil(P));
-    }
-    if (b.wave) {
-        const int want = (int)std::ceil(1.2 * t_max + 64.0);
-        b.cap = std::min(kWaveStageMax, std::max(256, (want + 15) & ~15));
-    }
-    return b;
-}
-
 void launch_build(const Sys* dsys, const Job* djobs, int nj, int max_cells, bool wide, bool one_step,
                   int lookup, const BuildPlan& bp, unsigned long long* cnt, hipStream_t sm)
 {
     if (bp.wave) {
-        launch_nbr_wave(dsys, djobs, nj, max_cells, lookup, bp.cap, bp.pairs, cnt, sm);
+        launch_nbr_wave(dsys, djobs, nj, bp.wave_grid, lookup, bp.cap, bp.pairs, cnt, sm);
         launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, bp.rest ? 2 : 1, cnt, sm);
     } else {
         launch_nbr_build(dsys, djobs, nj, max_cells, wide, one_step, 0, cnt, sm);
@@ -897,9 +941,12 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     const Prepared& P = ps[0];
     const int F = s.n_frames;
     Sys sys = make_sys(P, (char*)p->arena, flags, tn.cb);
-    const BuildPlan bp = plan_build(ps);
+    BuildPlan bp = plan_build(ps);
     std::vector<Job> jobs(F);
-    for (int f = 0; f < F; ++f) jobs[f] = {0, f};
+    for (int f = 0; f < F; ++f) {
+        jobs[f] = {0, f, 0};
+        bp.wave_grid = plan_wave_grid(&jobs[f], 1, ps, bp);   // one job per launch
+    }
     std::vector<Seg> segs;
     int items_per_frame = 0;
     for (int f = 0; f < F; ++f) {
@@ -1033,8 +1080,9 @@ g3_status run_plain_noalloc(g3_plan p, const g3_system& s, bool worst_case)
     p->recs.push_back({s, 0, worst_case, flags});
 
     const int F = s.n_frames, N = P.g.N;
-    const BuildPlan bp = plan_build(ps);
-    const Job job{0, 0};
+    BuildPlan bp = plan_build(ps);
+    Job job{0, 0, 0};
+    bp.wave_grid = plan_wave_grid(&job, 1, ps, bp);
     // geometry tables (in the arena) and the per-call tables
     if ((st = put_bytes(p, B + P.off_thr, P.g.thr.data(), P.g.thr.size() * 4))) return st;
     if ((st = put_bytes(p, B + P.off_tab, P.g.tab.data(), P.g.tab.size()))) return st;
@@ -1139,7 +1187,8 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             padded = padded && pads_rejected(P.g);
         }
         const int lookup = step_ok ? kLookupStepTable : one_step ? kLookupOneStep : kLookupSteps;
-        const BuildPlan bp = plan_build(ps);
+        BuildPlan bp = plan_build(ps);
+        bp.wave_grid = plan_wave_grid(jobs.data(), (int)jobs.size(), ps, bp);
         const int n_wg = p->n_cu * tn.wg_per_cu;
         const int max_slots = slot_count(n_wg, (int)segs.size(), tn.hb_max, tn.slot_limit);
         const size_t o_sys = 0, o_jobs = align_up(sizeof(Sys) * sys.size(), 256),
@@ -1170,6 +1219,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         put(&bp.wave, sizeof(bp.wave));
         put(&bp.rest, sizeof(bp.rest));
         put(&bp.pairs, sizeof(bp.pairs));
+        put(&bp.wave_grid, sizeof(bp.wave_grid));
         put(&bp.cap, sizeof(bp.cap));
         // tuning fields one by one (the struct's padding bytes are undefined)
         const int32_t tk[5] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0, tn.slot_limit};

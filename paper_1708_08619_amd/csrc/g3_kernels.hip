@@ -788,7 +788,7 @@ __device__ __forceinline__ uint32_t as_u32(short2p v) { return __builtin_bit_cas
 template <int LOOKUP>
 __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k_nbr_wave(const Sys* __restrict__ sys,
                                                                    const Job* __restrict__ jobs,
-                                                                   int cap, int with_g2,
+                                                                   int n_jobs, int cap, int with_g2,
                                                                    unsigned long long* cnt)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -806,7 +806,16 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k
     int32_t* st_oy = reinterpret_cast<int32_t*>(wb + WL.offy);
     int32_t* st_oz = reinterpret_cast<int32_t*>(wb + WL.offz);
 
-    const Job jb = jobs[blockIdx.y];
+    // this workgroup's job: the last whose first workgroup is not after it
+    int jl = 0, jh = n_jobs - 1;
+    while (jl < jh) {
+        const int mid = (jl + jh + 1) >> 1;
+        if (jobs[mid].wg0 <= (int)blockIdx.x) jl = mid;
+        else jh = mid - 1;
+    }
+    const Job jb = jobs[jl];
+    const int wg_local = (int)blockIdx.x - jb.wg0;
+    const int wg_count = (jl + 1 < n_jobs ? jobs[jl + 1].wg0 : (int)gridDim.x) - jb.wg0;
     const Sys& S = sys[jb.sys];
     const int f = jb.frame, N = S.N;
     if (gp(S.flags)[f] & kFlagDomain) return;   // uniform over the workgroup
@@ -888,8 +897,7 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k
     uint32_t chunk_base = 0, chunk_left = 0;   // this wave's slice of the frame's pool
     uint64_t n_tested = 0, n_found = 0;        // this wave's candidates and neighbours
 
-    for (int cell = blockIdx.x * kWaveBuildWaves + wave; cell < ncell;
-         cell += gridDim.x * kWaveBuildWaves) {
+    for (int cell = wg_local * kWaveBuildWaves + wave; cell < ncell; cell += wg_count * kWaveBuildWaves) {
         const int c0 = __builtin_amdgcn_readfirstlane(cs[cell]);
         const int c1 = __builtin_amdgcn_readfirstlane(cs[cell + 1]);
         if (c0 == c1) continue;
@@ -1977,21 +1985,19 @@ size_t nbr_wave_lds_bytes(int stage_cap, bool pairs)
     return kWaveShared + (size_t)kWaveBuildWaves * wave_lds(stage_cap, pairs).size;
 }
 
-void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int max_cells, int lookup,
+void launch_nbr_wave(const Sys* sys, const Job* jobs, int n_jobs, int n_wgs, int lookup,
                      int stage_cap, bool pairs, unsigned long long* cnt, hipStream_t s)
 {
-    // about four rounds of resident workgroups over the whole batch; a wave
-    // takes cells blockIdx.x * 4 + wave + k * gridDim.x * 4
+    // wave w of a job's workgroup l (of its n) takes cells 4 l + w + 4 n k
     const size_t lds = nbr_wave_lds_bytes(stage_cap, pairs);
     const int g2 = pairs ? 1 : 0;
-    const int per_job = wave_wgs_per_job(n_jobs, max_cells, wave_wgs_per_cu(lds));
-    const dim3 g(per_job, n_jobs), b(kWaveBuildWaves * 64);
+    const dim3 g(n_wgs), b(kWaveBuildWaves * 64);
     if (lookup == kLookupStepTable)
-        hipLaunchKernelGGL((k_nbr_wave<kLookupStepTable>), g, b, lds, s, sys, jobs, stage_cap, g2, cnt);
+        hipLaunchKernelGGL((k_nbr_wave<kLookupStepTable>), g, b, lds, s, sys, jobs, n_jobs, stage_cap, g2, cnt);
     else if (lookup == kLookupOneStep)
-        hipLaunchKernelGGL((k_nbr_wave<kLookupOneStep>), g, b, lds, s, sys, jobs, stage_cap, g2, cnt);
+        hipLaunchKernelGGL((k_nbr_wave<kLookupOneStep>), g, b, lds, s, sys, jobs, n_jobs, stage_cap, g2, cnt);
     else
-        hipLaunchKernelGGL((k_nbr_wave<kLookupSteps>), g, b, lds, s, sys, jobs, stage_cap, g2, cnt);
+        hipLaunchKernelGGL((k_nbr_wave<kLookupSteps>), g, b, lds, s, sys, jobs, n_jobs, stage_cap, g2, cnt);
 }
 
 hipError_t set_kernel_lds_limits(size_t triplet_bytes, size_t build_bytes, size_t wave_build_bytes)
