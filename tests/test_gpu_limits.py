@@ -2,7 +2,9 @@
 take (at most 63 slabs of whole rows per system, the bound the header states
 for the default tuning and for 2048 centres per item) bit for bit against the
 oracle, one more bin rejected with G3_EINVAL before anything is queued; the
-largest and the smallest cutoff (rmax = 46340 and 1 unit); one bin."""
+largest and the smallest cutoff (rmax = 46340 and 1 unit); one bin; the
+largest number of atoms (2^22, a perfect crystal with a closed-form
+histogram)."""
 from __future__ import annotations
 
 import numpy as np
@@ -116,3 +118,38 @@ def test_smallest_cutoff_and_one_bin(g3mod, plan, torch_dev, oracle_mod):
         assert want.sum() > 0
         want = _check(g3mod, plan, torch_dev, oracle_mod, fr, box, 300.0, 1, 1, layout)
         assert want.sum() > 0
+
+
+def test_perfect_fcc_at_the_atom_limit(g3mod, plan, torch_dev):
+    """N = 2^22 atoms, the largest N, as a 128 x 128 x 64 FCC crystal at the
+    large-system density and cutoff: every site sees the same neighbour
+    vectors, so the expected histogram is N times the lattice-vector count.
+    Cell, list and pool offsets reach their largest sizes here."""
+    import oracle
+    import refs
+    a = 6708                                   # ~1.638 sigma at 4096/sigma: rho ~ 0.91
+    n = (128, 128, 64)
+    box = [a * k for k in n]
+    h = a // 2
+    basis = np.array([[0, 0, 0], [0, h, h], [h, 0, h], [h, h, 0]], dtype=np.int32)
+    g = np.stack(np.meshgrid(*[np.arange(k, dtype=np.int32) * a for k in n], indexing="ij"),
+                 -1).reshape(-1, 3)
+    sites = (g[:, None, :] + basis[None]).reshape(-1, 3)
+    N = len(sites)
+    assert N == 1 << 22
+    fr = np.ascontiguousarray(sites.T[None])
+    del g, sites
+    rmax, nb = 3.0 * 4096, 60
+    want_full = refs.lattice_full(refs.fcc_vectors(a, rmax), N, rmax, nb)
+    want_half, bad = oracle.fold_half(want_full)
+    assert bad == 0
+    d = _dev(fr, torch_dev)
+    for layout, want in ((0, want_half), (1, want_full.reshape(-1))):
+        h1 = g3mod.new_hist(nb, layout, torch_dev)
+        plan.accumulate(d, box, rmax, nb, layout, h1)
+        plan.sync()
+        assert np.array_equal(_np(h1), want), f"plain layout {layout}"
+        h2 = g3mod.new_hist(nb, layout, torch_dev)
+        plan.accumulate_batch([dict(frames=d, box=box, rmax=rmax, nbins=nb, layout=layout, hist=h2)])
+        plan.sync()
+        assert np.array_equal(_np(h2), want), f"batched layout {layout}"
