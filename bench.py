@@ -29,16 +29,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic int32 operations of the method (see the design notes):
-#   per candidate pair (centre, unordered {j,k} within rmax of the centre):
-#     d_jk = d_ik - d_ij (3 sub), |d_jk|^2 (3 mul + 2 add), compare with R2 (1)
-#   per histogram increment: exact bin of |d_jk|^2 (table + compare: 2),
-#     histogram address (1), increment (1)
-# In the default enumeration a candidate pair is one of the centre's
-# neighbours ranked above it, and one increment stands for one triangle
-# (three triplets binned, added by the expansion).
-OPS_PER_CANDIDATE = 9
-OPS_PER_BINNED = 4
+# Algorithmic int32 operations of the method (see the design notes), per
+# candidate pair (centre, unordered {j,k} within rmax of the centre):
+#   d_jk = d_ik - d_ij (3 sub), |d_jk|^2 (3 mul + 2 add), compare with R2 (1),
+#   exact bin of |d_jk|^2 (table + step: 2), histogram address (1) and the
+#   accept decision for the increment (1): 13, within the 12-15 a candidate
+#   costs when every candidate is binned and accepted ones are kept.  The
+#   histogram increments themselves are LDS operations, priced by the LDS
+#   ceiling.  In the default enumeration a candidate pair is one of the
+#   centre's neighbours ranked above it, and one increment stands for one
+#   triangle (three triplets binned, added by the expansion).
+OPS_PER_CANDIDATE = 13
+OPS_PER_BINNED = 0
 # Neighbour build: per (centre, stencil atom) pair tested, the same 9 (3 sub,
 # 3 mul, 2 add, 1 compare); per neighbour written: its bin (table + compare:
 # 2), its r12 slab (1) and its list position (1)
