@@ -509,17 +509,17 @@ BuildPlan plan_build(const std::vector<Prepared>& ps)
 }
 
 // Per-wave build grid.  Each job gets workgroups in proportion to its cells:
-// in all about four rounds of the resident workgroups, with at least
+// in all about four rounds of the workgroups resident on the n_cu CUs, with at least
 // kWaveMinCells cells per wave unless that leaves less than one round (a
 // wave's set-up and pool chunks cost about as much as a few cells; more
 // waves only pay where the GPU would not be full), and at most one cell per
 // wave.  `cells`: the cells of all jobs of one launch.
 constexpr double kWaveMinCells = 4.0;
 
-double wave_cells_per_wave(int64_t cells, const BuildPlan& bp)
+double wave_cells_per_wave(int64_t cells, const BuildPlan& bp, int n_cu)
 {
     const double one_round =
-        256.0 * wave_wgs_per_cu(nbr_wave_lds_bytes(bp.cap, bp.pairs)) * kWaveBuildWaves;
+        (double)n_cu * wave_wgs_per_cu(nbr_wave_lds_bytes(bp.cap, bp.pairs)) * kWaveBuildWaves;
     const double waves = std::min(4.0 * one_round, std::max(one_round, (double)cells / kWaveMinCells));
     return std::max((double)cells / waves, 1e-9);
 }
@@ -533,11 +533,11 @@ int wave_wgs_of(int ncell, double per_wave)
 
 // Sets the first workgroup of each of the n jobs of one launch; returns the
 // launch's workgroups.
-int plan_wave_grid(Job* jobs, int n, const std::vector<Prepared>& ps, const BuildPlan& bp)
+int plan_wave_grid(Job* jobs, int n, const std::vector<Prepared>& ps, const BuildPlan& bp, int n_cu)
 {
     int64_t cells = 0;
     for (int j = 0; j < n; ++j) cells += ps[jobs[j].sys].g.ncell;
-    const double per_wave = wave_cells_per_wave(cells, bp);
+    const double per_wave = wave_cells_per_wave(cells, bp, n_cu);
     int wg = 0;
     for (int j = 0; j < n; ++j) {
         jobs[j].wg0 = wg;
@@ -550,7 +550,7 @@ int plan_wave_grid(Job* jobs, int n, const std::vector<Prepared>& ps, const Buil
 // Triangle-once buffers of all systems are laid out last, back to back, so one
 // fill clears them.
 size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case, size_t base,
-                      bool tri_once)
+                      bool tri_once, int n_cu)
 {
     size_t o = base;
     // triangle-once needs every side inside the pair cutoff (nb3 == nbins);
@@ -571,7 +571,7 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
     for (auto& P : ps) {
         const Geometry& g = P.g;
         // (a per-frame launch has one job: its cells alone set the grid)
-        const double per_wave = wave_cells_per_wave(per_frame ? cells : g.ncell, bp);
+        const double per_wave = wave_cells_per_wave(per_frame ? cells : g.ncell, bp, n_cu);
         const int64_t slack = ((int64_t)build_wgs_per_job(n_jobs, max_cells) * kBuildWavesPerWG +
                                (int64_t)wave_wgs_of(g.ncell, per_wave) * kWaveBuildWaves) *
                               chunk;
@@ -928,7 +928,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     st = prepare(s, tn.hb_max, ps[0]);
     if (st) return st;
     const size_t tables_base = 0;
-    const size_t need = layout_scratch(ps, false, worst_case, 0, tn.tri_once);
+    const size_t need = layout_scratch(ps, false, worst_case, 0, tn.tri_once, p->n_cu);
     G3_TRY_HIP(grow(&p->arena, &p->arena_n, need));
     st = set_lds_limits(p);
     if (st) return st;
@@ -945,7 +945,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     std::vector<Job> jobs(F);
     for (int f = 0; f < F; ++f) {
         jobs[f] = {0, f, 0};
-        bp.wave_grid = plan_wave_grid(&jobs[f], 1, ps, bp);   // one job per launch
+        bp.wave_grid = plan_wave_grid(&jobs[f], 1, ps, bp, p->n_cu);   // one job per launch
     }
     std::vector<Seg> segs;
     int items_per_frame = 0;
@@ -1063,7 +1063,7 @@ g3_status run_plain_noalloc(g3_plan p, const g3_system& s, bool worst_case)
     const int slots_fit = (int)std::max<size_t>(1, (kStaticScratchBytes / 8) / ((size_t)tn.hb_max * 4));
     const int max_slots = std::min(slot_count(n_wg, S, tn.hb_max, tn.slot_limit), slots_fit);
     const size_t o_arena = align_up(o_slotseg + sizeof(int32_t) * max_slots, 256);
-    const size_t arena_end = layout_scratch(ps, false, worst_case, o_arena, tn.tri_once);
+    const size_t arena_end = layout_scratch(ps, false, worst_case, o_arena, tn.tri_once, p->n_cu);
     const size_t o_slots = align_up(arena_end, 256);
     const size_t end = o_slots + (size_t)max_slots * tn.hb_max * 4;
     if (end > kStaticScratchBytes) return G3_ENOMEM;
@@ -1082,7 +1082,7 @@ g3_status run_plain_noalloc(g3_plan p, const g3_system& s, bool worst_case)
     const int F = s.n_frames, N = P.g.N;
     BuildPlan bp = plan_build(ps);
     Job job{0, 0, 0};
-    bp.wave_grid = plan_wave_grid(&job, 1, ps, bp);
+    bp.wave_grid = plan_wave_grid(&job, 1, ps, bp, p->n_cu);
     // geometry tables (in the arena) and the per-call tables
     if ((st = put_bytes(p, B + P.off_thr, P.g.thr.data(), P.g.thr.size() * 4))) return st;
     if ((st = put_bytes(p, B + P.off_tab, P.g.tab.data(), P.g.tab.size()))) return st;
@@ -1154,7 +1154,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             ps.push_back(std::move(P));
         }
         if (ps.empty()) continue;
-        const size_t need = layout_scratch(ps, true, false, 0, tn.tri_once);
+        const size_t need = layout_scratch(ps, true, false, 0, tn.tri_once, p->n_cu);
         // flags for every frame of the group
         int total_f = 0;
         for (auto& P : ps) total_f += P.in.n_frames;
@@ -1188,7 +1188,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         }
         const int lookup = step_ok ? kLookupStepTable : one_step ? kLookupOneStep : kLookupSteps;
         BuildPlan bp = plan_build(ps);
-        bp.wave_grid = plan_wave_grid(jobs.data(), (int)jobs.size(), ps, bp);
+        bp.wave_grid = plan_wave_grid(jobs.data(), (int)jobs.size(), ps, bp, p->n_cu);
         const int n_wg = p->n_cu * tn.wg_per_cu;
         const int max_slots = slot_count(n_wg, (int)segs.size(), tn.hb_max, tn.slot_limit);
         const size_t o_sys = 0, o_jobs = align_up(sizeof(Sys) * sys.size(), 256),
