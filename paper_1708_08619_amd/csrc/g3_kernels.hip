@@ -1136,7 +1136,8 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k
 // (b_j, b_k) for the row j it was evaluated from; the reduce folds (a, b) and
 // (b, a) into the half-layout bin (min, max, c).
 //
-// Per centre the neighbour list is sorted by pair bin.  The pairs whose
+// Per centre the neighbour list is partitioned by the r12 slab of its pair
+// bins, slabs in increasing order (any order inside a slab).  The pairs whose
 // smaller bin lies in the slab are those with at least one member among the
 // slab rows, entries [J_q, J_q+1) (local 0..r-1 counted from J_q; m entries
 // from J_q to the end of the list).  Row j takes k = j+1 .. m-1: the slab
