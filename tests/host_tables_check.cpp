@@ -9,6 +9,7 @@
 // int16 staging: wherever the host sets pk_ok, every coordinate of a cell's
 // 3 x 3 x 3 stencil (periodic shift applied) minus the kernel's midpoint
 // reference fits int16, and the sentinel atoms are rejected by every centre.
+// Then the per-wave build's grid over the jobs of a launch.
 // Exit status: the number of geometries with a failure.
 #include "../paper_1708_08619_amd/csrc/g3_host.cpp"
 
@@ -158,5 +159,48 @@ int main()
         if (bad) ++failed;
     }
     if (staged_ok < 6) ++failed;     // the benchmark-like axes must qualify
+
+    // Per-wave build grid: each job's workgroups start where the previous
+    // job's end (the kernel finds its job by binary search over them), every
+    // job has at least one and at most one per 4 cells, and a launch has about
+    // four rounds of resident workgroups at most (one round at least unless
+    // that would put fewer than one cell in a wave).
+    struct GridCase { std::vector<int> cells; int frames; } grids[] = {
+        {{2744}, 50}, {{2744}, 1}, {{1331, 216, 729, 27, 64, 1000, 343, 512}, 8},
+        {{1}, 1}, {{3}, 3}, {{161874}, 1}, {{8, 8000000}, 2}};
+    for (const GridCase& gc : grids) {
+        std::vector<Prepared> ps(gc.cells.size());
+        for (size_t k = 0; k < ps.size(); ++k) ps[k].g.ncell = gc.cells[k];
+        std::vector<Job> jobs;
+        for (size_t k = 0; k < ps.size(); ++k)
+            for (int f = 0; f < gc.frames; ++f) jobs.push_back({(int)k, f, -1});
+        BuildPlan bp;
+        bp.wave = true;
+        bp.cap = 480;
+        const int n_cu = 256;
+        const int total = plan_wave_grid(jobs.data(), (int)jobs.size(), ps, bp, n_cu);
+        const int64_t resident = (int64_t)n_cu * wave_wgs_per_cu(nbr_wave_lds_bytes(bp.cap, bp.pairs));
+        int64_t cells = 0;
+        bool bad = jobs.empty() || jobs[0].wg0 != 0;
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            const int nc = ps[jobs[j].sys].g.ncell;
+            cells += nc;
+            const int end = j + 1 < jobs.size() ? jobs[j + 1].wg0 : total;
+            const int w = end - jobs[j].wg0;
+            if (w < 1 || w > (nc + kWaveBuildWaves - 1) / kWaveBuildWaves) bad = true;
+        }
+        // at most about four rounds (each job's count is rounded up)
+        if ((int64_t)total > 4 * resident + (int64_t)jobs.size()) bad = true;
+        // at least one round, or one cell per wave everywhere
+        const int64_t one_cell = [&] {
+            int64_t t = 0;
+            for (const Job& jb : jobs) t += (ps[jb.sys].g.ncell + kWaveBuildWaves - 1) / kWaveBuildWaves;
+            return t;
+        }();
+        if ((int64_t)total < std::min<int64_t>(resident, one_cell)) bad = true;
+        std::printf("wave grid: %zu jobs, %lld cells -> %d workgroups (resident %lld) %s\n", jobs.size(),
+                    (long long)cells, total, (long long)resident, bad ? "FAIL" : "ok");
+        if (bad) ++failed;
+    }
     return failed;
 }
