@@ -1060,9 +1060,11 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k
                     const bool mine = q == (uint32_t)qq;
                     const uint64_t mk = __ballot(mine);
                     if (lane == qq) jlane = J;
-                    if (mine) epos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mk, J));
-                    J += (uint32_t)__popcll(mk);
+                    if (mk) {   // (the innermost slabs are often empty)
+                        if (mine) epos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mk, J));
+                        J += (uint32_t)__popcll(mk);
+                    }
                 }
                 if (lane == n_slabs) jlane = J;   // = n
                 if (lane <= n_slabs) slab_j[(size_t)ci * (n_slabs + 1) + lane] = (uint16_t)jlane;
