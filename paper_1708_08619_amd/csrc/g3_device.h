@@ -127,6 +127,8 @@ struct Seg {
     int32_t lo0, lo1;        // slab rows
     int32_t hb;              // LDS bins of the slab: (lo1 - lo0) * rl
     int32_t rl;              // bins per slab row: (nbins - lo0) * nbins
+    int32_t step;            // items per run handed to a workgroup
+    int32_t fetch_begin;     // first run index: runs are numbered in segment order
 };
 
 struct Ctl {
@@ -140,6 +142,7 @@ struct TripletArgs {
     const Seg* segs;
     int32_t n_segs;
     int32_t total_items;
+    int32_t n_fetch;         // runs of items (the work counter's range)
     Ctl* ctl;
     uint32_t* slots;         // [max_slots][hb_max]
     int32_t* slot_seg;       // [max_slots]

@@ -763,9 +763,37 @@ void add_segments(const Prepared& P, int sys_index, int frame0, int n_frames, in
         s.lo1 = g.slab_lo[q + 1];
         s.hb = (int)slab_bins(s.lo0, s.lo1, g.nbins, g.nb3);
         s.rl = (g.nbins - s.lo0) * g.nb3;
+        s.step = 1;
+        s.fetch_begin = items;
         segs.push_back(s);
         items += n_blocks * n_frames;
     }
+}
+
+// Runs of items for the triplet kernel's work counter.  A workgroup flushes
+// its slab whenever its next item lies in another segment; with one item
+// per fetch, a segment with fewer items than workgroups has every item taken
+// by a different workgroup, one flush (the whole slab written to a partial
+// slot) per item, which dominates batches of many small systems.  Such a
+// segment is cut into runs of up to g consecutive items, g growing with the
+// launch's items (up to kRunMax) so that small launches keep their
+// parallelism; a segment with at least one item per workgroup keeps single
+// items (its workgroups take consecutive items of it anyway).  Sets each
+// segment's step and first run; returns the number of runs.
+constexpr int kRunMax = 16;
+
+int plan_runs(std::vector<Seg>& segs, int total_items, int n_wg)
+{
+    const int g = std::max(1, std::min(kRunMax, total_items / std::max(1, 8 * n_wg)));
+    int f = 0;
+    for (size_t q = 0; q < segs.size(); ++q) {
+        const int end = q + 1 < segs.size() ? segs[q + 1].item_begin : total_items;
+        const int k = end - segs[q].item_begin;
+        segs[q].step = k >= n_wg ? 1 : std::max(1, std::min(g, k));
+        segs[q].fetch_begin = f;
+        f += (k + segs[q].step - 1) / segs[q].step;
+    }
+    return f;
 }
 
 g3_status ensure_common(g3_plan p)
@@ -987,6 +1015,7 @@ g3_status run_plain(g3_plan p, const g3_system& s, bool worst_case)
     a.cand = p->cand;
     a.n_segs = S;
     a.total_items = items_per_frame;
+    a.n_fetch = items_per_frame;       // one item per run
     const int N = P.g.N;
     const auto tri = tri_range(ps);
     launch_zero_u32((uint32_t*)((char*)p->arena + P.off_cursor), (size_t)F * kCursorStride, p->stream);
@@ -1097,6 +1126,7 @@ g3_status run_plain_noalloc(g3_plan p, const g3_system& s, bool worst_case)
     a.segs = (const Seg*)(B + o_segs);
     a.n_segs = S;
     a.total_items = items;
+    a.n_fetch = items;                 // one item per run
     a.ctl = (Ctl*)(B + kNaCtl);
     a.slots = (uint32_t*)(B + o_slots);
     a.slot_seg = (int32_t*)(B + o_slotseg);
@@ -1190,6 +1220,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         BuildPlan bp = plan_build(ps);
         bp.wave_grid = plan_wave_grid(jobs.data(), (int)jobs.size(), ps, bp, p->n_cu);
         const int n_wg = p->n_cu * tn.wg_per_cu;
+        const int n_fetch = plan_runs(segs, items, n_wg);
         const int max_slots = slot_count(n_wg, (int)segs.size(), tn.hb_max, tn.slot_limit);
         const size_t o_sys = 0, o_jobs = align_up(sizeof(Sys) * sys.size(), 256),
                      o_segs = align_up(o_jobs + sizeof(Job) * jobs.size(), 256),
@@ -1225,7 +1256,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         const int32_t tk[5] = {tn.hb_max, tn.cb, tn.wg_per_cu, tn.tri_once ? 1 : 0, tn.slot_limit};
         put(tk, sizeof(tk));
         int nj = (int)jobs.size(), ns = (int)segs.size();
-        put(&nj, 4); put(&ns, 4); put(&items, 4); put(&max_n, 4); put(&max_hb, 4); put(&max_cells, 4);
+        put(&nj, 4); put(&ns, 4); put(&items, 4); put(&n_fetch, 4); put(&max_n, 4); put(&max_hb, 4); put(&max_cells, 4);
         put(&p->arena, sizeof(void*)); put(&p->tables, sizeof(void*)); put(&p->slots, sizeof(void*));
         put(&p->flag_log, sizeof(void*));
         size_t arena_used = need;
@@ -1239,6 +1270,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
         a.segs = (const Seg*)(T + o_segs);
         a.n_segs = ns;
         a.total_items = items;
+        a.n_fetch = n_fetch;
         a.ctl = (Ctl*)p->ctl;
         a.slots = (uint32_t*)p->slots;
         a.slot_seg = (int32_t*)(T + o_slotseg);

@@ -1380,18 +1380,32 @@ __global__ void __launch_bounds__(kTripletThreads) k_triplet(TripletArgs A)
         for (int x = tid; x < hb; x += kTripletThreads) st32(kTlHist + 4u * x, 0u);
     };
 
+    // The counter hands out runs of consecutive items of one segment (a
+    // segment's run length is `step`), so a workgroup keeps its slab over a
+    // run.  Runs come in increasing order, so each workgroup finds the
+    // segment of its next run by scanning forward from the last one.
+    int seg = 0, item = 0, run_left = 0;
     for (;;) {
         if (tid == 0) {
-            st32(kTlItem, __hip_atomic_fetch_add(gp(&A.ctl->next_item), 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT));
+            if (run_left == 0)
+                st32(kTlItem, __hip_atomic_fetch_add(gp(&A.ctl->next_item), 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
             st32(kTlAny, 0u);
         }
         __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane((int)ld32(kTlItem));
+        if (run_left == 0) {
+            const int fi = __builtin_amdgcn_readfirstlane((int)ld32(kTlItem));
+            if (fi >= A.n_fetch) break;
+            while (seg + 1 < A.n_segs && A.segs[seg + 1].fetch_begin <= fi) ++seg;
+            const Seg& R = A.segs[seg];
+            const int end = seg + 1 < A.n_segs ? A.segs[seg + 1].item_begin : A.total_items;
+            item = R.item_begin + (fi - R.fetch_begin) * R.step;
+            run_left = min(R.step, end - item);
+        } else {
+            ++item;
+        }
+        --run_left;
         __syncthreads();
-        if (item >= A.total_items) break;
-        int seg = 0;
-        while (seg + 1 < A.n_segs && A.segs[seg + 1].item_begin <= item) ++seg;
         const Seg& G = A.segs[seg];
         const Sys& S = A.sys[G.sys];
         if (seg != cur_seg) {
