@@ -512,15 +512,19 @@ BuildPlan plan_build(const std::vector<Prepared>& ps)
 // in all about four rounds of the workgroups resident on the n_cu CUs, with at least
 // kWaveMinCells cells per wave unless that leaves less than one round (a
 // wave's set-up and pool chunks cost about as much as a few cells; more
-// waves only pay where the GPU would not be full), and at most one cell per
-// wave.  `cells`: the cells of all jobs of one launch.
+// waves only pay where the GPU would not be full), at most kWaveMaxCells
+// (a large batch of many jobs then takes more rounds, which keeps the last
+// workgroups short), and at most one cell per wave.  `cells`: the cells of
+// all jobs of one launch.
 constexpr double kWaveMinCells = 4.0;
+constexpr double kWaveMaxCells = 16.0;
 
 double wave_cells_per_wave(int64_t cells, const BuildPlan& bp, int n_cu)
 {
     const double one_round =
         (double)n_cu * wave_wgs_per_cu(nbr_wave_lds_bytes(bp.cap, bp.pairs)) * kWaveBuildWaves;
-    const double waves = std::min(4.0 * one_round, std::max(one_round, (double)cells / kWaveMinCells));
+    const double waves = std::min(std::max(4.0 * one_round, (double)cells / kWaveMaxCells),
+                                  std::max(one_round, (double)cells / kWaveMinCells));
     return std::max((double)cells / waves, 1e-9);
 }
 
