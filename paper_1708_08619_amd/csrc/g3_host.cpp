@@ -378,13 +378,16 @@ g3_status fail(g3_plan p, hipError_t e)
 hipError_t grow(void** ptr, size_t* have, size_t need)
 {
     if (need <= *have) return hipSuccess;
+    // at least half again the old size, so that a run of slightly larger
+    // calls does not reallocate (and synchronize in hipFree) every time
+    const size_t old = *have;
     if (*ptr) {
         hipError_t e = hipFree(*ptr);
         *ptr = nullptr;
         *have = 0;
         if (e) return e;
     }
-    size_t n = std::max(need, *have + *have / 2);
+    size_t n = std::max(need, old + old / 2);
     n = (n + 4095) & ~(size_t)4095;
     hipError_t e = hipMalloc(ptr, n);
     if (e) { *ptr = nullptr; return e; }

@@ -94,12 +94,17 @@ class GpuExecutor:
         torch.cuda.set_device(self.device)
         self.plan = g3.Plan()
         self._host = {}
+        self._pinned = {}                    # free pinned histogram buffers by length
 
     def upload(self, frames: np.ndarray):
+        # Straight from pageable host memory (the runtime stages the copy):
+        # pinning every request's frames cost more than the copy itself
+        # whenever the pinned-memory cache was cold, as in a burst of new
+        # requests.
         t = self.torch
-        host = t.from_numpy(np.ascontiguousarray(frames, dtype=np.int32)).pin_memory()
+        host = t.from_numpy(np.ascontiguousarray(frames, dtype=np.int32))
         dev = host.to(self.device, non_blocking=True)
-        self._host[id(dev)] = host           # keep the pinned source alive until released
+        self._host[id(dev)] = host           # the source stays alive until released
         return dev
 
     def new_hist(self, n: int):
@@ -117,12 +122,16 @@ class GpuExecutor:
 
     def start_fetch(self, hist):
         t = self.torch
-        host = t.empty(hist.shape, dtype=t.uint64, pin_memory=True)
+        free = self._pinned.get(int(hist.numel()))
+        host = free.pop() if free else t.empty(hist.shape, dtype=t.uint64, pin_memory=True)
         host.copy_(hist, non_blocking=True)
         return host
 
     def finish_fetch(self, token) -> np.ndarray:
-        return token.numpy().copy()
+        out = token.numpy().copy()
+        # the copy has landed (the caller waited for its event): reuse the buffer
+        self._pinned.setdefault(int(token.numel()), []).append(token)
+        return out
 
     def release(self, frames, hist):
         self._host.pop(id(frames), None)
