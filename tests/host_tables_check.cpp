@@ -9,7 +9,8 @@
 // int16 staging: wherever the host sets pk_ok, every coordinate of a cell's
 // 3 x 3 x 3 stencil (periodic shift applied) minus the kernel's midpoint
 // reference fits int16, and the sentinel atoms are rejected by every centre.
-// Then the per-wave build's grid over the jobs of a launch.
+// Then the per-wave build's grid over the jobs of a launch, and the triplet
+// kernel's runs of items.
 // Exit status: the number of geometries with a failure.
 #include "../paper_1708_08619_amd/csrc/g3_host.cpp"
 
@@ -211,6 +212,46 @@ int main()
         if ((int64_t)total < std::min<int64_t>(resident, one_cell)) bad = true;
         std::printf("wave grid: %zu jobs, %lld cells -> %d workgroups (resident %lld) %s\n", jobs.size(),
                     (long long)cells, total, (long long)resident, bad ? "FAIL" : "ok");
+        if (bad) ++failed;
+    }
+
+    // Runs of items for the triplet kernel: replaying the kernel's mapping
+    // (forward scan over segments by first run, item = start + run * step),
+    // every item of every segment is handed out exactly once, no run leaves
+    // its segment, runs are 1 to 16 items, and a segment with at least one
+    // item per workgroup keeps runs of one.
+    struct RunCase { std::vector<int> seg_items; int n_wg; } runs[] = {
+        {{24, 24, 24, 5, 1, 300, 3}, 256}, {{1600, 1600, 1600, 1600, 1600}, 256},
+        {std::vector<int>(400, 24), 256}, {std::vector<int>(1500, 40), 256}, {{7}, 256}, {{100, 2, 9}, 4}};
+    for (const RunCase& rc : runs) {
+        std::vector<Seg> segs;
+        int total = 0;
+        for (int k : rc.seg_items) {
+            Seg sg{};
+            sg.item_begin = total;
+            segs.push_back(sg);
+            total += k;
+        }
+        const int n_fetch = plan_runs(segs, total, rc.n_wg);
+        std::vector<int> seen(total, 0);
+        bool bad = false;
+        int q = 0, max_step = 0;
+        for (int f = 0; f < n_fetch; ++f) {
+            while (q + 1 < (int)segs.size() && segs[q + 1].fetch_begin <= f) ++q;
+            const int end = q + 1 < (int)segs.size() ? segs[q + 1].item_begin : total;
+            const int item = segs[q].item_begin + (f - segs[q].fetch_begin) * segs[q].step;
+            const int n = std::min(segs[q].step, end - item);
+            if (item < segs[q].item_begin || n < 1) { bad = true; break; }
+            for (int i = item; i < item + n; ++i) ++seen[i];
+        }
+        for (size_t k = 0; k < segs.size(); ++k) {
+            max_step = std::max(max_step, segs[k].step);
+            if (segs[k].step < 1 || segs[k].step > 16) bad = true;
+            if (rc.seg_items[k] >= rc.n_wg && segs[k].step != 1) bad = true;
+        }
+        for (int v : seen) if (v != 1) bad = true;
+        std::printf("runs: %zu segments, %d items -> %d runs (longest %d) %s\n", segs.size(), total, n_fetch,
+                    max_step, bad ? "FAIL" : "ok");
         if (bad) ++failed;
     }
     return failed;

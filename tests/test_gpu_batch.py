@@ -127,3 +127,24 @@ def test_tickets(g3mod, torch_dev, oracle_mod):
             plan.ticket_query(3)
         with pytest.raises(g3mod.G3Error):
             plan.ticket_query(0)
+
+
+def test_many_small_systems_in_runs(g3mod, torch_dev, oracle_mod):
+    """120 small systems (N 200..800, 3 frames, both layouts) at 64 centres
+    per item: about 10^4 items, so the work counter hands out runs of
+    several consecutive items of each small segment; every system equals the
+    oracle bin for bin."""
+    rng = np.random.default_rng(47)
+    ws = []
+    for k in range(120):
+        N = int(rng.integers(200, 801))
+        fr, box = synth.jittered_fcc(N, float(rng.uniform(0.7, 0.9)), 0.1, 3, [47, k])
+        ws.append(synth.Workload(f"small{k}", fr, box, 2.5 * 4096, 50, int(rng.integers(0, 2)), {}))
+    with g3mod.Plan() as plan:
+        plan.set_tuning(centres_per_item=64)
+        systems = _systems(g3mod, ws, torch_dev)
+        plan.accumulate_batch(systems)
+        plan.sync()
+        for w, s in zip(ws, systems):
+            got = s["hist"].cpu().numpy().astype(np.uint64)
+            assert np.array_equal(got, oracle_mod.hist(w.frames, w.box, w.rmax, w.nbins, w.layout)), w.name
