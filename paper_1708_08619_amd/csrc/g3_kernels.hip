@@ -744,7 +744,9 @@ __global__ void __launch_bounds__(kBuildThreads, 8) k_nbr_build(const Sys* __res
 //   partitioned by slab exactly as the general build does.
 // A cell whose stencil exceeds the wave's stage capacity, and every cell of a
 // system without pk_ok, is appended to the frame's overflow list; the
-// general build then runs on those cells only.
+// general build then runs on those cells only.  Workgroups of 4 waves on a
+// 1-D grid: each job (one frame of one system) owns the workgroups from its
+// wg0 to the next job's, in proportion to its cells.
 namespace {
 
 constexpr int kStagePad = 64;
@@ -842,9 +844,9 @@ __global__ void __launch_bounds__(kWaveBuildWaves * 64, kWaveBuildMaxWgsPerCU) k
     const bool tri_once = S.tri != nullptr;
     const uint32_t pair_inc = tri_once ? 2u : 1u;
 
-    // bin tables and the bin -> slab map, once per workgroup
-    // the bin tables (a few KB) are read through the vector cache, which
-    // keeps LDS for the stages: up to six 4-wave workgroups share a CU
+    // the bin -> slab map, once per workgroup; the bin tables (a few KB) are
+    // read through the vector cache, which keeps LDS for the stages (up to
+    // seven 4-wave workgroups share a CU)
     const gptr<const uint32_t> g_thr = gp(S.thr);
     const gptr<const uint8_t> g_tab = gp(S.tab);
     const gptr<const uint32_t> g_step = gp(S.step);
