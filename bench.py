@@ -370,9 +370,9 @@ def uneven_bench(torch, dev, steps: int):
 def saturated_bench(torch, dev, n_requests: int):
     """Served throughput with the server saturated (every request arrives at
     t = 0) against plain per-request launches (g3_accumulate per request, one
-    after another on one stream), on the same requests; both take each
-    request's frames from pinned host memory and return its histogram to host
-    memory."""
+    after another on one stream), on the same requests; both copy each
+    request's frames from its (pageable) host memory and return its histogram
+    to pinned host memory."""
     from paper_1708_08619_amd import g3, serve
     store = serve.TrajectoryStore(n_systems=16, max_frames=20, n_min=1024, n_max=65536)
     reqs0 = serve.poisson_requests(store, n_requests, 1e9)
@@ -397,11 +397,12 @@ def saturated_bench(torch, dev, n_requests: int):
         def plain_all():
             res = []
             for r in reqs0:
-                host = torch.from_numpy(np.ascontiguousarray(r.frames)).pin_memory()
-                fr = host.to(dev, non_blocking=True)
+                fr = torch.from_numpy(np.ascontiguousarray(r.frames)).to(dev, non_blocking=True)
                 h = g3.new_hist(r.nbins, r.layout, dev)
                 plan.accumulate(fr, r.box, r.rmax, r.nbins, r.layout, h)
-                res.append(h.to("cpu", non_blocking=True))
+                host = torch.empty(h.shape, dtype=h.dtype, pin_memory=True)
+                host.copy_(h, non_blocking=True)
+                res.append(host)
             plan.sync()
             torch.cuda.synchronize()
             return res

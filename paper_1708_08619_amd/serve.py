@@ -94,7 +94,8 @@ class GpuExecutor:
         torch.cuda.set_device(self.device)
         self.plan = g3.Plan()
         self._host = {}
-        self._pinned = {}                    # free pinned histogram buffers by length
+        self._pinned = {}                    # free pinned histogram buffers by length,
+                                             # kept for reuse while the executor lives
 
     def upload(self, frames: np.ndarray):
         # Straight from pageable host memory (the runtime stages the copy):
