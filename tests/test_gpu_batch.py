@@ -148,3 +148,42 @@ def test_many_small_systems_in_runs(g3mod, torch_dev, oracle_mod):
         for w, s in zip(ws, systems):
             got = s["hist"].cpu().numpy().astype(np.uint64)
             assert np.array_equal(got, oracle_mod.hist(w.frames, w.box, w.rmax, w.nbins, w.layout)), w.name
+
+
+def test_mixed_features_in_one_batch(g3mod, torch_dev, oracle_mod):
+    """72 small systems in one batch at 64 centres per item (runs of several
+    items): cutoffs 2.0-2.5 sigma, 30-50 bins, both layouts, every third
+    system with the pair histogram (the launch's build then keeps pair
+    counters), every fourth with a doubled third axis (the per-centre
+    enumeration beside triangle-once systems); every histogram and pair
+    histogram equals the oracle's."""
+    rng = np.random.default_rng(53)
+    cases, systems = [], []
+    for k in range(72):
+        N = int(rng.integers(200, 701))
+        rho = float(rng.uniform(0.7, 0.9))
+        fr, box = synth.jittered_fcc(N, rho, 0.1, 2, [53, k])
+        rmax = float(rng.uniform(2.0, 2.5)) * 4096
+        nb = int(rng.integers(30, 51))
+        layout = int(rng.integers(0, 2))
+        nc = 2 * nb if k % 4 == 3 else nb
+        if nc > nb:                 # the third cutoff (2 rmax) must stay below L/2
+            rmax = min(rmax, (min(box) / 2 - 2) / 2)
+        h = g3mod.new_hist(nb, layout, torch_dev, nbins_third=nc)
+        p = g3mod.new_pair_hist(nb, torch_dev) if k % 3 == 0 else None
+        s = dict(frames=_dev(fr, torch_dev), box=box, rmax=rmax, nbins=nb, layout=layout, hist=h,
+                 nbins_third=nc)
+        if p is not None:
+            s["pair_hist"] = p
+        systems.append(s)
+        cases.append((fr, box, rmax, nb, layout, nc))
+    with g3mod.Plan() as plan:
+        plan.set_tuning(centres_per_item=64)
+        plan.accumulate_batch(systems)
+        plan.sync()
+        for k, ((fr, box, rmax, nb, layout, nc), s) in enumerate(zip(cases, systems)):
+            got = s["hist"].cpu().numpy().astype(np.uint64)
+            assert np.array_equal(got, oracle_mod.hist(fr, box, rmax, nb, layout, nbins_third=nc)), k
+            if "pair_hist" in s:
+                gp = s["pair_hist"].cpu().numpy().astype(np.uint64)
+                assert np.array_equal(gp, oracle_mod.pair_hist(fr, box, rmax, nb)), k
