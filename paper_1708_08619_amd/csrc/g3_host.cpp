@@ -517,8 +517,10 @@ BuildPlan plan_build(const std::vector<Prepared>& ps)
 // wave's set-up and pool chunks cost about as much as a few cells; more
 // waves only pay where the GPU would not be full), at most kWaveMaxCells
 // (a large batch of many jobs then takes more rounds, which keeps the last
-// workgroups short), and at most one cell per wave.  `cells`: the cells of
-// all jobs of one launch.
+// workgroups short), and at most one cell per wave; above one round, a whole
+// number of rounds (no partial last round): the fewer rounds unless that
+// breaks the kWaveMaxCells bound.  `cells`: the cells of all jobs of one
+// launch.
 constexpr double kWaveMinCells = 4.0;
 constexpr double kWaveMaxCells = 16.0;
 
@@ -526,8 +528,12 @@ double wave_cells_per_wave(int64_t cells, const BuildPlan& bp, int n_cu)
 {
     const double one_round =
         (double)n_cu * wave_wgs_per_cu(nbr_wave_lds_bytes(bp.cap, bp.pairs)) * kWaveBuildWaves;
-    const double waves = std::min(std::max(4.0 * one_round, (double)cells / kWaveMaxCells),
-                                  std::max(one_round, (double)cells / kWaveMinCells));
+    double waves = std::min(std::max(4.0 * one_round, (double)cells / kWaveMaxCells),
+                            std::max(one_round, (double)cells / kWaveMinCells));
+    if (waves > one_round) {
+        const double lo = std::floor(waves / one_round) * one_round;
+        waves = (double)cells / lo <= kWaveMaxCells ? lo : lo + one_round;
+    }
     return std::max((double)cells / waves, 1e-9);
 }
 

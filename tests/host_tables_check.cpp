@@ -165,8 +165,8 @@ int main()
     // job's end (the kernel finds its job by binary search over them), every
     // job has at least one and at most one per 4 cells, and a launch has about
     // four rounds of resident workgroups at most, or more to keep at most 16
-    // cells in a wave (one round at least unless that would put fewer than
-    // one cell in a wave).
+    // cells in a wave, in whole rounds (one round at least unless that would
+    // put fewer than one cell in a wave).
     struct GridCase { std::vector<int> cells; int frames; } grids[] = {
         {{2744}, 50}, {{2744}, 1}, {{1331, 216, 729, 27, 64, 1000, 343, 512}, 8},
         {{1}, 1}, {{3}, 3}, {{161874}, 1}, {{8, 8000000}, 2}};
@@ -191,9 +191,9 @@ int main()
             const int w = end - jobs[j].wg0;
             if (w < 1 || w > (nc + kWaveBuildWaves - 1) / kWaveBuildWaves) bad = true;
         }
-        // at most about four rounds, or 16 cells per wave (each job's count
-        // is rounded up)
-        if ((int64_t)total > std::max<int64_t>(4 * resident, cells / (16 * kWaveBuildWaves) + 1) +
+        // at most about four rounds, or 16 cells per wave, in whole rounds
+        // (one more round at most; each job's count is rounded up)
+        if ((int64_t)total > std::max<int64_t>(4 * resident, cells / (16 * kWaveBuildWaves) + 1) + resident +
                                  (int64_t)jobs.size())
             bad = true;
         // no wave with more than 16 cells
