@@ -764,7 +764,9 @@ void add_segments(const Prepared& P, int sys_index, int frame0, int n_frames, in
     const int n_blocks = (g.N + cb - 1) / cb;
     const int S = (int)g.slab_lo.size() - 1;
     if (n_blocks == 0 || n_frames == 0) return;
-    for (int q = 0; q < S; ++q) {
+    // from the outermost slab inwards: its items carry the most candidate
+    // pairs, so the persistent kernel's last items (its tail) are light ones
+    for (int q = S - 1; q >= 0; --q) {
         Seg s;
         s.sys = sys_index;
         s.slab = q;
