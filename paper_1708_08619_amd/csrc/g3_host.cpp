@@ -785,6 +785,39 @@ void add_segments(const Prepared& P, int sys_index, int frame0, int n_frames, in
     }
 }
 
+// A batch's segments in order of the expected candidate pairs of one item,
+// heaviest first (across systems), so that the persistent kernel ends on
+// light items; item numbers follow the new order.  The estimate is the
+// uniform fluid's: n(x) neighbours below x rmax (halved in triangle-once
+// lists), a centre's rows in the slab r = n(hi) - n(lo), its entries from
+// the slab on m = n(1) - n(lo), and r(r-1)/2 + r(m-r) pairs per centre.
+// Only for batches of a few systems: interleaving the segments of hundreds
+// of systems makes workgroups change systems (and reload their bin tables)
+// more often than the shorter tail saves (the uneven 8-system batch gained
+// 8 %, a 300-system served mix lost 4 %); larger batches keep each system's
+// segments together, outer slab first.
+constexpr int kOrderSystemsMax = 32;
+void order_segments(std::vector<Seg>& segs, const std::vector<Prepared>& ps, int cb)
+{
+    auto weight = [&](const Seg& sg) {
+        const Prepared& P = ps[sg.sys];
+        const double V = (double)P.g.box[0] * P.g.box[1] * P.g.box[2];
+        const double rm = (double)P.in.rmax;
+        const double per = (double)P.g.N / V * 4.18879020478639 * rm * rm * rm * (P.tri_once ? 0.5 : 1.0);
+        auto n = [&](double x) { return per * x * x * x; };
+        const double lo = (double)sg.lo0 / P.g.nbins, hi = (double)sg.lo1 / P.g.nbins;
+        const double r = n(hi) - n(lo), m = n(1.0) - n(lo);
+        return (double)std::min(cb, P.g.N) * (r * (r - 1.0) / 2.0 + r * (m - r));
+    };
+    std::stable_sort(segs.begin(), segs.end(), [&](const Seg& a, const Seg& b) { return weight(a) > weight(b); });
+    int items = 0;
+    for (auto& sg : segs) {
+        sg.item_begin = items;
+        sg.fetch_begin = items;
+        items += sg.n_blocks * sg.n_frames;
+    }
+}
+
 // Runs of items for the triplet kernel's work counter.  A workgroup flushes
 // its slab whenever its next item lies in another segment; with one item
 // per fetch, a segment with fewer items than workgroups has every item taken
@@ -1222,6 +1255,7 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             add_segments(ps[k], (int)k, 0, ps[k].in.n_frames, tn.cb, segs, items);
             max_n = std::max(max_n, ps[k].g.N);
         }
+        if ((int)ps.size() <= kOrderSystemsMax) order_segments(segs, ps, tn.cb);
         for (auto& s : segs) max_hb = std::max(max_hb, s.hb);
         int max_cells = 0;
         for (auto& P : ps) max_cells = std::max(max_cells, P.g.ncell);
