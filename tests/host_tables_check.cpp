@@ -9,8 +9,8 @@
 // int16 staging: wherever the host sets pk_ok, every coordinate of a cell's
 // 3 x 3 x 3 stencil (periodic shift applied) minus the kernel's midpoint
 // reference fits int16, and the sentinel atoms are rejected by every centre.
-// Then the per-wave build's grid over the jobs of a launch, and the triplet
-// kernel's runs of items.
+// Then the per-wave build's grid over the jobs of a launch, the triplet
+// kernel's runs of items and a small batch's segment order.
 // Exit status: the number of geometries with a failure.
 #include "../paper_1708_08619_amd/csrc/g3_host.cpp"
 
@@ -252,6 +252,52 @@ int main()
         for (int v : seen) if (v != 1) bad = true;
         std::printf("runs: %zu segments, %d items -> %d runs (longest %d) %s\n", segs.size(), total, n_fetch,
                     max_step, bad ? "FAIL" : "ok");
+        if (bad) ++failed;
+    }
+
+    // Segment order of a small batch: every segment kept, items numbered
+    // contiguously in the new order, and within one system (same density and
+    // cutoff) an outer slab (more rows beyond it) before an inner one whose
+    // rows are fewer -- checked on the benchmark-like slabs (rows from 0, 8,
+    // 17, 28, 44 of 60), where the estimate ranks slab 3 and 4 first.
+    {
+        std::vector<Prepared> ps(3);
+        const int Ns[3] = {65536, 4096, 20000};
+        for (int k = 0; k < 3; ++k) {
+            Prepared& P = ps[k];
+            P.g.N = Ns[k];
+            P.g.nbins = 60;
+            P.g.nb3 = 60;
+            const int L = (int)std::lround(std::cbrt((double)Ns[k] / 0.85) * 4096.0);
+            P.g.box[0] = P.g.box[1] = P.g.box[2] = L;
+            P.in.rmax = 3.0 * 4096;
+            P.tri_once = true;
+            P.g.slab_lo = {0, 8, 17, 28, 44, 60};
+        }
+        std::vector<Seg> segs;
+        int items = 0;
+        for (int k = 0; k < 3; ++k) add_segments(ps[k], k, 0, 5, 2048, segs, items);
+        const size_t n_before = segs.size();
+        order_segments(segs, ps, 2048);
+        bool bad = segs.size() != n_before;
+        int it = 0;
+        for (const Seg& sg : segs) {
+            if (sg.item_begin != it) bad = true;
+            it += sg.n_blocks * sg.n_frames;
+        }
+        if (it != items) bad = true;
+        // the first segment of each system is one of its two outer slabs,
+        // its last one the innermost
+        for (int k = 0; k < 3; ++k) {
+            int first = -1, last = -1;
+            for (const Seg& sg : segs)
+                if (sg.sys == k) {
+                    if (first < 0) first = sg.slab;
+                    last = sg.slab;
+                }
+            if (first < 3 || last != 0) bad = true;
+        }
+        std::printf("segment order: %zu segments, %d items %s\n", segs.size(), items, bad ? "FAIL" : "ok");
         if (bad) ++failed;
     }
     return failed;
