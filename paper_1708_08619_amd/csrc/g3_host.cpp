@@ -13,6 +13,8 @@
 #include <deque>
 #include <string>
 #include <map>
+#include <set>
+#include <tuple>
 #include <vector>
 
 #include "g3_device.h"
@@ -433,7 +435,36 @@ struct Prepared {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-g3_status prepare(const g3_system& s, int hb_max, Prepared& P)
+// Bin tables depend on (rmax, nbins, nbins_third) alone: a batch of many
+// systems computes them once per distinct triple.
+using BinKey = std::tuple<uint64_t, int, int>;
+using BinCache = std::map<BinKey, Geometry>;
+
+BinKey bin_key(double rmax, int nbins, int nb3)
+{
+    uint64_t bits;
+    std::memcpy(&bits, &rmax, sizeof(bits));
+    return BinKey(bits, nbins, nb3);
+}
+
+void copy_bins(const Geometry& from, Geometry& g)
+{
+    g.thr = from.thr;
+    g.tab = from.tab;
+    g.step = from.step;
+    g.R2 = from.R2;
+    g.R3 = from.R3;
+    g.C3 = from.C3;
+    g.sh = from.sh;
+    g.tab_len = from.tab_len;
+    g.tab_bits = from.tab_bits;
+    g.one_step = from.one_step;
+    g.step_sh = from.step_sh;
+    g.step_bits = from.step_bits;
+    g.step_ok = from.step_ok;
+}
+
+g3_status prepare(const g3_system& s, int hb_max, Prepared& P, BinCache* cache = nullptr)
 {
     g3_status st = check3(s.n_atoms, s.box, s.rmax, s.nbins, s.nbins_third, s.layout);
     if (st) return st;
@@ -445,7 +476,18 @@ g3_status prepare(const g3_system& s, int hb_max, Prepared& P)
     g.layout = s.layout;
     for (int d = 0; d < 3; ++d) g.box[d] = s.box[d];
     g.C = (int)std::ceil(s.rmax);
-    plan_bins(g, s.rmax);
+    if (cache) {
+        const BinKey k = bin_key(s.rmax, g.nbins, g.nb3);
+        const auto it = cache->find(k);
+        if (it == cache->end()) {
+            plan_bins(g, s.rmax);
+            cache->emplace(k, g);
+        } else {
+            copy_bins(it->second, g);
+        }
+    } else {
+        plan_bins(g, s.rmax);
+    }
     // 16-bit entries need every accepted third-side component in int16
     g.wide = g.C3 > 32767 ? 1 : 0;
     plan_cells(g);
@@ -560,8 +602,9 @@ int plan_wave_grid(Job* jobs, int n, const std::vector<Prepared>& ps, const Buil
 }
 
 // Lay out scratch for a list of prepared systems; returns total bytes.
-// Triangle-once buffers of all systems are laid out last, back to back, so one
-// fill clears them.
+// The cell counts and pool cursors of all systems come first and the
+// triangle-once buffers last, each back to back, so one fill clears each;
+// systems with the same bin tables share one copy.
 size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case, size_t base,
                       bool tri_once, int n_cu)
 {
@@ -581,6 +624,28 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
     }
     const BuildPlan bp = plan_build(ps);
     const uint32_t chunk = per_frame ? kBuildChunk : kPlainChunk;
+    // the regions that start at zero (cell counts, pool cursors) back to
+    // back, so that one fill clears the whole group's
+    for (auto& P : ps) {
+        const size_t F = per_frame ? (size_t)std::max(P.in.n_frames, 1) : 1;
+        P.off_cell_count = o; o = align_up(o + F * P.g.ncell * 4, 256);
+        P.off_cursor = o;     o = align_up(o + (size_t)std::max(P.in.n_frames, 1) * kCursorStride * 4, 256);
+    }
+    // one copy of the bin tables per distinct (rmax, nbins, nbins_third)
+    std::map<BinKey, const Prepared*> first;
+    for (auto& P : ps) {
+        const Geometry& g = P.g;
+        const auto ins = first.emplace(bin_key(P.in.rmax, g.nbins, g.nb3), &P);
+        if (!ins.second) {
+            P.off_thr = ins.first->second->off_thr;
+            P.off_tab = ins.first->second->off_tab;
+            P.off_step = ins.first->second->off_step;
+            continue;
+        }
+        P.off_thr = o;        o = align_up(o + (g.nb3 + 1) * 4, 256);
+        P.off_tab = o;        o = align_up(o + g.tab_len, 256);
+        P.off_step = o;       o = align_up(o + g.step.size() * 4, 256);
+    }
     for (auto& P : ps) {
         const Geometry& g = P.g;
         // (a per-frame launch has one job: its cells alone set the grid)
@@ -592,19 +657,14 @@ size_t layout_scratch(std::vector<Prepared>& ps, bool per_frame, bool worst_case
         const size_t N = (size_t)g.N;
         const int S = (int)g.slab_lo.size() - 1;
         P.per_frame = per_frame ? 1 : 0;
-        P.off_cell_count = o; o = align_up(o + F * g.ncell * 4, 256);
         P.off_cell_start = o; o = align_up(o + F * (g.ncell + 1) * 4, 256);
         P.off_atom_cell = o;  o = align_up(o + F * N * 4, 256);
         P.off_atom_rank = o;  o = align_up(o + F * N * 4, 256);
         P.off_sorted = o;     o = align_up(o + F * 3 * N * 4, 256);
         P.off_nbr_off = o;    o = align_up(o + F * N * 4, 256);
         P.off_nbr_cnt = o;    o = align_up(o + F * N * 4, 256);
-        P.off_cursor = o;     o = align_up(o + (size_t)std::max(P.in.n_frames, 1) * kCursorStride * 4, 256);
         P.off_slab_j = o;     o = align_up(o + F * N * (S + 1) * 2, 256);
         P.off_ovf = o;        o = align_up(o + F * g.ncell * 4, 256);
-        P.off_thr = o;        o = align_up(o + (g.nb3 + 1) * 4, 256);
-        P.off_tab = o;        o = align_up(o + g.tab_len, 256);
-        P.off_step = o;       o = align_up(o + g.step.size() * 4, 256);
         if (!worst_case) {
             // expected neighbours of a uniform fluid, with headroom; a frame
             // that overflows is recomputed by g3_sync with the worst case
@@ -958,19 +1018,24 @@ g3_status end_upload(g3_plan p)
     return G3_OK;
 }
 
+// (systems that share bin tables share their offsets: each copy once)
 size_t geometry_bytes(const std::vector<Prepared>& ps)
 {
     size_t n = 0;
+    std::set<size_t> seen;
     for (const auto& P : ps)
-        n += align_up(P.g.thr.size() * 4, 64) + align_up(P.g.tab.size(), 64) +
-             align_up(P.g.step.size() * 4, 64);
+        if (seen.insert(P.off_thr).second)
+            n += align_up(P.g.thr.size() * 4, 64) + align_up(P.g.tab.size(), 64) +
+                 align_up(P.g.step.size() * 4, 64);
     return n;
 }
 
 g3_status upload_geometry(g3_plan p, const std::vector<Prepared>& ps)
 {
     char* A = (char*)p->arena;
+    std::set<size_t> seen;
     for (const auto& P : ps) {
+        if (!seen.insert(P.off_thr).second) continue;
         g3_status st = upload(p, A + P.off_thr, P.g.thr.data(), P.g.thr.size() * 4);
         if (st) return st;
         st = upload(p, A + P.off_tab, P.g.tab.data(), P.g.tab.size());
@@ -1218,19 +1283,21 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
 {
     g3_status st = ensure_common(p);
     if (st) return st;
-    // group by entry format
+    const Tun tn = effective(p);
+    // every system checked and prepared before anything is queued
+    // (grouped by entry format)
+    std::vector<Prepared> by_format[2];
+    BinCache bins;
+    for (int i = 0; i < n_sys; ++i) {
+        const g3_system& s = systems[i];
+        if (s.n_frames == 0 || s.n_atoms == 0) continue;
+        Prepared P;
+        if ((st = prepare(s, tn.hb_max, P, &bins))) return st;
+        by_format[P.g.wide ? 1 : 0].push_back(std::move(P));
+    }
     for (int grp = 0; grp < 2; ++grp) {
         const bool wide = grp == 1;
-        const Tun tn = effective(p);
-        std::vector<Prepared> ps;
-        for (int i = 0; i < n_sys; ++i) {
-            const g3_system& s = systems[i];
-            if (s.n_frames == 0 || s.n_atoms == 0) continue;
-            Prepared P;
-            if ((st = prepare(s, tn.hb_max, P))) return st;
-            if ((P.g.wide != 0) != wide) continue;
-            ps.push_back(std::move(P));
-        }
+        std::vector<Prepared>& ps = by_format[grp];
         if (ps.empty()) continue;
         const size_t need = layout_scratch(ps, true, false, 0, tn.tri_once, p->n_cu);
         // flags for every frame of the group
@@ -1328,12 +1395,13 @@ g3_status run_batch(g3_plan p, const g3_system* systems, int n_sys)
             a.cb = tn.cb;
         a.tb_max = kTabMax;
         a.cand = p->cand;
-        // cell-count zeroing covers the group's whole scratch prefix of counts
+        // one fill over the group's cell counts and pool cursors, which the
+        // layout puts back to back
         std::vector<std::pair<uint32_t*, size_t>> zero;
-        for (auto& P : ps) {
-            zero.push_back({(uint32_t*)((char*)p->arena + P.off_cell_count),
-                            (size_t)P.g.ncell * (size_t)P.in.n_frames});
-            zero.push_back({(uint32_t*)((char*)p->arena + P.off_cursor), (size_t)P.in.n_frames * kCursorStride});
+        {
+            const size_t z0 = ps.front().off_cell_count;
+            const size_t z1 = ps.back().off_cursor + (size_t)ps.back().in.n_frames * kCursorStride * 4;
+            zero.push_back({(uint32_t*)((char*)p->arena + z0), (z1 - z0) / 4});
         }
         const auto tri = tri_range(ps);
         if (tri.second > tri.first)

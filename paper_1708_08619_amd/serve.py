@@ -188,8 +188,14 @@ class Server:
             raise g3.G3Error(st, f"request {req.rid}")
         if req.n_frames == 0:
             raise ValueError("a request needs at least one frame")
-        lo = np.asarray(req.box, dtype=np.int64)[None, :, None]
-        if fr.min() < 0 or np.any(fr >= lo):
+        if fr.dtype == np.int32:
+            # one pass: a negative coordinate read as uint32 is >= 2^31 > L
+            hi = fr.view(np.uint32).max(axis=(0, 2)) if fr.size else np.zeros(3, np.uint32)
+            bad = bool(np.any(hi.astype(np.int64) >= np.asarray(req.box, dtype=np.int64)))
+        else:
+            lo = np.asarray(req.box, dtype=np.int64)[None, :, None]
+            bad = bool(fr.size) and (fr.min() < 0 or bool(np.any(fr >= lo)))
+        if bad:
             raise g3.G3Error(g3.EDOMAIN, f"request {req.rid}")
         req.nbytes = footprint_bytes(req, self.frames_per_iter)
         if req.nbytes + self.reserve > self.budget:

@@ -127,6 +127,24 @@ def test_rejections(oracle_mod):
     with pytest.raises(g3.G3Error) as e:
         srv.submit(serve.Request(0, bad, box, 2.0 * 4096, 40))
     assert e.value.status == g3.EDOMAIN
+    # a negative coordinate, on each axis, in int32 and in a wider type
+    for ax in range(3):
+        for dt in (np.int32, np.int64):
+            neg = fr.astype(dt)
+            neg[-1, ax, -1] = -1
+            with pytest.raises(g3.G3Error) as e:
+                srv.submit(serve.Request(0, neg, box, 2.0 * 4096, 40))
+            assert e.value.status == g3.EDOMAIN
+            hi = fr.astype(dt)
+            hi[0, ax, 1] = box[ax]
+            with pytest.raises(g3.G3Error) as e:
+                srv.submit(serve.Request(0, hi, box, 2.0 * 4096, 40))
+            assert e.value.status == g3.EDOMAIN
+    edge = fr.copy()
+    edge[0, :, 0] = np.asarray(box) - 1            # the largest valid coordinates
+    edge[0, :, 1] = 0
+    srv.submit(serve.Request(9, edge, box, 2.0 * 4096, 40))
+    srv.queue.clear()
     with pytest.raises(g3.G3Error) as e:
         srv.submit(serve.Request(1, fr, box, 0.5, 40))
     assert e.value.status == g3.EINVAL
