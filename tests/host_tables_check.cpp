@@ -10,7 +10,8 @@
 // 3 x 3 x 3 stencil (periodic shift applied) minus the kernel's midpoint
 // reference fits int16, and the sentinel atoms are rejected by every centre.
 // Then the per-wave build's grid over the jobs of a launch, the triplet
-// kernel's runs of items and a small batch's segment order.
+// kernel's runs of items, a small batch's segment order and a batch's
+// scratch layout.
 // Exit status: the number of geometries with a failure.
 #include "../paper_1708_08619_amd/csrc/g3_host.cpp"
 
@@ -298,6 +299,101 @@ int main()
             if (first < 3 || last != 0) bad = true;
         }
         std::printf("segment order: %zu segments, %d items %s\n", segs.size(), items, bad ? "FAIL" : "ok");
+        if (bad) ++failed;
+    }
+
+    // A batch's scratch layout: systems prepared with the shared bin-table
+    // cache get the same tables as without it; no two regions overlap except
+    // the tables of systems with the same (rmax, nbins, nbins_third), which
+    // are one copy; the block cleared by one fill holds every system's cell
+    // counts and pool cursors and nothing else.
+    {
+        struct Spec { int N, F; double rmax; int nb, nb3, layout; };
+        const Spec specs[] = {{4000, 3, 3.0 * 4096, 60, 60, 0}, {9000, 1, 2.5 * 4096, 50, 50, 1},
+                              {4000, 2, 3.0 * 4096, 60, 60, 1}, {1500, 4, 2.5 * 4096, 50, 100, 1},
+                              {30000, 2, 3.0 * 4096, 60, 60, 0}, {2500, 1, 2.5 * 4096, 50, 50, 0},
+                              {700, 5, 2.5 * 4096, 50, 100, 1}, {5000, 2, 2.0 * 4096, 40, 40, 0}};
+        std::vector<Prepared> ps;
+        BinCache cache;
+        bool bad = false;
+        static int32_t dummy_frames[1];
+        static uint64_t dummy_hist[1];
+        for (const Spec& sp : specs) {
+            g3_system in{};
+            in.frames = dummy_frames;
+            in.hist = dummy_hist;
+            in.n_frames = sp.F;
+            in.n_atoms = sp.N;
+            const int L = (int)std::lround(std::cbrt((double)sp.N / 0.85) * 4096.0);
+            in.box[0] = in.box[1] = in.box[2] = L;
+            in.rmax = sp.rmax;
+            in.nbins = sp.nb;
+            in.nbins_third = sp.nb3 == sp.nb ? 0 : sp.nb3;
+            in.layout = sp.layout;
+            Prepared P, Q;
+            if (prepare(in, 30784, P, &cache) != G3_OK || prepare(in, 30784, Q) != G3_OK) {
+                bad = true;
+                continue;
+            }
+            if (P.g.thr != Q.g.thr || P.g.tab != Q.g.tab || P.g.step != Q.g.step || P.g.sh != Q.g.sh ||
+                P.g.step_sh != Q.g.step_sh || P.g.step_ok != Q.g.step_ok || P.g.one_step != Q.g.one_step ||
+                P.g.R2 != Q.g.R2 || P.g.R3 != Q.g.R3 || P.g.C3 != Q.g.C3 || P.g.tab_bits != Q.g.tab_bits)
+                bad = true;
+            ps.push_back(std::move(P));
+        }
+        const size_t total = layout_scratch(ps, true, false, 0, true, 256);
+        struct Region { size_t b, e; int sys; int kind; };
+        std::vector<Region> rs;
+        auto add = [&](size_t b, size_t n, int k, int kind) { if (n) rs.push_back({b, b + n, k, kind}); };
+        for (int k = 0; k < (int)ps.size(); ++k) {
+            const Prepared& P = ps[k];
+            const size_t F = (size_t)P.in.n_frames, N = (size_t)P.g.N, C = (size_t)P.g.ncell;
+            const size_t S = P.g.slab_lo.size() - 1;
+            add(P.off_cell_count, F * C * 4, k, 0);
+            add(P.off_cursor, F * kCursorStride * 4, k, 0);
+            add(P.off_cell_start, F * (C + 1) * 4, k, 1);
+            add(P.off_atom_cell, F * N * 4, k, 1);
+            add(P.off_atom_rank, F * N * 4, k, 1);
+            add(P.off_sorted, F * 3 * N * 4, k, 1);
+            add(P.off_nbr_off, F * N * 4, k, 1);
+            add(P.off_nbr_cnt, F * N * 4, k, 1);
+            add(P.off_slab_j, F * N * (S + 1) * 2, k, 1);
+            add(P.off_ovf, F * C * 4, k, 1);
+            add(P.off_pool, F * (size_t)(P.pool_cap + kPoolPad) * (P.g.wide ? 16 : 8), k, 1);
+            if (P.tri_once) add(P.off_tri, g3_hist_len(P.g.nbins, G3_HALF) * 8, k, 1);
+            bool shared = false;
+            for (int j = 0; j < k; ++j) {
+                const bool same = ps[j].in.rmax == P.in.rmax && ps[j].g.nbins == P.g.nbins &&
+                                  ps[j].g.nb3 == P.g.nb3;
+                const bool same_off = ps[j].off_thr == P.off_thr;
+                if (same != same_off) bad = true;
+                if (same) {
+                    shared = true;
+                    if (ps[j].off_tab != P.off_tab || ps[j].off_step != P.off_step) bad = true;
+                }
+            }
+            if (!shared) {
+                add(P.off_thr, (P.g.nb3 + 1) * 4, k, 2);
+                add(P.off_tab, (size_t)P.g.tab_len, k, 2);
+                add(P.off_step, P.g.step.size() * 4, k, 2);
+            }
+        }
+        for (size_t i = 0; i < rs.size(); ++i) {
+            if (rs[i].e > total) bad = true;
+            for (size_t j = i + 1; j < rs.size(); ++j)
+                if (rs[i].b < rs[j].e && rs[j].b < rs[i].e) bad = true;
+        }
+        const size_t z0 = ps.front().off_cell_count;
+        const size_t z1 = ps.back().off_cursor + (size_t)ps.back().in.n_frames * kCursorStride * 4;
+        for (const Region& r : rs) {
+            const bool inside = r.b >= z0 && r.e <= z1;
+            const bool outside = r.e <= z0 || r.b >= z1;
+            if (r.kind == 0 ? !inside : !outside) bad = true;
+        }
+        int n_tables = 0;
+        for (const Region& r : rs) n_tables += r.kind == 2 && r.b == ps[r.sys].off_thr;
+        std::printf("batch layout: %zu systems, %zu regions, %d table copies, cleared block %zu B of %zu %s\n",
+                    ps.size(), rs.size(), n_tables, z1 - z0, total, bad ? "FAIL" : "ok");
         if (bad) ++failed;
     }
     return failed;
