@@ -1,5 +1,7 @@
 """GPU: the batched form on the uneven-systems workload at its configured
-size against the oracle, the autotuner, and per-call completion tickets."""
+size against the oracle, the autotuner, per-call completion tickets, many
+small systems in runs of items, mixed features in one batch, and bin tables
+shared only between systems with equal parameters."""
 from __future__ import annotations
 
 import numpy as np
@@ -187,3 +189,30 @@ def test_mixed_features_in_one_batch(g3mod, torch_dev, oracle_mod):
             if "pair_hist" in s:
                 gp = s["pair_hist"].cpu().numpy().astype(np.uint64)
                 assert np.array_equal(gp, oracle_mod.pair_hist(fr, box, rmax, nb)), k
+
+
+def test_bin_tables_shared_only_between_equal_parameters(g3mod, torch_dev, oracle_mod):
+    """A batch keeps one copy of the bin tables per (rmax, nbins,
+    nbins_third).  Systems whose cutoffs differ by half a unit or one unit
+    (thresholds differ in a few bins), one with the same cutoff and a
+    doubled third axis, and exact repeats, interleaved in one batch: each
+    equals the oracle bin for bin, so no system read another's tables."""
+    base = 1.5 * 4096
+    params = [(base, 30, 30), (base + 0.5, 30, 30), (base, 30, 60), (base + 1.0, 30, 30),
+              (base, 30, 30), (base + 0.5, 30, 30), (base, 29, 29), (base, 30, 60)]
+    cases, systems = [], []
+    for k, (rmax, nb, nc) in enumerate(params):
+        fr, box = synth.jittered_fcc(400 + 37 * k, 0.85, 0.1, 2, [59, k])
+        if nc > nb:                 # the third cutoff (2 rmax) must stay below L/2
+            assert 2 * rmax < min(box) / 2
+        layout = k % 2
+        h = g3mod.new_hist(nb, layout, torch_dev, nbins_third=nc)
+        systems.append(dict(frames=_dev(fr, torch_dev), box=box, rmax=rmax, nbins=nb, layout=layout,
+                            hist=h, nbins_third=nc))
+        cases.append((fr, box, rmax, nb, layout, nc))
+    with g3mod.Plan() as plan:
+        plan.accumulate_batch(systems)
+        plan.sync()
+        for k, ((fr, box, rmax, nb, layout, nc), s) in enumerate(zip(cases, systems)):
+            got = s["hist"].cpu().numpy().astype(np.uint64)
+            assert np.array_equal(got, oracle_mod.hist(fr, box, rmax, nb, layout, nbins_third=nc)), k
