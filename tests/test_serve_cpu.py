@@ -215,3 +215,27 @@ def test_recomputed_frames_are_in_the_result(oracle_mod, monkeypatch):
         want = oracle_mod.hist(r.frames, r.box, r.rmax, r.nbins, r.layout)
         assert np.array_equal(r.result, want), r.rid
     assert srv.used == 0 and ex.live == 0
+
+
+def test_result_blocks_hand_out_disjoint_slices():
+    """Histograms copied out of the device land in slices of shared host
+    blocks: every slice has its length, slices never overlap (each keeps its
+    own values), a full block is followed by a new one, and a histogram
+    larger than a block gets an array of its own."""
+    rb = serve.ResultBlocks()
+    words = rb.BLOCK_BYTES // 8
+    rng = np.random.default_rng(5)
+    sizes = [int(x) for x in rng.integers(1, words // 7, size=40)] + [words, words + 1, 3]
+    outs = []
+    for k, n in enumerate(sizes):
+        o = rb.take(n)
+        assert o.shape == (n,) and o.dtype == np.uint64
+        if o.base is not None:
+            assert (o.ctypes.data - o.base.ctypes.data) % 64 == 0
+        o[:] = k
+        outs.append(o)
+    for k, o in enumerate(outs):
+        assert np.all(o == k), k
+    spans = sorted((o.ctypes.data, o.ctypes.data + 8 * o.size) for o in outs)
+    assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:]))
+    assert outs[-2].base is None or outs[-2].base.size == words + 1   # its own array
