@@ -244,7 +244,9 @@ class Server:
 
     def result(self, req: Request) -> np.ndarray:
         """Serve until ``req`` is complete and return its uint64 histogram
-        (other requests keep advancing meanwhile)."""
+        (other requests keep advancing meanwhile).  On the GPU executor the
+        array is a slice of a shared 16 MiB host block (see
+        :class:`ResultBlocks`); ``.copy()`` it to hold it on its own."""
         while math.isnan(req.done):
             if not self.step():
                 raise RuntimeError(f"request {req.rid} is not queued on this server")
